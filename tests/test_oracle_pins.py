@@ -1,0 +1,415 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+None of these re-derives a value by calling the same oracle routine twice or by
+retyping its formula: each checks a closed form, an invariant, a symmetry, a
+special case with a known answer, or brute force on a tiny input.  Equation and
+section numbers refer to arXiv 2411.13992.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import cases
+import oracle
+from oracle import brute
+
+pytestmark = pytest.mark.usefixtures("oracle_lib")
+
+
+# ---------------------------------------------------------------- kernel
+@pytest.mark.filterwarnings("ignore::scipy.integrate.IntegrationWarning")
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("h", [0.026, 1.0, 3.7])
+def test_kernel_normalisation(dim, h):
+    """The Wendland kernel (Sec. 4) integrates to one over its 2h support."""
+    if dim == 2:
+        f = lambda r: 2.0 * math.pi * r * oracle.kernel_w(2, r, h)
+    else:
+        f = lambda r: 4.0 * math.pi * r * r * oracle.kernel_w(3, r, h)
+    val, err = integrate.quad(f, 0.0, 2.0 * h, epsabs=1e-14, epsrel=1e-14, limit=200)
+    assert abs(val - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_kernel_smoothness_and_support(dim):
+    """Wendland C2: W, W', W'' vanish at q = 2 and W'(0) = 0 (C2 radial
+    function); W is zero outside the support and positive inside."""
+    h = 0.7
+    w = lambda r: oracle.kernel_w(dim, r, h)
+    e = 1e-4 * h
+    r2 = 2.0 * h
+    assert w(r2) == 0.0 and w(r2 * 1.5) == 0.0
+    assert w(r2 - e) > 0.0
+    # one-sided derivatives at the support edge, from inside
+    d1 = (w(r2 - e) - w(r2 - 2 * e)) / e
+    d2 = (w(r2 - e) - 2 * w(r2 - 2 * e) + w(r2 - 3 * e)) / (e * e)
+    assert abs(d1) < 1e-8 * w(0.0) / h
+    assert abs(d2) < 1e-3 * w(0.0) / h ** 2
+    # symmetric derivative at the origin vanishes
+    assert abs((w(e) - w(0.0)) / e) < 1e-3 * w(0.0) / h
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_kernel_gradient_matches_fd(dim):
+    """F(r) = W'(r)/r: F(r) r equals a central difference of W."""
+    h = 0.9
+    for r in np.linspace(0.05, 1.95, 39) * h:
+        e = 1e-6 * h
+        fd = (oracle.kernel_w(dim, r + e, h) - oracle.kernel_w(dim, r - e, h)) / (2 * e)
+        an = oracle.kernel_f(dim, r, h) * r
+        assert abs(fd - an) <= 1e-7 * abs(oracle.kernel_f(dim, 0.0, h)) * h
+
+
+def _r2_count(m: int) -> int:
+    """Number of integer pairs (a, b) with a^2 + b^2 = m, by Jacobi's two-square
+    theorem r2(m) = 4 (d1(m) - d3(m)) for m > 0."""
+    if m == 0:
+        return 1
+    d1 = sum(1 for d in range(1, m + 1) if m % d == 0 and d % 4 == 1)
+    d3 = sum(1 for d in range(1, m + 1) if m % d == 0 and d % 4 == 3)
+    return 4 * (d1 - d3)
+
+
+def _r3_count(m: int) -> int:
+    return sum(_r2_count(m - c * c) * (1 if c == 0 else 2)
+               for c in range(0, int(math.isqrt(m)) + 1))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_lattice_kappa_shell_sum(dim):
+    """kappa_D (the reference kernel sum of Eq. 8 on a perfect lattice) equals
+    the sum over lattice shells |k|^2 = m weighted by the number-theoretic shell
+    counts, an enumeration independent of the oracle's loops."""
+    cnt = _r2_count if dim == 2 else _r3_count
+    ref = 0.0
+    for m in range(0, 8):
+        if math.sqrt(m) < 2.6:
+            ref += cnt(m) * oracle.kernel_w(dim, math.sqrt(m), 1.3)
+    assert abs(oracle.lattice_kappa(dim, 1.3) - ref) < 1e-14 * ref
+
+
+@pytest.mark.parametrize("dim,n,expect", [(2, 16, 20), (3, 9, 80)])
+def test_lattice_neighbour_count(dim, n, expect):
+    """h = 1.3 dx, support 2.6 dx: the shells 0 < |k|^2 <= 6 hold 20 points in
+    2-D (4+4+4+8) and 80 in 3-D (6+12+8+6+24+24)."""
+    cnt = _r2_count if dim == 2 else _r3_count
+    assert sum(cnt(m) for m in range(1, 7)) == expect
+    c = cases.taylor_green_2d(n) if dim == 2 else cases.taylor_green_3d(n, jitter=0.0)
+    start, _ = oracle.neighbors(c.pos, c.h, c.box)
+    assert np.all(np.diff(start) == expect)
+
+
+# ---------------------------------------------------------------- neighbours
+def _small_sets():
+    out = [cases.taylor_green_2d(12, jitter=0.3, seed=3),
+           cases.taylor_green_2d(6, jitter=0.2, seed=4),           # 2 cells/axis: fallback
+           cases.taylor_green_3d(8, jitter=0.2, seed=5)]
+    v = cases.taylor_green_2d(14, jitter=0.25, seed=6)
+    rng = np.random.default_rng(7)
+    v.h = v.h * rng.uniform(0.7, 1.0, size=v.n)                   # variable h
+    out.append(v)
+    return out
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_neighbour_search_matches_brute_force(idx):
+    """Both oracle searches return exactly the brute-force set
+    { j != i : r_ij < 2 h_ij }, in ascending j, including across the seam."""
+    c = _small_sets()[idx]
+    ref = brute.neighbor_sets(c.pos, c.h, c.box)
+    for method in ("brute", "grid"):
+        start, lst = oracle.neighbors(c.pos, c.h, c.box, method=method)
+        for i in range(c.n):
+            got = lst[start[i]:start[i + 1]]
+            assert np.array_equal(got, ref[i]), (method, i)
+
+
+# ---------------------------------------------------------------- density
+@pytest.mark.parametrize("dim,n,box", [(2, 20, 1.0), (2, 24, 3.0), (3, 10, 1.0)])
+def test_density_on_lattice_is_rho0(dim, n, box):
+    """Eq. (8): on the perfect lattice the kernel sum equals its reference
+    value, so rho = rho0 for any spacing."""
+    if dim == 2:
+        c = cases.taylor_green_2d(n)
+    else:
+        c = cases.taylor_green_3d(n, jitter=0.0)
+    pos = c.pos * box
+    h = c.h * box
+    mass = c.mass * box ** dim * 1.7      # rho0 = 1.7
+    nb = oracle.neighbors(pos, h, np.full(dim, box))
+    rho = oracle.density(pos, mass, h, np.full(dim, box), nb, oracle.lattice_kappa(dim))
+    assert np.max(np.abs(rho / 1.7 - 1.0)) < 1e-13
+
+
+def test_density_gradient_is_tv_sum():
+    """Eq. (14)'s sum g_i = sum_j V_j grad_i W_ij (V_j = m_j / rho_j) is the
+    gradient, with respect to r_i, of the kernel sum sum_j V_j W_ij: the density
+    sum of Eq. (8) evaluated with the volumes V_j in place of the masses, times
+    kappa.  Compare with a central difference that moves particle i alone, on
+    non-uniform densities so that V_j must use rho_j."""
+    c = cases.taylor_green_2d(16, jitter=0.2, seed=11)
+    kappa = oracle.lattice_kappa(2)
+    rho = 1.0 + 0.2 * np.random.default_rng(12).uniform(-1.0, 1.0, size=c.n)
+    vol = c.mass / rho
+    nb = oracle.neighbors(c.pos, c.h, c.box)
+    out = oracle.tv(c.pos, c.mass, rho, c.h, c.box, nb, c.h_min)
+    for i in (0, 37, 101, 200):
+        for k in range(2):
+            e = 1e-6 * c.dx
+            vals = []
+            for sgn in (1, -1):
+                p = c.pos.copy()
+                p[k, i] += sgn * e
+                nbp = oracle.neighbors(p, c.h, c.box)
+                vals.append(oracle.density(p, vol, c.h, c.box, nbp, kappa)[i])
+            fd = (vals[0] - vals[1]) / (2 * e) * kappa
+            assert abs(fd - out["g"][k, i]) < 1e-6 * out["gscale"][i]
+
+
+# ---------------------------------------------------------------- transport velocity
+@pytest.mark.parametrize("dim,n", [(2, 20), (3, 10)])
+def test_tv_vanishes_on_lattice(dim, n):
+    """Zero-order consistency (Sec. 3): the correction of Eq. (14)/(16) is zero
+    on a uniform distribution, and the limiter of Eq. (15) is off."""
+    c = cases.taylor_green_2d(n) if dim == 2 else cases.taylor_green_3d(n, jitter=0.0)
+    nb = oracle.neighbors(c.pos, c.h, c.box)
+    rho = oracle.density(c.pos, c.mass, c.h, c.box, nb, oracle.lattice_kappa(dim))
+    out = oracle.tv(c.pos, c.mass, rho, c.h, c.box, nb, c.h_min)
+    assert np.max(np.abs(out["g"]) / out["gscale"]) < 1e-13
+    assert np.all(out["beta"] == 0.0)
+    assert np.all(out["dr"] == 0.0)
+
+
+def _displaced(delta):
+    c = cases.taylor_green_2d(20)
+    i = 10 + 20 * 10
+    pos = c.pos.copy()
+    pos[0, i] += delta * c.dx
+    nb = oracle.neighbors(pos, c.h, c.box)
+    rho = oracle.density(pos, c.mass, c.h, c.box, nb, oracle.lattice_kappa(2))
+    out = oracle.tv(pos, c.mass, rho, c.h, c.box, nb, c.h_min)
+    return c, i, out
+
+
+def test_tv_is_restoring_and_limited():
+    """One particle displaced along x on a lattice: the correction of Eq. (16)
+    points back (restoring), has no y component (mirror symmetry), grows like
+    delta (so s like delta^2), and beta follows the three branches of Eq. (15)."""
+    seen = set()
+    s_prev = None
+    for delta in (0.005, 0.01, 0.02, 0.03, 0.05, 0.1, 0.2):
+        c, i, out = _displaced(delta)
+        s, beta, dr = out["s"][i], out["beta"][i], out["dr"][:, i]
+        assert out["g"][0, i] * delta > 0.0      # g points towards the crowded side
+        assert abs(out["g"][1, i]) < 1e-12 * out["gscale"][i]
+        if s <= 5e-4:
+            assert beta == 0.0 and np.all(dr == 0.0)
+            seen.add("off")
+        else:
+            assert dr[0] * delta < 0.0           # restoring
+            if s < 1e-3:
+                assert abs(beta - 1e3 * s) < 1e-15
+                seen.add("ramp")
+            else:
+                assert beta == 1.0
+                seen.add("full")
+            assert abs(dr[0] - (-0.2) * beta * c.h_min ** 2 * out["g"][0, i]) < 1e-18
+        if delta <= 0.01:
+            if s_prev is not None:
+                assert abs(s / s_prev - 4.0) < 0.02   # linear response
+            s_prev = s
+    assert seen == {"off", "ramp", "full"}
+
+
+# ---------------------------------------------------------------- forces
+def test_pressure_linear_field():
+    """A linear pressure p = G x (rho = rho0 + G x / c0^2) at rest: the Riemann
+    momentum equation (3b) with U_l = U_r reduces to the symmetric SPH pressure
+    gradient, a_i = -(M G)/rho0 with M = -sum_j V_j F_ij r_ij r_ij^T the discrete
+    second moment (exact up to the O(G h / (rho0 c0^2)) density denominators),
+    and M approaches the identity of the continuum (within 3% at h = 1.3 dx)."""
+    c = cases.taylor_green_2d(50)
+    nb = oracle.neighbors(c.pos, c.h, c.box)
+    G, c0 = 1e-4, 10.0
+    rho = 1.0 + G * c.pos[0] / c0 ** 2
+    acc, _ = oracle.forces(c.pos, np.zeros_like(c.pos), c.mass, rho, c.h, c.box, nb,
+                           1.0, c0, 0.0)
+    # second moment from the lattice neighbourhood of one interior particle
+    start, lst = nb
+    i0 = 25 + 50 * 25
+    M = np.zeros((2, 2))
+    for j in lst[start[i0]:start[i0 + 1]]:
+        r = c.pos[:, i0] - c.pos[:, j]
+        M -= c.mass[j] * oracle.kernel_f(2, np.linalg.norm(r), c.h[0]) * np.outer(r, r)
+    inner = (c.pos[0] > 3 * c.h[0]) & (c.pos[0] < 1 - 3 * c.h[0])
+    expect = -(M @ np.array([G, 0.0]))
+    assert np.max(np.abs(acc[0, inner] - expect[0])) < 1e-5 * abs(expect[0])
+    assert np.max(np.abs(acc[1, inner])) < 1e-12 * G
+    assert abs(M[0, 0] - 1.0) < 0.03 and abs(M[0, 1]) < 1e-14
+
+
+def _pair(du_over_c, c0=10.0):
+    """Two particles on the x axis approaching with relative speed du (> 0)."""
+    pos = np.array([[0.5, 0.52], [0.5, 0.5]])
+    u = 0.5 * du_over_c * c0
+    vel = np.array([[u, -u], [0.0, 0.0]])
+    h = np.full(2, 0.013)
+    m = np.full(2, 0.01 ** 2)
+    box = np.array([1.0, 1.0])
+    nb = oracle.neighbors(pos, h, box, method="brute")
+    acc, _ = oracle.forces(pos, vel, m, np.ones(2), h, box, nb, 1.0, c0, 0.0)
+    return acc
+
+
+def test_riemann_dissipation_limiter():
+    """At p = 0 the pair force is the Riemann dissipation of Eq. (5) with the
+    limiter of Eq. (6): zero when separating, repulsive when approaching,
+    growing like 3 (dU/c)^2 until beta saturates at 1, then like dU."""
+    a0 = _pair(0.1)
+    assert a0[0, 0] < 0.0 and a0[0, 1] > 0.0            # pushed apart
+    assert a0[0, 0] == -a0[0, 1] and a0[1, 0] == 0.0      # equal and opposite
+    ratios = [_pair(x)[0, 0] / a0[0, 0] for x in (0.2, 0.5, 1.0)]
+    # beta = 0.3, 0.6, 1, 1 for dU/c = 0.1, 0.2, 0.5, 1 -> P* ~ 0.03, 0.12, 0.5, 1
+    assert np.allclose(ratios, [4.0, 0.5 / 0.03, 1.0 / 0.03], rtol=1e-12)
+    sep = _pair(-0.3)
+    assert np.all(sep == 0.0)
+
+
+def test_viscous_shear():
+    """Eq. (7): a linear shear gives zero acceleration (symmetry), and a sine
+    shear u = U sin(2 pi y) gives a = nu d2u/dy2 up to the discrete second
+    moment and O((k h)^2) error (within 4%)."""
+    c = cases.taylor_green_2d(50)
+    nb = oracle.neighbors(c.pos, c.h, c.box)
+    inner = (c.pos[1] > 3 * c.h[0]) & (c.pos[1] < 1 - 3 * c.h[0])
+    lin = np.stack([1e-3 * c.pos[1], np.zeros(c.n)])
+    acc, scale = oracle.forces(c.pos, lin, c.mass, np.ones(c.n), c.h, c.box, nb, 1.0, 10.0, 0.01)
+    assert np.max(np.abs(acc[:, inner]) / scale[inner]) < 1e-13
+    U = 1e-3
+    sine = np.stack([U * np.sin(2 * np.pi * c.pos[1]), np.zeros(c.n)])
+    acc, _ = oracle.forces(c.pos, sine, c.mass, np.ones(c.n), c.h, c.box, nb, 1.0, 10.0, 0.01)
+    expect = -0.01 * (2 * np.pi) ** 2 * sine[0]
+    m = np.abs(sine[0]) > 0.5 * U
+    assert np.max(np.abs(acc[0, m] / expect[m] - 1.0)) < 0.04
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("variable", [False, True])
+def test_momentum_conservation(dim, variable):
+    """Pair terms of Eq. (3b) and (7) are antisymmetric, so sum_i m_i a_i = 0 in
+    a periodic box, for any velocities and densities, and (with the symmetric
+    pair smoothing length) for non-uniform masses and smoothing lengths."""
+    rng = np.random.default_rng(21)
+    if dim == 2:
+        c = cases.taylor_green_2d(24, jitter=0.3, seed=22)
+    else:
+        c = cases.taylor_green_3d(9, jitter=0.3, seed=22)
+    mass, h = c.mass, c.h
+    if variable:
+        mass = mass * rng.uniform(0.5, 1.5, size=c.n)
+        h = h * rng.uniform(0.75, 1.0, size=c.n)
+    vel = rng.normal(size=c.pos.shape)
+    rho = 1.0 + 0.01 * rng.normal(size=c.n)
+    nb = oracle.neighbors(c.pos, h, c.box)
+    acc, scale = oracle.forces(c.pos, vel, mass, rho, h, c.box, nb, 1.0, 10.0, 0.01)
+    tot = np.sum(mass * acc, axis=1)
+    assert np.max(np.abs(tot)) < 1e-13 * np.sum(mass * scale)
+
+
+def test_pair_kernel_is_symmetric_for_variable_h():
+    """With different smoothing lengths a pair still sees one kernel value and
+    opposite gradients: feeding a unit mass on one particle only, the density
+    sum of Eq. (8) gives W_ij = W_ji and the sum of Eq. (14) gives
+    grad_i W_ij = -grad_j W_ji."""
+    c = cases.taylor_green_2d(12, jitter=0.3, seed=41)
+    h = c.h * np.random.default_rng(42).uniform(0.7, 1.0, size=c.n)
+    nb = oracle.neighbors(c.pos, h, c.box)
+    start, lst = nb
+    kappa = oracle.lattice_kappa(2)
+    i = 30
+    unit_i = np.zeros(c.n)
+    unit_i[i] = 1.0
+    ones = np.ones(c.n)
+    rho_from_i = oracle.density(c.pos, unit_i, h, c.box, nb, kappa)
+    g_from_i = oracle.tv(c.pos, unit_i, ones, h, c.box, nb, 1.0)["g"]
+    nbrs = lst[start[i]:start[i + 1]]
+    assert len(nbrs) > 5
+    for j in nbrs:
+        unit_j = np.zeros(c.n)
+        unit_j[j] = 1.0
+        rho_from_j = oracle.density(c.pos, unit_j, h, c.box, nb, kappa)
+        g_from_j = oracle.tv(c.pos, unit_j, ones, h, c.box, nb, 1.0)["g"]
+        assert abs(rho_from_i[j] - rho_from_j[i]) <= 1e-15 * rho_from_j[i]
+        assert np.allclose(g_from_i[:, j], -g_from_j[:, i], rtol=1e-14, atol=0.0)
+
+
+# ---------------------------------------------------------------- whole step
+def test_step_grid_equals_brute_and_threads():
+    """The step does not depend on how neighbours are found or on the thread
+    count: bit-identical states."""
+    c = cases.taylor_green_2d(20, jitter=0.1, seed=31)
+    states = []
+    for grid, threads in ((False, 1), (True, 1), (True, 4)):
+        oracle.set_threads(threads)
+        st = oracle.State(c, use_grid=grid)
+        st.run(3)
+        states.append((st.pos.copy(), st.vel.copy(), st.rho.copy(), st.acc.copy()))
+    oracle.set_threads(0)
+    for s in states[1:]:
+        for a, b in zip(states[0], s):
+            assert np.array_equal(a, b)
+
+
+def test_tg_initial_energy_and_momentum():
+    """Eq. (17) at t = 0 on the lattice: KE = rho0 U^2 / 4 exactly (discrete
+    orthogonality of the sampled sines), zero momentum, and momentum stays zero
+    to roundoff through 50 steps."""
+    c = cases.taylor_green_2d(50)
+    st = oracle.State(c)
+    assert abs(st.kinetic_energy() - 0.25) < 1e-14
+    d = st.run(50)
+    assert np.max(np.abs(d[:, 1:4])) < 1e-14
+    assert np.all((st.pos >= 0.0) & (st.pos < 1.0))
+
+
+def _ke_slope(c, nsteps, eta=None):
+    if eta is not None:
+        c.eta = eta
+    st = oracle.State(c)
+    ke = [st.kinetic_energy()]
+    ke += list(st.run(nsteps)[:, 0])
+    t = np.arange(nsteps + 1) * c.dt
+    return np.polyfit(t, np.log(ke), 1)[0]
+
+
+def test_tg2d_viscous_decay_rate():
+    """Sec. 4.1: the kinetic energy of the 2-D Taylor-Green vortex decays at
+    -16 pi^2 / Re.  Early on (t < 0.035) the viscous part of the decay, the
+    slope of ln KE with viscosity minus the slope without, matches it within
+    5% (the discrete second moment accounts for ~3%), and the total slope
+    approaches it as resolution grows."""
+    exact = -16 * math.pi ** 2 / 100.0
+    errs = []
+    for n in (25, 50, 100):
+        c = cases.taylor_green_2d(n)
+        ns = int(round(0.035 / c.dt))
+        s1 = _ke_slope(cases.taylor_green_2d(n), ns)
+        s0 = _ke_slope(cases.taylor_green_2d(n), ns, eta=0.0)
+        assert abs((s1 - s0) / exact - 1.0) < 0.05
+        errs.append(abs(s1 - exact))
+    assert errs[0] > errs[1] > errs[2]
+
+
+def test_tg3d_viscous_decay_rate():
+    """3-D Taylor-Green initial field: at t = 0 the kinetic energy decays at
+    -2 nu 3 (2 pi)^2 = -24 pi^2 nu (Stokes limit).  The viscous part of the
+    early slope is within 12% at 16^3 and closer at 20^3."""
+    exact = -24 * math.pi ** 2 * 0.01
+    errs = []
+    for n in (16, 20):
+        s1 = _ke_slope(cases.taylor_green_3d(n, jitter=0.0), 10)
+        s0 = _ke_slope(cases.taylor_green_3d(n, jitter=0.0), 10, eta=0.0)
+        errs.append(abs((s1 - s0) / exact - 1.0))
+    assert errs[0] < 0.12 and errs[1] < errs[0]
