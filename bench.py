@@ -1,0 +1,214 @@
+"""Benchmark: pair interactions per second of one transport-velocity WCSPH step.
+
+Workload: 2-D periodic Taylor-Green vortex, 400 x 400 lattice (160,000
+particles) jittered by +-0.05 dx, h = 1.3 dx, Wendland C2, Re = 100, the
+h-scaled transport-velocity correction with its limiter every step.  A step
+is the whole hot path: correction sweep, kick + drift + rebin, cell build,
+density sweep, force sweep, kick + FP64 diagnostics.  Inputs are resident on
+the GPU before timing starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  `value` is FP32 pair interactions per second (ordered
+neighbour pairs j != i with r < 2h, counted by the step itself, divided by the
+step time).  Extra fields: the FP64 rate, the adjoint / forward time ratio,
+the roofline of the dominant kernel (the force sweep, timed live with HIP
+events on its stream) and the FP64 CPU oracle's rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pair interactions/s per TV-WCSPH step, FP32 vs FP64; adjoint/forward time"
+WORKLOAD = "tg2d_400"
+
+# Algorithmic work per interacting pair and bytes per particle of the force
+# sweep (2-D): flops counted on the pair formula (FMA = 2), bytes = compulsory
+# per-particle reads (offsets 2, velocity 2, density 1) and writes (acceleration 2).
+FORCE_FLOPS_PER_PAIR_2D = 46
+FORCE_BYTES_PER_PARTICLE = {"f32": 28, "f64": 56}
+# Non-packed vector FP32 peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+# x 2 flops per FMA (packed FP32 math is not used).
+VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "forces_kernel_tg2d_400_f32_pmc.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2411_13992_amd", "csrc", "sweeps.hip")
+
+
+def _events_time(fn, reps):
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(reps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / 1e3 / reps
+
+
+def time_steps(sim, steps, warmup):
+    import torch
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t = _events_time(lambda: sim.step(1), steps)
+    pairs = float(sim.diagnostics()["npairs"])
+    return t, pairs
+
+
+def time_adjoint(sim, steps, every):
+    """Seconds per step of the forward rollout and of its reverse sweep
+    (recompute with tapes + reverse steps + the init reverse)."""
+    import torch
+    from paper_2411_13992_amd.adjoint import backward_run, forward_run
+    v0 = sim.velocity_by_id().clone()
+    xi = sim.params.xi
+    forward_run(sim, v0, xi, steps, every)     # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ckpts = forward_run(sim, v0, xi, steps, every)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / steps
+    vbar = v0.clone()
+    tapes = torch.empty((every, sim.tape_bytes()), dtype=torch.uint8, device=sim.device)
+    backward_run(sim, ckpts, steps, every, vbar, tapes)   # warm
+    ckpts = forward_run(sim, v0, xi, steps, every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    backward_run(sim, ckpts, steps, every, vbar, tapes)
+    torch.cuda.synchronize()
+    t_bwd = (time.perf_counter() - t0) / steps
+    return t_fwd, t_bwd
+
+
+def kernel_roofline(sim, pairs, dtype, reps=200):
+    """Average duration of the force sweep launch (sph_forces on the benchmark
+    state, same kernel and launch shape as inside the step), by HIP events on
+    the stream it runs on."""
+    import torch
+    out = torch.empty_like(sim.acc)
+    sim.forces(out=out)
+    t = _events_time(lambda: sim.forces(out=out), reps)
+    flops = FORCE_FLOPS_PER_PAIR_2D * pairs
+    bytes_ = FORCE_BYTES_PER_PARTICLE[dtype] * sim.n
+    achieved = flops / t / 1e12
+    traffic = _pmc_traffic()
+    return {
+        "kernel": "forces_kernel",
+        "bound": "alu",
+        "achieved": achieved,
+        "peak": VALU_FP32_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": achieved / VALU_FP32_PEAK_TFLOPS,
+        "traffic": traffic,
+        "avg_launch_us": t * 1e6,
+        "algorithmic_flops_per_launch": flops,
+        "algorithmic_bytes_per_launch": bytes_,
+        "hbm_frac": bytes_ / t / 8e12,
+    }
+
+
+def _pmc_traffic():
+    """HBM bytes per launch of the force sweep from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    text = open(PMC_SUMMARY).read()
+    m = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not b:
+        return None
+    cur = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    return float(b.group(1)) if cur == m.group(1) else None
+
+
+def cpu_baseline(case, budget_s=12.0):
+    """The FP64 oracle, as it stands, on the same workload: whole steps until
+    the time budget is used (at least one)."""
+    import oracle
+    threads = oracle.get_threads()
+    st = oracle.State(case)
+    t0 = time.perf_counter()
+    steps, pairs = 0, 0.0
+    while True:
+        d = st.step()
+        steps += 1
+        pairs += d["npairs"]
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps} whole FP64 steps of the {case.n}-particle workload "
+                      f"(neighbour search by cells, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import cases
+    from paper_2411_13992_amd import Simulation
+
+    case = cases.make(WORKLOAD)
+    sim = Simulation.from_case(case, dtype="f32")
+    t32, pairs = time_steps(sim, args.steps, args.warmup)
+    roof = kernel_roofline(sim, pairs, "f32")
+    flags32 = sim.flags()
+    sim64 = Simulation.from_case(case, dtype="f64")
+    t64, pairs64 = time_steps(sim64, max(args.steps // 2, 1), max(args.warmup // 2, 1))
+    del sim64
+    simadj = Simulation.from_case(case, dtype="f32")
+    t_fwd, t_bwd = time_adjoint(simadj, 40, 20)
+    del simadj
+    out = {
+        "metric": METRIC,
+        "value": pairs / t32,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t32 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2-D periodic Taylor-Green vortex, 400x400 lattice jittered "
+                               "+-0.05 dx (160,000 particles), h = 1.3 dx, Wendland C2, "
+                               "Re = 100, c0 = 10 U, transport-velocity correction with "
+                               "limiter every step, FP32 sweeps with FP64 reductions",
+                   "particles": case.n, "pairs_per_step": pairs, "dt": case.dt},
+        "fp64": {"value": pairs64 / t64, "ms_per_step": t64 * 1e3,
+                 "fp32_speedup": t64 / t32},
+        "adjoint": {"forward_ms_per_step": t_fwd * 1e3, "reverse_ms_per_step": t_bwd * 1e3,
+                    "adjoint_over_forward": t_bwd / t_fwd,
+                    "rollout": "40 FP32 steps, checkpoints every 20, reverse includes "
+                               "recomputation with tapes"},
+        "roofline": roof,
+        "device_flags": flags32,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

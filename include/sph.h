@@ -1,0 +1,231 @@
+/*
+ * libsph: C-ABI for the data-parallel hot path of one transport-velocity
+ * weakly-compressible SPH step on a gfx950 GPU (method of Wang, Haidn & Hu,
+ * arXiv 2411.13992).
+ *
+ * One step n -> n+1 (kick-drift-kick with fixed dt):
+ *   1. transport correction at r^n:  g_i = sum_j V_j grad_i W_ij, V_j = m_j/rho_j,
+ *      s_i = h_min^2 |g_i|^2, beta_i = min(C s_i, 1) if s_i > s0 else 0,
+ *      dr_i = xi beta_i h_min^2 g_i                              (Sec. 3, Eq. 14-16)
+ *   2. half kick v' = v + dt/2 a; drift r += dt v' + dr; rebin to cells
+ *   3. cell build: particles sorted by (cell, id)
+ *   4. density summation rho_i = sum_{j incl. i} m_j W_ij / kappa      (Eq. 8)
+ *   5. EOS p = c0^2 (rho - rho0)                                        (Eq. 2)
+ *   6. accelerations: Riemann pressure term with the limited linear
+ *      solver and the viscous shear term                       (Eq. 3b, 5-7)
+ *   7. half kick v = v' + dt/2 a
+ *
+ * Kernel: Wendland C2 with support 2h, h = 1.3 dp (Sec. 4).  The kernel
+ * gradient is taken with respect to r_i; the Riemann axis points from i to j;
+ * pairs of different smoothing length use h_ij = (h_i + h_j)/2; neighbours are
+ * j != i with r_ij < 2 h_ij.
+ *
+ * Conventions for every entry point:
+ *  - returns SPH_OK (0) or a negative SPH_E_* status; no exception crosses
+ *    the boundary; sph_status_string() names the status;
+ *  - every array pointer is a DEVICE pointer owned by the caller; the library
+ *    allocates no device memory and keeps no state between calls; scratch
+ *    memory is the caller's workspace of sph_workspace_size() bytes;
+ *  - every call is asynchronous on `stream` (a hipStream_t, NULL = the null
+ *    stream) and never synchronises, except sph_get_flags();
+ *  - argument errors are detected on the host and returned at once, before
+ *    anything is enqueued; errors found on the device (non-finite values, a
+ *    particle that moved more than one cell in a step, a position outside the
+ *    box) set bits in a flag word held in the workspace (sph_get_flags);
+ *  - vector fields are structure-of-arrays [D][N] (component-major,
+ *    contiguous); all floating-point arrays have the element type named by
+ *    params.dtype (float for SPH_F32, double for SPH_F64) unless stated;
+ *  - positions are stored as a linear cell index (x fastest) plus cell-local
+ *    offsets in [0, L_k), L_k = box[k] / ncell[k] >= 2 h_max;
+ *  - particle ids are preserved through every reordering, so a caller maps
+ *    results back to its own order through `id`.
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SPH_OK             0
+#define SPH_E_ARG         -1  /* invalid argument (null pointer, size, shape) */
+#define SPH_E_HIP         -2  /* a HIP runtime call failed                    */
+#define SPH_E_WORKSPACE   -3  /* workspace or tape smaller than required      */
+#define SPH_E_CELL_RANGE  -4  /* cell grid does not satisfy L_k >= 2 h_max, or
+                                 fewer than 3 cells on an axis                */
+#define SPH_E_NONFINITE   -5  /* non-finite parameter                         */
+#define SPH_E_UNSUPPORTED -6  /* dimension or dtype not supported             */
+
+/* device flag bits (sph_get_flags) */
+#define SPH_FLAG_NONFINITE  1u  /* a velocity, acceleration or density is NaN/Inf */
+#define SPH_FLAG_CFL        2u  /* a particle moved more than one cell in a step  */
+#define SPH_FLAG_OUT_OF_BOX 4u  /* an input position lies outside [0, box)        */
+
+/* dtype */
+#define SPH_F32 0
+#define SPH_F64 1
+
+/* Run parameters.  Symbols follow the paper: rho0 reference density, c0
+ * artificial sound speed (Eq. 2), eta dynamic viscosity (Eq. 7), xi the
+ * correction coefficient (-0.2, Eq. 14/16), lim_c and lim_s0 the limiter slope
+ * (1e3) and threshold (5e-4) of Eq. 15, riemann_eta the dissipation limiter
+ * constant (3, Eq. 6). */
+typedef struct {
+    int32_t dim;          /* 2 or 3                                              */
+    int32_t dtype;        /* SPH_F32 or SPH_F64: storage and sweep precision     */
+    int64_t n;            /* number of particles, 0 <= n < 2^31                  */
+    int32_t ncell[3];     /* cells per axis (>= 3); unused axes ignored          */
+    int32_t tv_every;     /* apply the correction on steps with index % k == 0;
+                             0 disables it                                       */
+    int32_t per_particle; /* 1: particles carry their own mass and h arrays
+                             (variable resolution); 0: uniform mass and h_min    */
+    double box[3];        /* periodic box edges                                  */
+    double rho0, c0, eta;
+    double h_min, h_max;  /* smallest / largest smoothing length                 */
+    double mass;          /* particle mass when particles.mass == NULL           */
+    double kappa;         /* perfect-lattice kernel sum times dx^D, the reference
+                             sum of Eq. 8 (sph_lattice_kappa)                     */
+    double dt, xi, lim_c, lim_s0, riemann_eta;
+    double band_tol;      /* relative half-width of the limiter band counted in
+                             the diagnostics: |s - s0| <= band_tol * s0          */
+} sph_params;
+
+/* Particle arrays, all device pointers of length N (or [D][N]). */
+typedef struct {
+    int32_t *cell;  /* linear cell index, x fastest                          */
+    int32_t *id;    /* original particle id                                  */
+    void *off;      /* [D][N] cell-local offsets, 0 <= off_k < L_k           */
+    void *vel;      /* [D][N] velocity                                       */
+    void *acc;      /* [D][N] acceleration                                   */
+    void *rho;      /* [N] density                                           */
+    void *mass;     /* [N] per-particle mass (params.per_particle = 1), else
+                       NULL and params.mass applies to all                   */
+    void *h;        /* [N] per-particle smoothing length (per_particle = 1),
+                       else NULL and h_min applies to all                    */
+} sph_particles;
+
+/* Cotangents (adjoint variables) of a state, device arrays in the particle
+ * order of the state they belong to. */
+typedef struct {
+    void *r_bar;    /* [D][N] cotangent of positions     */
+    void *v_bar;    /* [D][N] cotangent of velocities    */
+    void *a_bar;    /* [D][N] cotangent of accelerations */
+    void *rho_bar;  /* [N]    cotangent of densities     */
+} sph_adjoint;
+
+/* Number of diagnostics written by sph_kdk_step / sph_diagnostics. */
+#define SPH_NDIAG 9
+/* diag[0] kinetic energy 1/2 sum m |v|^2, diag[1..3] momentum sum m v,
+ * diag[4] max |v|, diag[5] ordered neighbour pairs at r^{n+1},
+ * diag[6] particles with beta > 0 at step n, diag[7] particles in the
+ * limiter band, diag[8] max |dr| / dt (the transport-velocity magnitude of
+ * Sec. 3's overcorrection discussion).  All reductions are FP64 and
+ * deterministic (fixed-order two-pass, no floating-point atomics). */
+
+/* ---- sizes and constants (host only, synchronous) ------------------------ */
+
+/* Bytes of workspace the step and sweep calls need for these parameters. */
+int32_t sph_workspace_size(const sph_params *p, size_t *bytes);
+
+/* Bytes of one step's tape (the recorded intermediates the adjoint needs). */
+int32_t sph_tape_size(const sph_params *p, size_t *bytes);
+
+/* kappa_D: sum of W(|k| dx, h) dx^D over a perfect lattice, self included,
+ * at h = h_over_dx * dx (dimensionless).  Eq. 8's reference sum; with it a
+ * perfect lattice has rho = rho0 exactly. */
+int32_t sph_lattice_kappa(int32_t dim, double h_over_dx, double *kappa);
+
+/* ---- hot path (asynchronous on `stream`) --------------------------------- */
+
+/* Bin absolute FP64 positions pos[D][N] (device, inside [0, box)) into
+ * particles.cell and particles.off.  Positions outside the box are wrapped
+ * and flagged SPH_FLAG_OUT_OF_BOX.  Does not sort. */
+int32_t sph_bin_positions(const sph_params *p, const double *pos, sph_particles *parts,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/* Cell-linked-list build: sort every particle array in place into
+ * (cell, id) order and write cell_start[ncells + 1] (CSR offsets: the
+ * particles of cell c are cell_start[c] .. cell_start[c+1]-1).  perm
+ * (optional, [N] int32) receives, for each new position, the particle's
+ * previous position.  Neighbour search itself is not in the paper; this is
+ * the data structure every sweep below iterates (3^D cells per particle). */
+int32_t sph_build_cells(const sph_params *p, sph_particles *parts, int32_t *cell_start,
+                        int32_t *perm, void *ws, size_t ws_bytes, void *stream);
+
+/* Density summation, Eq. 8: rho_out[i] = sum_{j in N(i) + i} m_j W_ij / kappa.
+ * Requires the particles sorted and cell_start built.  FP32 sums are
+ * Kahan-compensated. */
+int32_t sph_density(const sph_params *p, const sph_particles *parts,
+                    const int32_t *cell_start, void *rho_out, void *stream);
+
+/* Accelerations, Eq. 3b with the limited linear Riemann solver (Eq. 5-6),
+ * the EOS of Eq. 2 and the viscous term of Eq. 7, from positions, the given
+ * velocity vel[D][N] and parts->rho.  acc_out[D][N].  Coincident particles
+ * contribute no pressure term (their Riemann axis is undefined). */
+int32_t sph_forces(const sph_params *p, const sph_particles *parts,
+                   const int32_t *cell_start, const void *vel, void *acc_out, void *stream);
+
+/* Transport-velocity correction, Eq. 14-16, from positions and parts->rho:
+ * dr_out[D][N]; beta_out [N] (optional) the limiter value; s_out [N] FP64
+ * (optional) h_min^2 |g|^2 (the limiter test is made in FP64); g_out [D][N]
+ * (optional) the raw sum g.  */
+int32_t sph_tv_correction(const sph_params *p, const sph_particles *parts,
+                          const int32_t *cell_start, void *dr_out, void *beta_out,
+                          double *s_out, void *g_out, void *stream);
+
+/* One kick-drift-kick step n -> n+1 (steps 1-7 above) on a state that is
+ * sorted with cell_start built and holds rho^n and a^n.  On return the
+ * particle arrays hold step n+1 in (cell, id) order and cell_start matches.
+ * step_index = n decides whether the correction applies (tv_every).  tape
+ * (optional, sph_tape_size bytes) records what sph_adjoint_step needs.  diag
+ * (optional, device, SPH_NDIAG doubles) receives the diagnostics. */
+int32_t sph_kdk_step(const sph_params *p, sph_particles *parts, int32_t *cell_start,
+                     int64_t step_index, void *ws, size_t ws_bytes, void *tape,
+                     double *diag, void *stream);
+
+/* Diagnostics of the current state alone (KE, momentum, max|v|, pairs);
+ * entries 6-8 are zero. */
+int32_t sph_diagnostics(const sph_params *p, const sph_particles *parts,
+                        const int32_t *cell_start, void *ws, size_t ws_bytes,
+                        double *diag, void *stream);
+
+/* Reverse of one sph_kdk_step recorded in `tape`.  On entry adj holds the
+ * cotangents of step n+1 in step n+1's order; on return those of step n in
+ * step n's order.  xi_bar (device, one double) is incremented by the
+ * derivative with respect to xi.  The neighbour sets are taken as fixed (the
+ * C2 kernel's value and first two derivatives vanish at the support edge);
+ * the limiter jump at s0 has zero derivative. */
+int32_t sph_adjoint_step(const sph_params *p, const void *tape, sph_adjoint *adj,
+                         double *xi_bar, void *ws, size_t ws_bytes, void *stream);
+
+/* Reverse of the initial evaluation rho^0 = R(r^0), a^0 = A(r^0, v^0, rho^0)
+ * on the sorted initial state: adds A^T a_bar to (r_bar, v_bar, rho_bar) and
+ * then R^T rho_bar to r_bar.  a_bar and rho_bar are consumed. */
+int32_t sph_adjoint_init(const sph_params *p, const sph_particles *parts,
+                         const int32_t *cell_start, sph_adjoint *adj, void *ws,
+                         size_t ws_bytes, void *stream);
+
+/* Per-particle neighbour counts |N(i)| (int32 [N]) of the current sorted
+ * state. */
+int32_t sph_neighbor_counts(const sph_params *p, const sph_particles *parts,
+                            const int32_t *cell_start, int32_t *counts, void *stream);
+
+/* ---- errors --------------------------------------------------------------- */
+
+/* Synchronise `stream`, then read (and clear) the device flag word. */
+int32_t sph_get_flags(void *ws, void *stream, uint32_t *host_flags);
+
+/* Clear the device flag word (asynchronous). */
+int32_t sph_clear_flags(void *ws, void *stream);
+
+const char *sph_status_string(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_H */

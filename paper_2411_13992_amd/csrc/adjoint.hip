@@ -1,0 +1,413 @@
+// Reverse (vector-Jacobian) sweeps of one TV-WCSPH step.
+//
+// Every pair term of the forward sweeps is antisymmetric under i <-> j up to
+// the mass ratio (m_i f_ij = -m_j f_ji for the accelerations; the kernel sum
+// of Eq. 8 and the gradient sum of Eq. 14 are symmetric / antisymmetric), so
+// the reverse sweeps are gathers too: particle i collects the derivative of
+// every pair term it takes part in from its own and its neighbours'
+// cotangents, and writes only its own entries.  No atomics.
+//
+// Notation per pair: r = r_i - r_j, q = |r| / h_ij, t = 1 - q/2,
+// F = W'(|r|)/|r| = fc t^3 with fc = -5 alpha / h^2, and
+// F'(|r|) / |r| = -1.5 fc t^2 / (h |r|).
+#include "sph_internal.hpp"
+
+namespace sph {
+
+template <int D, typename T>
+struct PairKernel {
+  T F;        // W'/r
+  T Fpr;      // F'(r)/r
+};
+
+template <int D, typename T, bool VAR>
+__device__ __forceinline__ bool pair_kernel(const Coeffs<T>& k, T r2, T hi, T hj,
+                                            PairKernel<D, T>& pk, T& inv_r) {
+  T sup2, inv_h, fc;
+  if constexpr (VAR) {
+    const T sup = hi + hj;
+    sup2 = sup * sup;
+    inv_h = frcp(T(0.5) * sup);
+    fc = T(-5) * wendland_alpha<D>(inv_h) * inv_h * inv_h;
+  } else {
+    sup2 = k.sup2;
+    inv_h = k.inv_h;
+    fc = k.fcoef;
+  }
+  if (!(r2 < sup2)) return false;
+  inv_r = r2 > T(0) ? frsq(r2) : T(0);
+  const T t = T(1) - T(0.5) * (r2 * inv_r) * inv_h;
+  pk.F = fc * t * t * t;
+  pk.Fpr = T(-1.5) * fc * t * t * inv_h * inv_r;
+  return true;
+}
+
+// ------------------------------------------------------------------ forces^T
+// Accumulates, for each i, over its neighbours j with w = abar_i - (m_i/m_j) abar_j:
+//   rbar_i   += (B.w) Cp r + Cc (-P* w + dP (r.w) v_perp / |r|)
+//   vbar_i   += Cc (eta w + dP (r.w) r / |r|)
+//   rhobar_i += -(f.w) / rho_i - Cc (c0^2/2 + beta c0 dU / 4) (r.w)
+// with Cc = 2 m_j F / (rho_i rho_j), Cp = 2 m_j (F'/|r|) / (rho_i rho_j),
+// B = eta v_ij - P* r, f = Cc B, dP = dP*/dU = rhobar c0 (beta + dU beta') / 2,
+// v_perp = v_ij - (v_ij . r) r / |r|^2.
+template <int D, typename T, bool VAR>
+__global__ __launch_bounds__(kBlock) void force_vjp_kernel(
+    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+    const T* __restrict__ off, const T* __restrict__ vel, const T* __restrict__ rho,
+    const T* __restrict__ mass, const T* __restrict__ hh, const T* __restrict__ a_bar,
+    T* __restrict__ r_bar, T* __restrict__ v_bar, T* __restrict__ rho_bar) {
+  const int n = g.n;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  T oi[3], vi[3], ai[3];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    oi[d] = off[d * n + i];
+    vi[d] = vel[d * n + i];
+    ai[d] = a_bar[d * n + i];
+  }
+  const T rhoi = rho[i];
+  const T inv_rhoi = T(1) / rhoi;
+  const T pi = k.c0sq * (rhoi - k.rho0);
+  const T hi = VAR ? hh[i] : k.h;
+  const T mi = VAR ? mass[i] : k.mass;
+  Acc<T, UseKahan<T>::value> rb[3], vb[3], pb;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    rb[d].init(T(0));
+    vb[d].init(T(0));
+  }
+  pb.init(T(0));
+  for_each_candidate<D>(g, k, cell[i], cs, [&](int j, const T* sh) {
+    T r[3];
+    T r2 = T(0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      r[d] = (oi[d] - off[d * n + j]) - sh[d];
+      r2 += r[d] * r[d];
+    }
+    if (j == i) return;
+    PairKernel<D, T> pk;
+    T inv_r;
+    if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? hh[j] : k.h, pk, inv_r)) return;
+    const T mj = VAR ? mass[j] : k.mass;
+    const T rhoj = rho[j];
+    const T pj = k.c0sq * (rhoj - k.rho0);
+    T vij[3], w[3];
+    T vr = T(0);
+    const T mratio = VAR ? mi / mj : T(1);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      vij[d] = vi[d] - vel[d * n + j];
+      vr += vij[d] * r[d];
+      w[d] = ai[d] - mratio * a_bar[d * n + j];
+    }
+    const T du = -vr * inv_r;
+    const T x = k.riemann_eta * du * k.inv_c0;
+    const T br = tmin(tmax(x, T(0)), T(1));
+    const T bprime = (x > T(0) && x < T(1)) ? k.riemann_eta * k.inv_c0 : T(0);
+    const T rhobar = T(0.5) * (rhoi + rhoj);
+    const T pstar = T(0.5) * (pi + pj) + T(0.5) * br * rhobar * k.c0 * du;
+    const T dP = T(0.5) * rhobar * k.c0 * (br + du * bprime);
+    const T base = T(2) * mj * inv_rhoi / rhoj;
+    const T Cc = base * pk.F;
+    const T Cp = base * pk.Fpr;
+    T Bw = T(0), rw = T(0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const T B = k.eta * vij[d] - pstar * r[d];
+      Bw += B * w[d];
+      rw += r[d] * w[d];
+    }
+    const T vperp_coef = vr * inv_r * inv_r;   // (v_ij . r) / |r|^2
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const T vperp = vij[d] - vperp_coef * r[d];
+      rb[d].add(Bw * Cp * r[d] + Cc * (-pstar * w[d] + dP * rw * vperp * inv_r));
+      vb[d].add(Cc * (k.eta * w[d] + dP * inv_r * rw * r[d]));
+    }
+    pb.add(-Cc * Bw * inv_rhoi - Cc * (T(0.5) * k.c0sq + T(0.25) * br * k.c0 * du) * rw);
+  });
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    r_bar[d * n + i] += rb[d].value();
+    v_bar[d * n + i] += vb[d].value();
+  }
+  rho_bar[i] += pb.value();
+}
+
+// ------------------------------------------------------------------ density^T
+// rbar_i += sum_j (rhobar_i m_j + rhobar_j m_i) F_ij r_ij / kappa, then
+// vbar_i += vcoef * rbar_i (the drift r' = r + dt v' of the same step).
+template <int D, typename T, bool VAR>
+__global__ __launch_bounds__(kBlock) void density_vjp_kernel(
+    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+    const T* __restrict__ off, const T* __restrict__ mass, const T* __restrict__ hh,
+    const T* __restrict__ rho_bar, T* __restrict__ r_bar, T* __restrict__ v_bar, T vcoef) {
+  const int n = g.n;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  T oi[3];
+#pragma unroll
+  for (int d = 0; d < D; ++d) oi[d] = off[d * n + i];
+  const T hi = VAR ? hh[i] : k.h;
+  const T mi = VAR ? mass[i] : k.mass;
+  const T pbi = rho_bar[i];
+  Acc<T, UseKahan<T>::value> acc[3];
+#pragma unroll
+  for (int d = 0; d < D; ++d) acc[d].init(T(0));
+  for_each_candidate<D>(g, k, cell[i], cs, [&](int j, const T* sh) {
+    T r[3];
+    T r2 = T(0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      r[d] = (oi[d] - off[d * n + j]) - sh[d];
+      r2 += r[d] * r[d];
+    }
+    if (j == i) return;
+    PairKernel<D, T> pk;
+    T inv_r;
+    if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? hh[j] : k.h, pk, inv_r)) return;
+    const T mj = VAR ? mass[j] : k.mass;
+    const T c = (pbi * mj + rho_bar[j] * mi) * pk.F;
+#pragma unroll
+    for (int d = 0; d < D; ++d) acc[d].add(c * r[d]);
+  });
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const T rb = r_bar[d * n + i] + acc[d].value() * k.inv_kappa;
+    r_bar[d * n + i] = rb;
+    if (v_bar) v_bar[d * n + i] += vcoef * rb;
+  }
+}
+
+// ------------------------------------------------------------------ correction^T, pass 1
+// ghat_i = xi h^2 (beta_i rbar_i + 2 C h^2 (g_i . rbar_i) g_i [ramp branch only]);
+// per-block partials of sum_i h^2 beta_i g_i . rbar_i (the xi derivative).
+template <int D, typename T>
+__global__ __launch_bounds__(kBlock) void tv_ghat_kernel(Coeffs<T> k, int n,
+                                                         const T* __restrict__ gsum,
+                                                         const T* __restrict__ beta,
+                                                         const T* __restrict__ r_bar,
+                                                         T* __restrict__ ghat,
+                                                         double* __restrict__ partials) {
+  __shared__ double red[kBlock / kWave];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  double xi_part = 0.0;
+  if (i < n) {
+    double gg = 0.0, gr = 0.0;
+    double gi[3], ri[3];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      gi[d] = (double)gsum[d * n + i];
+      ri[d] = (double)r_bar[d * n + i];
+      gg += gi[d] * gi[d];
+      gr += gi[d] * ri[d];
+    }
+    const double b = (double)beta[i];
+    const double s = k.hmin2 * gg;
+    const bool ramp = (s > k.lim_s0) && (k.lim_c * s < 1.0);
+    const double two_c_h2 = ramp ? 2.0 * k.lim_c * k.hmin2 : 0.0;
+    const double f = k.xi * k.hmin2;
+#pragma unroll
+    for (int d = 0; d < D; ++d) ghat[d * n + i] = (T)(f * (b * ri[d] + two_c_h2 * gr * gi[d]));
+    xi_part = k.hmin2 * b * gr;
+  }
+  const double tot = block_reduce<double, false>(xi_part, red);
+  if (threadIdx.x == 0) partials[blockIdx.x * kNumPartials] = tot;
+}
+
+// ------------------------------------------------------------------ correction^T, pass 2
+// r_out_i = r_in_i + sum_j H_ij (V_j ghat_i - V_i ghat_j),  H = F I + (F'/r) r r^T
+// rho_out_i = (m_i / rho_i^2) sum_j F_ij (ghat_j . r_ij)
+template <int D, typename T, bool VAR>
+__global__ __launch_bounds__(kBlock) void tv_vjp_kernel(
+    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+    const T* __restrict__ off, const T* __restrict__ rho, const T* __restrict__ mass,
+    const T* __restrict__ hh, const T* __restrict__ ghat, const T* __restrict__ r_in,
+    T* __restrict__ r_out, T* __restrict__ rho_out) {
+  const int n = g.n;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  T oi[3], gi[3];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    oi[d] = off[d * n + i];
+    gi[d] = ghat[d * n + i];
+  }
+  const T hi = VAR ? hh[i] : k.h;
+  const T mi = VAR ? mass[i] : k.mass;
+  const T rhoi = rho[i];
+  const T Vi = mi / rhoi;
+  Acc<T, UseKahan<T>::value> acc[3], pb;
+#pragma unroll
+  for (int d = 0; d < D; ++d) acc[d].init(T(0));
+  pb.init(T(0));
+  for_each_candidate<D>(g, k, cell[i], cs, [&](int j, const T* sh) {
+    T r[3];
+    T r2 = T(0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      r[d] = (oi[d] - off[d * n + j]) - sh[d];
+      r2 += r[d] * r[d];
+    }
+    if (j == i) return;
+    PairKernel<D, T> pk;
+    T inv_r;
+    if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? hh[j] : k.h, pk, inv_r)) return;
+    const T mj = VAR ? mass[j] : k.mass;
+    const T Vj = mj / rho[j];
+    T u[3], gj[3];
+    T ur = T(0), gjr = T(0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      gj[d] = ghat[d * n + j];
+      u[d] = Vj * gi[d] - Vi * gj[d];
+      ur += u[d] * r[d];
+      gjr += gj[d] * r[d];
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) acc[d].add(pk.F * u[d] + pk.Fpr * ur * r[d]);
+    pb.add(pk.F * gjr);
+  });
+#pragma unroll
+  for (int d = 0; d < D; ++d) r_out[d * n + i] = r_in[d * n + i] + acc[d].value();
+  rho_out[i] = pb.value() * mi / (rhoi * rhoi);
+}
+
+// ------------------------------------------------------------------ elementwise
+template <typename T>
+__global__ __launch_bounds__(kBlock) void unpermute_kernel(int n, int ncomp, const int* __restrict__ perm,
+                                                           const T* __restrict__ src,
+                                                           T* __restrict__ dst) {
+  const int q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= n) return;
+  const int p = perm[q];
+  for (int d = 0; d < ncomp; ++d) dst[d * n + p] = src[d * n + q];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void adj_kick_kernel(long dn, T half_dt, const T* __restrict__ v_bar,
+                                                          T* __restrict__ a_bar) {
+  const long i = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (i < dn) a_bar[i] += half_dt * v_bar[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void adj_finish_kernel(long dn, T half_dt,
+                                                            const T* __restrict__ vh_bar,
+                                                            T* __restrict__ v_bar,
+                                                            T* __restrict__ a_bar) {
+  const long i = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (i < dn) {
+    const T v = vh_bar[i];
+    v_bar[i] = v;
+    a_bar[i] = half_dt * v;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void xi_final_kernel(int nblk, const double* __restrict__ partials,
+                                                          double* __restrict__ xi_bar) {
+  __shared__ double red[kBlock / kWave];
+  double v = 0.0;
+  for (int r = threadIdx.x; r < nblk; r += kBlock) v += partials[r * kNumPartials];
+  const double t = block_reduce<double, false>(v, red);
+  if (threadIdx.x == 0) xi_bar[0] += t;
+}
+
+// ------------------------------------------------------------------ launchers
+#define SPH_DISPATCH(KERNEL, ...)                                                            \
+  do {                                                                                       \
+    dim3 grid_(l.nblk), block_(kBlock);                                                      \
+    if (l.dim == 2) {                                                                        \
+      if (l.var) hipLaunchKernelGGL((KERNEL<2, T, true>), grid_, block_, 0, l.stream, __VA_ARGS__); \
+      else hipLaunchKernelGGL((KERNEL<2, T, false>), grid_, block_, 0, l.stream, __VA_ARGS__);     \
+    } else {                                                                                 \
+      if (l.var) hipLaunchKernelGGL((KERNEL<3, T, true>), grid_, block_, 0, l.stream, __VA_ARGS__); \
+      else hipLaunchKernelGGL((KERNEL<3, T, false>), grid_, block_, 0, l.stream, __VA_ARGS__);     \
+    }                                                                                        \
+  } while (0)
+
+template <typename T>
+void launch_force_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
+                      const int* cs, const T* vel, const T* a_bar, T* r_bar, T* v_bar,
+                      T* rho_bar) {
+  if (g.n == 0) return;
+  SPH_DISPATCH(force_vjp_kernel, g, k, p.cell, cs, p.off, vel, p.rho, p.mass, p.h, a_bar, r_bar,
+               v_bar, rho_bar);
+}
+
+template <typename T>
+void launch_density_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
+                        const int* cs, const T* rho_bar, T* r_bar, T* v_bar, T vcoef) {
+  if (g.n == 0) return;
+  SPH_DISPATCH(density_vjp_kernel, g, k, p.cell, cs, p.off, p.mass, p.h, rho_bar, r_bar, v_bar,
+               vcoef);
+}
+
+template <typename T>
+void launch_tv_ghat(const Launch& l, const Coeffs<T>& k, int n, const T* gsum, const T* beta,
+                    const T* r_bar, T* ghat, double* partials) {
+  if (n == 0) return;
+  if (l.dim == 2)
+    hipLaunchKernelGGL((tv_ghat_kernel<2, T>), dim3(l.nblk), dim3(kBlock), 0, l.stream, k, n,
+                       gsum, beta, r_bar, ghat, partials);
+  else
+    hipLaunchKernelGGL((tv_ghat_kernel<3, T>), dim3(l.nblk), dim3(kBlock), 0, l.stream, k, n,
+                       gsum, beta, r_bar, ghat, partials);
+}
+
+template <typename T>
+void launch_tv_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
+                   const int* cs, const T* ghat, const T* r_in, T* r_out, T* rho_out) {
+  if (g.n == 0) return;
+  SPH_DISPATCH(tv_vjp_kernel, g, k, p.cell, cs, p.off, p.rho, p.mass, p.h, ghat, r_in, r_out,
+               rho_out);
+}
+
+template <typename T>
+void launch_unpermute(const Launch& l, int n, const int* perm, const T* src, T* dst, int ncomp) {
+  if (n == 0) return;
+  hipLaunchKernelGGL((unpermute_kernel<T>), dim3(blocks_for(n)), dim3(kBlock), 0, l.stream, n,
+                     ncomp, perm, src, dst);
+}
+
+template <typename T>
+void launch_adj_kick(const Launch& l, const Coeffs<T>& k, int n, const T* v_bar, T* a_bar) {
+  const long dn = (long)l.dim * n;
+  if (dn == 0) return;
+  hipLaunchKernelGGL((adj_kick_kernel<T>), dim3(blocks_for(dn)), dim3(kBlock), 0, l.stream, dn,
+                     k.half_dt, v_bar, a_bar);
+}
+
+template <typename T>
+void launch_adj_finish(const Launch& l, const Coeffs<T>& k, int n, const T* vhalf_bar, T* v_bar,
+                       T* a_bar) {
+  const long dn = (long)l.dim * n;
+  if (dn == 0) return;
+  hipLaunchKernelGGL((adj_finish_kernel<T>), dim3(blocks_for(dn)), dim3(kBlock), 0, l.stream, dn,
+                     k.half_dt, vhalf_bar, v_bar, a_bar);
+}
+
+void launch_xi_final(hipStream_t s, int nblk, const double* partials, double* xi_bar) {
+  hipLaunchKernelGGL(xi_final_kernel, dim3(1), dim3(kBlock), 0, s, nblk, partials, xi_bar);
+}
+
+#define SPH_INST(T)                                                                          \
+  template void launch_force_vjp<T>(const Launch&, const Grid&, const Coeffs<T>&,            \
+                                    const PArrays<T>&, const int*, const T*, const T*, T*,   \
+                                    T*, T*);                                                 \
+  template void launch_density_vjp<T>(const Launch&, const Grid&, const Coeffs<T>&,          \
+                                      const PArrays<T>&, const int*, const T*, T*, T*, T);   \
+  template void launch_tv_ghat<T>(const Launch&, const Coeffs<T>&, int, const T*, const T*,  \
+                                  const T*, T*, double*);                                    \
+  template void launch_tv_vjp<T>(const Launch&, const Grid&, const Coeffs<T>&,               \
+                                 const PArrays<T>&, const int*, const T*, const T*, T*, T*); \
+  template void launch_unpermute<T>(const Launch&, int, const int*, const T*, T*, int);      \
+  template void launch_adj_kick<T>(const Launch&, const Coeffs<T>&, int, const T*, T*);      \
+  template void launch_adj_finish<T>(const Launch&, const Coeffs<T>&, int, const T*, T*, T*);
+SPH_INST(float)
+SPH_INST(double)
+#undef SPH_INST
+
+}  // namespace sph

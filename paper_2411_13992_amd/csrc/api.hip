@@ -1,0 +1,728 @@
+// libsph C-ABI: argument checks, workspace and tape layout, and the order of
+// kernel launches for each entry point.  Declarations and the contract of
+// every function are in include/sph.h.
+#include <cmath>
+#include <cstring>
+
+#include "sph.h"
+#include "sph_internal.hpp"
+
+namespace sph {
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Sizes {
+  int dim, n, ncells, nblk;
+  size_t tsz;     // bytes per float element
+  bool var;
+};
+
+// Workspace regions (byte offsets from the workspace base).
+struct WsLayout {
+  size_t flags, counts, block_sums, slot, tmp, perm;
+  size_t stg_cell, stg_id, stg_off, stg_vel, stg_acc, stg_rho, stg_mass, stg_h;
+  size_t dr, partials;
+  size_t adj_r, adj_v, adj_rho, adj_g, adj_r2;
+  size_t total;
+};
+
+// One step's tape: the sorted state before the step (order n), the raw
+// correction sum and limiter value at step n, the permutation from order
+// n+1 to order n, and the sorted state after the forces (order n+1, with the
+// half-step velocity).
+struct TapeLayout {
+  size_t pre_cell, pre_off, pre_rho, pre_mass, pre_h, pre_cs, g, beta, perm;
+  size_t post_cell, post_off, post_vhalf, post_rho, post_mass, post_h, post_cs;
+  size_t total;
+};
+
+struct Cursor {
+  size_t o = 0;
+  size_t take(size_t bytes) {
+    size_t r = o;
+    o += align_up(bytes > 0 ? bytes : 1);
+    return r;
+  }
+};
+
+Sizes sizes_of(const sph_params* p, bool var) {
+  Sizes s;
+  s.dim = p->dim;
+  s.n = (int)p->n;
+  s.ncells = p->ncell[0] * p->ncell[1] * (p->dim == 3 ? p->ncell[2] : 1);
+  s.nblk = blocks_for(s.n);
+  s.tsz = p->dtype == SPH_F64 ? 8 : 4;
+  s.var = var;
+  return s;
+}
+
+WsLayout ws_layout(const Sizes& s) {
+  Cursor c;
+  WsLayout w;
+  const size_t n = (size_t)s.n, dn = (size_t)s.dim * n, t = s.tsz;
+  w.flags = c.take(kAlign);
+  w.counts = c.take(sizeof(int) * ((size_t)s.ncells + 1));
+  w.block_sums = c.take(sizeof(int) * ((size_t)scan_blocks(s.ncells) + 1));
+  w.slot = c.take(sizeof(int) * n);
+  w.tmp = c.take(sizeof(int) * n);
+  w.perm = c.take(sizeof(int) * n);
+  w.stg_cell = c.take(sizeof(int) * n);
+  w.stg_id = c.take(sizeof(int) * n);
+  w.stg_off = c.take(t * dn);
+  w.stg_vel = c.take(t * dn);
+  w.stg_acc = c.take(t * dn);
+  w.stg_rho = c.take(t * n);
+  w.stg_mass = c.take(t * n);
+  w.stg_h = c.take(t * n);
+  w.dr = c.take(t * dn);
+  w.partials = c.take(sizeof(double) * kNumPartials * (size_t)(s.nblk > 0 ? s.nblk : 1));
+  w.adj_r = c.take(t * dn);
+  w.adj_v = c.take(t * dn);
+  w.adj_rho = c.take(t * n);
+  w.adj_g = c.take(t * dn);
+  w.adj_r2 = c.take(t * dn);
+  w.total = c.o;
+  return w;
+}
+
+TapeLayout tape_layout(const Sizes& s) {
+  Cursor c;
+  TapeLayout tl;
+  const size_t n = (size_t)s.n, dn = (size_t)s.dim * n, t = s.tsz;
+  const size_t cs = sizeof(int) * ((size_t)s.ncells + 1);
+  tl.pre_cell = c.take(sizeof(int) * n);
+  tl.pre_off = c.take(t * dn);
+  tl.pre_rho = c.take(t * n);
+  tl.pre_mass = c.take(s.var ? t * n : 0);
+  tl.pre_h = c.take(s.var ? t * n : 0);
+  tl.pre_cs = c.take(cs);
+  tl.g = c.take(t * dn);
+  tl.beta = c.take(t * n);
+  tl.perm = c.take(sizeof(int) * n);
+  tl.post_cell = c.take(sizeof(int) * n);
+  tl.post_off = c.take(t * dn);
+  tl.post_vhalf = c.take(t * dn);
+  tl.post_rho = c.take(t * n);
+  tl.post_mass = c.take(s.var ? t * n : 0);
+  tl.post_h = c.take(s.var ? t * n : 0);
+  tl.post_cs = c.take(cs);
+  tl.total = c.o;
+  return tl;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+int32_t check_params(const sph_params* p) {
+  if (!p) return SPH_E_ARG;
+  if (p->dim != 2 && p->dim != 3) return SPH_E_UNSUPPORTED;
+  if (p->dtype != SPH_F32 && p->dtype != SPH_F64) return SPH_E_UNSUPPORTED;
+  if (p->n < 0 || p->n >= (int64_t(1) << 31)) return SPH_E_ARG;
+  if (p->tv_every < 0) return SPH_E_ARG;
+  if (p->per_particle != 0 && p->per_particle != 1) return SPH_E_ARG;
+  const double vals[] = {p->rho0, p->c0, p->h_min, p->h_max, p->kappa, p->mass};
+  for (double v : vals)
+    if (!std::isfinite(v)) return SPH_E_NONFINITE;
+  const double maybe_zero[] = {p->eta, p->dt, p->xi, p->lim_c, p->lim_s0, p->riemann_eta,
+                               p->band_tol};
+  for (double v : maybe_zero)
+    if (!std::isfinite(v)) return SPH_E_NONFINITE;
+  if (!finite_pos(p->rho0) || !finite_pos(p->c0) || !finite_pos(p->h_min) ||
+      !finite_pos(p->kappa) || !finite_pos(p->mass))
+    return SPH_E_ARG;
+  if (p->h_max < p->h_min || p->eta < 0.0 || p->dt < 0.0) return SPH_E_ARG;
+  long ncells = 1;
+  for (int k = 0; k < p->dim; ++k) {
+    if (!finite_pos(p->box[k])) return SPH_E_ARG;
+    if (p->ncell[k] < 3) return SPH_E_CELL_RANGE;
+    const double L = p->box[k] / p->ncell[k];
+    if (L < 2.0 * p->h_max * (1.0 - 1e-12)) return SPH_E_CELL_RANGE;
+    ncells *= p->ncell[k];
+  }
+  // the cell scan handles up to 2048 * 2048 cells
+  if (ncells > 2048L * 2048L) return SPH_E_UNSUPPORTED;
+  return SPH_OK;
+}
+
+Grid grid_of(const sph_params* p) {
+  Grid g;
+  g.n = (int)p->n;
+  for (int k = 0; k < 3; ++k) {
+    const bool used = k < p->dim;
+    g.nc[k] = used ? p->ncell[k] : 1;
+    g.box[k] = used ? p->box[k] : 1.0;
+    g.L[k] = used ? p->box[k] / p->ncell[k] : 1.0;
+  }
+  g.ncells = g.nc[0] * g.nc[1] * g.nc[2];
+  return g;
+}
+
+template <typename T>
+T round_down(double x) {
+  T t = (T)x;
+  if ((double)t > x) t = std::nextafter(t, T(0));
+  return t;
+}
+
+template <typename T>
+Coeffs<T> coeffs_of(const sph_params* p, const Grid& g) {
+  Coeffs<T> k;
+  for (int d = 0; d < 3; ++d) k.L[d] = round_down<T>(g.L[d]);
+  const double h = p->h_min;
+  const double alpha = p->dim == 2 ? 7.0 / (4.0 * kPi * h * h) : 21.0 / (16.0 * kPi * h * h * h);
+  k.h = (T)h;
+  k.inv_h = (T)(1.0 / h);
+  k.sup2 = (T)(4.0 * h * h);
+  k.alpha = (T)alpha;
+  k.fcoef = (T)(-5.0 * alpha / (h * h));
+  k.mass = (T)p->mass;
+  k.rho0 = (T)p->rho0;
+  k.c0 = (T)p->c0;
+  k.c0sq = (T)(p->c0 * p->c0);
+  k.inv_c0 = (T)(1.0 / p->c0);
+  k.eta = (T)p->eta;
+  k.riemann_eta = (T)p->riemann_eta;
+  k.inv_kappa = (T)(1.0 / p->kappa);
+  k.dt = (T)p->dt;
+  k.half_dt = (T)(0.5 * p->dt);
+  k.xi = p->xi;
+  k.lim_c = p->lim_c;
+  k.lim_s0 = p->lim_s0;
+  k.hmin2 = h * h;
+  k.band_tol = p->band_tol;
+  k.inv_dt = p->dt > 0.0 ? 1.0 / p->dt : 0.0;
+  return k;
+}
+
+template <typename T>
+PArrays<T> arrays_of(const sph_particles* s) {
+  PArrays<T> a;
+  a.cell = s->cell;
+  a.id = s->id;
+  a.off = (T*)s->off;
+  a.vel = (T*)s->vel;
+  a.acc = (T*)s->acc;
+  a.rho = (T*)s->rho;
+  a.mass = (T*)s->mass;
+  a.h = (T*)s->h;
+  return a;
+}
+
+template <typename T>
+PArrays<T> staging_of(char* ws, const WsLayout& w, bool var) {
+  PArrays<T> a;
+  a.cell = (int*)(ws + w.stg_cell);
+  a.id = (int*)(ws + w.stg_id);
+  a.off = (T*)(ws + w.stg_off);
+  a.vel = (T*)(ws + w.stg_vel);
+  a.acc = (T*)(ws + w.stg_acc);
+  a.rho = (T*)(ws + w.stg_rho);
+  a.mass = var ? (T*)(ws + w.stg_mass) : nullptr;
+  a.h = var ? (T*)(ws + w.stg_h) : nullptr;
+  return a;
+}
+
+int32_t hip_status() {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SPH_OK : SPH_E_HIP;
+}
+
+int32_t check_particles(const sph_params* p, const sph_particles* s, bool need_dyn) {
+  if (!s) return SPH_E_ARG;
+  if (p->n == 0) return SPH_OK;
+  if (!s->cell || !s->id || !s->off) return SPH_E_ARG;
+  if (need_dyn && (!s->vel || !s->acc || !s->rho)) return SPH_E_ARG;
+  if (p->per_particle) {
+    if (!s->mass || !s->h) return SPH_E_ARG;
+  } else if (s->mass || s->h) {
+    return SPH_E_ARG;
+  }
+  return SPH_OK;
+}
+
+bool is_var(const sph_params* p) { return p->per_particle == 1; }
+
+Launch launch_of(const sph_params* p, bool var, void* stream) {
+  Launch l;
+  l.dim = p->dim;
+  l.var = var;
+  l.stream = (hipStream_t)stream;
+  l.nblk = blocks_for(p->n);
+  return l;
+}
+
+hipError_t copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+}
+
+// ---------------------------------------------------------------- cell build
+template <typename T>
+int32_t build_cells_t(const sph_params* p, sph_particles* parts, int32_t* cs, int32_t* perm,
+                      char* ws, hipStream_t stream) {
+  const bool var = is_var(p);
+  const Sizes sz = sizes_of(p, var);
+  const WsLayout w = ws_layout(sz);
+  Launch l = launch_of(p, var, stream);
+  int* counts = (int*)(ws + w.counts);
+  launch_fill(stream, counts, sz.ncells, 0);
+  PArrays<T> src = arrays_of<T>(parts);
+  PArrays<T> stg = staging_of<T>(ws, w, var);
+  if (!src.vel) stg.vel = nullptr;
+  if (!src.acc) stg.acc = nullptr;
+  if (!src.rho) stg.rho = nullptr;
+  launch_stage_copy<T>(l, sz.n, src, stg, counts, (int*)(ws + w.slot));
+  launch_scan(stream, sz.ncells, counts, (int*)(ws + w.block_sums), cs);
+  launch_scatter(stream, sz.n, stg.cell, (int*)(ws + w.slot), cs, (int*)(ws + w.tmp));
+  launch_rank_gather<T>(l, sz.n, (int*)(ws + w.tmp), cs, stg, src, perm);
+  return hip_status();
+}
+
+// ---------------------------------------------------------------- step
+template <typename T>
+int32_t kdk_step_t(const sph_params* p, sph_particles* parts, int32_t* cs, int64_t step_index,
+                   char* ws, char* tape, double* diag, hipStream_t stream) {
+  const bool var = is_var(p);
+  const Sizes sz = sizes_of(p, var);
+  const WsLayout w = ws_layout(sz);
+  const Grid g = grid_of(p);
+  const Coeffs<T> k = coeffs_of<T>(p, g);
+  const Launch l = launch_of(p, var, stream);
+  unsigned* flags = (unsigned*)(ws + w.flags);
+  double* partials = diag ? (double*)(ws + w.partials) : nullptr;
+  PArrays<T> a = arrays_of<T>(parts);
+  PArrays<T> stg = staging_of<T>(ws, w, var);
+  const size_t n = (size_t)sz.n, dn = (size_t)sz.dim * n, t = sz.tsz;
+  const size_t csb = sizeof(int) * ((size_t)sz.ncells + 1);
+  const bool apply = p->tv_every > 0 && (step_index % p->tv_every) == 0;
+  TapeLayout tl;
+  if (tape) {
+    tl = tape_layout(sz);
+    hipError_t e = hipSuccess;
+    e = e ? e : copy_d2d(tape + tl.pre_cell, a.cell, sizeof(int) * n, stream);
+    e = e ? e : copy_d2d(tape + tl.pre_off, a.off, t * dn, stream);
+    e = e ? e : copy_d2d(tape + tl.pre_rho, a.rho, t * n, stream);
+    if (var) {
+      e = e ? e : copy_d2d(tape + tl.pre_mass, a.mass, t * n, stream);
+      e = e ? e : copy_d2d(tape + tl.pre_h, a.h, t * n, stream);
+    }
+    e = e ? e : copy_d2d(tape + tl.pre_cs, cs, csb, stream);
+    if (e != hipSuccess) return SPH_E_HIP;
+  }
+  if (partials) launch_zero_partials(stream, sz.nblk, partials);
+
+  // 1. transport-velocity correction at r^n (Eq. 14-16)
+  T* dr = nullptr;
+  if (apply) {
+    dr = (T*)(ws + w.dr);
+    launch_tv<T>(l, g, k, a, cs, dr, tape ? (T*)(tape + tl.beta) : nullptr, nullptr,
+                 tape ? (T*)(tape + tl.g) : nullptr, partials);
+  } else if (tape) {
+    // no correction this step: record g = 0, beta = 0 (the reverse then adds nothing)
+    launch_zero<T>(stream, (T*)(tape + tl.g), (long)dn);
+    launch_zero<T>(stream, (T*)(tape + tl.beta), (long)n);
+  }
+  // 2. half kick + drift + rebin, 3. cell build
+  int* counts = (int*)(ws + w.counts);
+  int* slot = (int*)(ws + w.slot);
+  launch_fill(stream, counts, sz.ncells, 0);
+  launch_drift<T>(l, g, k, a, dr, stg, counts, slot, flags);
+  launch_scan(stream, sz.ncells, counts, (int*)(ws + w.block_sums), cs);
+  launch_scatter(stream, sz.n, stg.cell, slot, cs, (int*)(ws + w.tmp));
+  PArrays<T> dst = a;
+  dst.acc = nullptr;
+  dst.rho = nullptr;
+  PArrays<T> src = stg;
+  src.acc = nullptr;
+  src.rho = nullptr;
+  int* perm = (int*)(ws + w.perm);
+  launch_rank_gather<T>(l, sz.n, (int*)(ws + w.tmp), cs, src, dst, perm);
+  // 4. density summation (Eq. 8), 5-6. accelerations at (r^{n+1}, v', rho^{n+1})
+  launch_density<T>(l, g, k, a, cs, a.rho, partials, nullptr, flags);
+  launch_forces<T>(l, g, k, a, cs, a.vel, a.acc, flags);
+  if (tape) {
+    hipError_t e = hipSuccess;
+    e = e ? e : copy_d2d(tape + tl.perm, perm, sizeof(int) * n, stream);
+    e = e ? e : copy_d2d(tape + tl.post_cell, a.cell, sizeof(int) * n, stream);
+    e = e ? e : copy_d2d(tape + tl.post_off, a.off, t * dn, stream);
+    e = e ? e : copy_d2d(tape + tl.post_vhalf, a.vel, t * dn, stream);
+    e = e ? e : copy_d2d(tape + tl.post_rho, a.rho, t * n, stream);
+    if (var) {
+      e = e ? e : copy_d2d(tape + tl.post_mass, a.mass, t * n, stream);
+      e = e ? e : copy_d2d(tape + tl.post_h, a.h, t * n, stream);
+    }
+    e = e ? e : copy_d2d(tape + tl.post_cs, cs, csb, stream);
+    if (e != hipSuccess) return SPH_E_HIP;
+  }
+  // 7. second half kick with FP64 diagnostics
+  launch_kick<T>(l, k, sz.n, a.vel, a.acc, a.mass, partials, true, flags);
+  if (diag) launch_diag_final(stream, sz.nblk, partials, diag);
+  return hip_status();
+}
+
+// ---------------------------------------------------------------- adjoint
+template <typename T>
+int32_t adjoint_step_t(const sph_params* p, const char* tape, sph_adjoint* adj, double* xi_bar,
+                       char* ws, hipStream_t stream) {
+  const bool var = is_var(p);
+  const Sizes sz = sizes_of(p, var);
+  const WsLayout w = ws_layout(sz);
+  const TapeLayout tl = tape_layout(sz);
+  const Grid g = grid_of(p);
+  const Coeffs<T> k = coeffs_of<T>(p, g);
+  const Launch l = launch_of(p, var, stream);
+  T* r_bar = (T*)adj->r_bar;
+  T* v_bar = (T*)adj->v_bar;
+  T* a_bar = (T*)adj->a_bar;
+  T* rho_bar = (T*)adj->rho_bar;
+  // state after the step (order n+1) and before it (order n), as recorded
+  PArrays<T> post{};
+  post.cell = (int*)(tape + tl.post_cell);
+  post.off = (T*)(tape + tl.post_off);
+  post.vel = (T*)(tape + tl.post_vhalf);
+  post.rho = (T*)(tape + tl.post_rho);
+  post.mass = var ? (T*)(tape + tl.post_mass) : nullptr;
+  post.h = var ? (T*)(tape + tl.post_h) : nullptr;
+  PArrays<T> pre{};
+  pre.cell = (int*)(tape + tl.pre_cell);
+  pre.off = (T*)(tape + tl.pre_off);
+  pre.rho = (T*)(tape + tl.pre_rho);
+  pre.mass = var ? (T*)(tape + tl.pre_mass) : nullptr;
+  pre.h = var ? (T*)(tape + tl.pre_h) : nullptr;
+  const int* cs_post = (const int*)(tape + tl.post_cs);
+  const int* cs_pre = (const int*)(tape + tl.pre_cs);
+  T* r_n = (T*)(ws + w.adj_r);
+  T* vh_n = (T*)(ws + w.adj_v);
+  T* ghat = (T*)(ws + w.adj_g);
+  double* partials = (double*)(ws + w.partials);
+
+  // 7^T: v = v' + dt/2 a  =>  abar += dt/2 vbar, v'bar = vbar
+  launch_adj_kick<T>(l, k, sz.n, v_bar, a_bar);
+  // 6^T, 5^T: accelerations (r^{n+1}, v', rho^{n+1})
+  launch_force_vjp<T>(l, g, k, post, cs_post, post.vel, a_bar, r_bar, v_bar, rho_bar);
+  // 4^T: density, then 2-3^T: r^{n+1} = r^n + dt v' + dr  =>  v'bar += dt rbar
+  launch_density_vjp<T>(l, g, k, post, cs_post, rho_bar, r_bar, v_bar, k.dt);
+  // the cell build is a permutation: back to order n
+  const int* perm = (const int*)(tape + tl.perm);
+  launch_unpermute<T>(l, sz.n, perm, r_bar, r_n, sz.dim);
+  launch_unpermute<T>(l, sz.n, perm, v_bar, vh_n, sz.dim);
+  // 1^T: the correction dr = T(r^n, rho^n; xi)
+  launch_tv_ghat<T>(l, k, sz.n, (const T*)(tape + tl.g), (const T*)(tape + tl.beta), r_n, ghat,
+                    partials);
+  if (xi_bar) launch_xi_final(stream, sz.nblk, partials, xi_bar);
+  launch_tv_vjp<T>(l, g, k, pre, cs_pre, ghat, r_n, r_bar, rho_bar);
+  // 2^T: v' = v^n + dt/2 a^n
+  launch_adj_finish<T>(l, k, sz.n, vh_n, v_bar, a_bar);
+  return hip_status();
+}
+
+template <typename T>
+int32_t adjoint_init_t(const sph_params* p, const sph_particles* parts, const int32_t* cs,
+                       sph_adjoint* adj, hipStream_t stream) {
+  const bool var = is_var(p);
+  const Sizes sz = sizes_of(p, var);
+  const Grid g = grid_of(p);
+  const Coeffs<T> k = coeffs_of<T>(p, g);
+  const Launch l = launch_of(p, var, stream);
+  PArrays<T> a = arrays_of<T>(parts);
+  T* r_bar = (T*)adj->r_bar;
+  T* v_bar = (T*)adj->v_bar;
+  T* a_bar = (T*)adj->a_bar;
+  T* rho_bar = (T*)adj->rho_bar;
+  launch_force_vjp<T>(l, g, k, a, cs, a.vel, a_bar, r_bar, v_bar, rho_bar);
+  launch_density_vjp<T>(l, g, k, a, cs, rho_bar, r_bar, nullptr, T(0));
+  launch_zero<T>(stream, a_bar, (long)sz.dim * sz.n);
+  launch_zero<T>(stream, rho_bar, (long)sz.n);
+  return hip_status();
+}
+
+template <typename F>
+int32_t dispatch(const sph_params* p, F&& f) {
+  if (p->dtype == SPH_F64) return f(double(0));
+  return f(float(0));
+}
+
+}  // namespace
+}  // namespace sph
+
+using namespace sph;
+
+extern "C" {
+
+int32_t sph_workspace_size(const sph_params* p, size_t* bytes) {
+  int32_t st = check_params(p);
+  if (st != SPH_OK) return st;
+  if (!bytes) return SPH_E_ARG;
+  // laid out for the variable-resolution case so one size fits both
+  *bytes = ws_layout(sizes_of(p, true)).total;
+  return SPH_OK;
+}
+
+int32_t sph_tape_size(const sph_params* p, size_t* bytes) {
+  int32_t st = check_params(p);
+  if (st != SPH_OK) return st;
+  if (!bytes) return SPH_E_ARG;
+  *bytes = tape_layout(sizes_of(p, is_var(p))).total;
+  return SPH_OK;
+}
+
+int32_t sph_lattice_kappa(int32_t dim, double h_over_dx, double* kappa) {
+  if ((dim != 2 && dim != 3) || !kappa || !(h_over_dx > 0.0) || !std::isfinite(h_over_dx))
+    return SPH_E_ARG;
+  // sum over integer lattice vectors k with |k| < 2 h/dx of W(|k|, h), self included
+  const double h = h_over_dx;
+  const double alpha = dim == 2 ? 7.0 / (4.0 * kPi * h * h) : 21.0 / (16.0 * kPi * h * h * h);
+  const int reach = (int)std::ceil(2.0 * h);
+  double sum = 0.0;
+  for (int z = (dim == 3 ? -reach : 0); z <= (dim == 3 ? reach : 0); ++z)
+    for (int y = -reach; y <= reach; ++y)
+      for (int x = -reach; x <= reach; ++x) {
+        const double q = std::sqrt((double)(x * x + y * y + z * z)) / h;
+        if (q < 2.0) {
+          const double t = 1.0 - 0.5 * q;
+          sum += alpha * t * t * t * t * (1.0 + 2.0 * q);
+        }
+      }
+  *kappa = sum;
+  return SPH_OK;
+}
+
+int32_t sph_bin_positions(const sph_params* p, const double* pos, sph_particles* parts, void* ws,
+                          size_t ws_bytes, void* stream) {
+  int32_t st = check_params(p);
+  if (st != SPH_OK) return st;
+  if (!parts || !ws) return SPH_E_ARG;
+  size_t need = 0;
+  sph_workspace_size(p, &need);
+  if (ws_bytes < need) return SPH_E_WORKSPACE;
+  if (p->n == 0) return SPH_OK;
+  if (!pos || !parts->cell || !parts->off) return SPH_E_ARG;
+  const Grid g = grid_of(p);
+  const Launch l = launch_of(p, is_var(p), stream);
+  const WsLayout w = ws_layout(sizes_of(p, true));
+  unsigned* flags = (unsigned*)((char*)ws + w.flags);
+  return dispatch(p, [&](auto tag) {
+    using T = decltype(tag);
+    launch_bin<T>(l, g, coeffs_of<T>(p, g), pos, parts->cell, (T*)parts->off, flags);
+    return hip_status();
+  });
+}
+
+int32_t sph_build_cells(const sph_params* p, sph_particles* parts, int32_t* cell_start,
+                        int32_t* perm, void* ws, size_t ws_bytes, void* stream) {
+  int32_t st = check_params(p);
+  if (st != SPH_OK) return st;
+  st = check_particles(p, parts, false);
+  if (st != SPH_OK) return st;
+  if (!cell_start || !ws) return SPH_E_ARG;
+  size_t need = 0;
+  sph_workspace_size(p, &need);
+  if (ws_bytes < need) return SPH_E_WORKSPACE;
+  return dispatch(p, [&](auto tag) {
+    using T = decltype(tag);
+    return build_cells_t<T>(p, parts, cell_start, perm, (char*)ws, (hipStream_t)stream);
+  });
+}
+
+int32_t sph_density(const sph_params* p, const sph_particles* parts, const int32_t* cell_start,
+                    void* rho_out, void* stream) {
+  int32_t st = check_params(p);
+  if (st != SPH_OK) return st;
+  st = check_particles(p, parts, false);
+  if (st != SPH_OK) return st;
+  if (p->n == 0) return SPH_OK;
+  if (!cell_start || !rho_out) return SPH_E_ARG;
+  const Grid g = grid_of(p);
+  const Launch l = launch_of(p, is_var(p), stream);
+  return dispatch(p, [&](auto tag) {
+    using T = decltype(tag);
+    launch_density<T>(l, g, coeffs_of<T>(p, g), arrays_of<T>(parts), cell_start, (T*)rho_out,
+                      nullptr, nullptr, nullptr);
+    return hip_status();
+  });
+}
+
+int32_t sph_neighbor_counts(const sph_params* p, const sph_particles* parts,
+                            const int32_t* cell_start, int32_t* counts, void* stream) {
+  int32_t st = check_params(p);
+  if (st != SPH_OK) return st;
+  st = check_particles(p, parts, false);
+  if (st != SPH_OK) return st;
+  if (p->n == 0) return SPH_OK;
+  if (!cell_start || !counts || !parts->rho) return SPH_E_ARG;
+  const Grid g = grid_of(p);
+  const Launch l = launch_of(p, is_var(p), stream);
+  // the density sweep counts its neighbours; it rewrites rho with the same values
+  return dispatch(p, [&](auto tag) {
+    using T = decltype(tag);
+    PArrays<T> a = arrays_of<T>(parts);
+    launch_density<T>(l, g, coeffs_of<T>(p, g), a, cell_start, a.rho, nullptr, counts, nullptr);
+    return hip_status();
+  });
+}
+
+int32_t sph_forces(const sph_params* p, const sph_particles* parts, const int32_t* cell_start,
+                   const void* vel, void* acc_out, void* stream) {
+  int32_t st = check_params(p);
+  if (st != SPH_OK) return st;
+  st = check_particles(p, parts, false);
+  if (st != SPH_OK) return st;
+  if (p->n == 0) return SPH_OK;
+  if (!cell_start || !vel || !acc_out || !parts->rho) return SPH_E_ARG;
+  const Grid g = grid_of(p);
+  const Launch l = launch_of(p, is_var(p), stream);
+  return dispatch(p, [&](auto tag) {
+    using T = decltype(tag);
+    launch_forces<T>(l, g, coeffs_of<T>(p, g), arrays_of<T>(parts), cell_start, (const T*)vel,
+                     (T*)acc_out, nullptr);
+    return hip_status();
+  });
+}
+
+int32_t sph_tv_correction(const sph_params* p, const sph_particles* parts,
+                          const int32_t* cell_start, void* dr_out, void* beta_out, double* s_out,
+                          void* g_out, void* stream) {
+  int32_t st = check_params(p);
+  if (st != SPH_OK) return st;
+  st = check_particles(p, parts, false);
+  if (st != SPH_OK) return st;
+  if (p->n == 0) return SPH_OK;
+  if (!cell_start || !dr_out || !parts->rho) return SPH_E_ARG;
+  const Grid g = grid_of(p);
+  const Launch l = launch_of(p, is_var(p), stream);
+  return dispatch(p, [&](auto tag) {
+    using T = decltype(tag);
+    launch_tv<T>(l, g, coeffs_of<T>(p, g), arrays_of<T>(parts), cell_start, (T*)dr_out,
+                 (T*)beta_out, s_out, (T*)g_out, nullptr);
+    return hip_status();
+  });
+}
+
+int32_t sph_kdk_step(const sph_params* p, sph_particles* parts, int32_t* cell_start,
+                     int64_t step_index, void* ws, size_t ws_bytes, void* tape, double* diag,
+                     void* stream) {
+  int32_t st = check_params(p);
+  if (st != SPH_OK) return st;
+  st = check_particles(p, parts, true);
+  if (st != SPH_OK) return st;
+  if (!cell_start || !ws || step_index < 0) return SPH_E_ARG;
+  size_t need = 0;
+  sph_workspace_size(p, &need);
+  if (ws_bytes < need) return SPH_E_WORKSPACE;
+  if (p->n == 0) {
+    if (diag) {
+      const WsLayout w = ws_layout(sizes_of(p, true));
+      double* partials = (double*)((char*)ws + w.partials);
+      launch_zero_partials((hipStream_t)stream, 1, partials);
+      launch_diag_final((hipStream_t)stream, 0, partials, diag);
+    }
+    return hip_status();
+  }
+  return dispatch(p, [&](auto tag) {
+    using T = decltype(tag);
+    return kdk_step_t<T>(p, parts, cell_start, step_index, (char*)ws, (char*)tape, diag,
+                         (hipStream_t)stream);
+  });
+}
+
+int32_t sph_diagnostics(const sph_params* p, const sph_particles* parts, const int32_t* cell_start,
+                        void* ws, size_t ws_bytes, double* diag, void* stream) {
+  int32_t st = check_params(p);
+  if (st != SPH_OK) return st;
+  st = check_particles(p, parts, true);
+  if (st != SPH_OK) return st;
+  if (!ws || !diag) return SPH_E_ARG;
+  size_t need = 0;
+  sph_workspace_size(p, &need);
+  if (ws_bytes < need) return SPH_E_WORKSPACE;
+  const bool var = is_var(p);
+  const Sizes sz = sizes_of(p, var);
+  const WsLayout w = ws_layout(sizes_of(p, true));
+  double* partials = (double*)((char*)ws + w.partials);
+  hipStream_t s = (hipStream_t)stream;
+  launch_zero_partials(s, sz.nblk, partials);
+  if (p->n > 0) {
+    if (!cell_start) return SPH_E_ARG;
+    const Grid g = grid_of(p);
+    const Launch l = launch_of(p, var, stream);
+    st = dispatch(p, [&](auto tag) {
+      using T = decltype(tag);
+      const Coeffs<T> k = coeffs_of<T>(p, g);
+      PArrays<T> a = arrays_of<T>(parts);
+      // pair count from a density sweep into the staging buffer (state untouched)
+      launch_density<T>(l, g, k, a, cell_start, (T*)((char*)ws + w.stg_rho), partials, nullptr,
+                        nullptr);
+      launch_kick<T>(l, k, sz.n, a.vel, a.acc, a.mass, partials, false, nullptr);
+      return SPH_OK;
+    });
+  }
+  launch_diag_final(s, sz.nblk, partials, diag);
+  return hip_status();
+}
+
+int32_t sph_adjoint_step(const sph_params* p, const void* tape, sph_adjoint* adj, double* xi_bar,
+                         void* ws, size_t ws_bytes, void* stream) {
+  int32_t st = check_params(p);
+  if (st != SPH_OK) return st;
+  if (!tape || !adj || !ws) return SPH_E_ARG;
+  size_t need = 0;
+  sph_workspace_size(p, &need);
+  if (ws_bytes < need) return SPH_E_WORKSPACE;
+  if (p->n == 0) return SPH_OK;
+  if (!adj->r_bar || !adj->v_bar || !adj->a_bar || !adj->rho_bar) return SPH_E_ARG;
+  return dispatch(p, [&](auto tag) {
+    using T = decltype(tag);
+    return adjoint_step_t<T>(p, (const char*)tape, adj, xi_bar, (char*)ws, (hipStream_t)stream);
+  });
+}
+
+int32_t sph_adjoint_init(const sph_params* p, const sph_particles* parts, const int32_t* cell_start,
+                         sph_adjoint* adj, void* ws, size_t ws_bytes, void* stream) {
+  int32_t st = check_params(p);
+  if (st != SPH_OK) return st;
+  st = check_particles(p, parts, true);
+  if (st != SPH_OK) return st;
+  if (!adj || !ws) return SPH_E_ARG;
+  size_t need = 0;
+  sph_workspace_size(p, &need);
+  if (ws_bytes < need) return SPH_E_WORKSPACE;
+  if (p->n == 0) return SPH_OK;
+  if (!cell_start || !adj->r_bar || !adj->v_bar || !adj->a_bar || !adj->rho_bar) return SPH_E_ARG;
+  return dispatch(p, [&](auto tag) {
+    using T = decltype(tag);
+    return adjoint_init_t<T>(p, parts, cell_start, adj, (hipStream_t)stream);
+  });
+}
+
+int32_t sph_get_flags(void* ws, void* stream, uint32_t* host_flags) {
+  if (!ws || !host_flags) return SPH_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipStreamSynchronize(s) != hipSuccess) return SPH_E_HIP;
+  if (hipMemcpy(host_flags, ws, sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return SPH_E_HIP;
+  launch_fill(s, (int*)ws, 1, 0);
+  if (hipStreamSynchronize(s) != hipSuccess) return SPH_E_HIP;
+  return hip_status();
+}
+
+int32_t sph_clear_flags(void* ws, void* stream) {
+  if (!ws) return SPH_E_ARG;
+  launch_fill((hipStream_t)stream, (int*)ws, 1, 0);
+  return hip_status();
+}
+
+const char* sph_status_string(int32_t status) {
+  switch (status) {
+    case SPH_OK: return "ok";
+    case SPH_E_ARG: return "invalid argument";
+    case SPH_E_HIP: return "HIP runtime error";
+    case SPH_E_WORKSPACE: return "workspace or tape too small";
+    case SPH_E_CELL_RANGE: return "cell grid too fine for the kernel support (need >= 3 cells of edge >= 2 h_max per axis)";
+    case SPH_E_NONFINITE: return "non-finite parameter";
+    case SPH_E_UNSUPPORTED: return "unsupported dimension, dtype or size";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

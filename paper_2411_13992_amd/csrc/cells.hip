@@ -1,0 +1,255 @@
+// Cell-linked-list build: bin absolute positions into (cell, offset), then
+// order particles by (cell, id).
+//
+// The order is a counting sort by cell (integer histogram with atomic slot
+// claims, exclusive scan, scatter) followed by ranking inside each cell by
+// id.  The slot claimed by the atomic is arbitrary, but the final order is
+// not: a particle's destination is cell_start[cell] + |{ q in cell : id_q < id }|,
+// a function of (cell, id) alone, so the result is bit-reproducible.
+#include "sph_internal.hpp"
+
+namespace sph {
+
+// ------------------------------------------------------------------ binning
+template <int D, typename T>
+__global__ __launch_bounds__(kBlock) void bin_kernel(Grid g, Coeffs<T> k,
+                                                     const double* __restrict__ pos,
+                                                     int* __restrict__ cell, T* __restrict__ off,
+                                                     unsigned* __restrict__ flags) {
+  const int n = g.n;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int c[3] = {0, 0, 0};
+  unsigned f = 0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    double x = pos[d * n + i];
+    const double B = g.box[d];
+    if (!isfinite(x)) {
+      f |= kFlagNonfinite;
+      x = 0.0;
+    }
+    if (!(x >= 0.0 && x < B)) {
+      f |= kFlagOutOfBox;
+      x -= B * floor(x / B);
+      if (!(x < B)) x = 0.0;
+    }
+    const double L = g.L[d];
+    int ci = (int)floor(x / L);
+    ci = ci < 0 ? 0 : (ci >= g.nc[d] ? g.nc[d] - 1 : ci);
+    double o = x - (double)ci * L;
+    if (o < 0.0) {
+      ci = wrap_index(ci - 1, g.nc[d]);
+      o += L;
+    }
+    T ot = (T)o;
+    if (ot >= k.L[d]) {           // rounds onto the face: start of the next cell
+      ci = wrap_index(ci + 1, g.nc[d]);
+      ot = T(0);
+    }
+    c[d] = ci;
+    off[d * n + i] = ot;
+  }
+  int lin = c[0] + g.nc[0] * (c[1] + g.nc[1] * c[2]);
+  cell[i] = lin;
+  if (f) atomicOr(flags, f);
+}
+
+template <typename T>
+void launch_bin(const Launch& l, const Grid& g, const Coeffs<T>& k, const double* pos,
+                int* cell, T* off, unsigned* flags) {
+  if (g.n == 0) return;
+  if (l.dim == 2)
+    hipLaunchKernelGGL((bin_kernel<2, T>), dim3(l.nblk), dim3(kBlock), 0, l.stream, g, k, pos,
+                       cell, off, flags);
+  else
+    hipLaunchKernelGGL((bin_kernel<3, T>), dim3(l.nblk), dim3(kBlock), 0, l.stream, g, k, pos,
+                       cell, off, flags);
+}
+
+// ------------------------------------------------------------------ fill
+__global__ __launch_bounds__(kBlock) void fill_kernel(int* __restrict__ p, long n, int v) {
+  long i = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+void launch_fill(hipStream_t s, int* p, long n, int v) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, p, n, v);
+}
+
+// ------------------------------------------------------------------ histogram
+__global__ __launch_bounds__(kBlock) void histogram_kernel(int n, const int* __restrict__ cell,
+                                                           int* __restrict__ counts,
+                                                           int* __restrict__ slot) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) slot[i] = atomicAdd(&counts[cell[i]], 1);
+}
+
+void launch_histogram(hipStream_t s, int n, const int* cell, int* counts, int* slot) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(histogram_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, cell, counts,
+                     slot);
+}
+
+// ------------------------------------------------------------------ scan
+// Three passes: per-block totals, a one-block scan of the totals, then a
+// per-block exclusive scan offset by the scanned totals.
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+int scan_blocks(int ncells) { return (ncells + kScanTile - 1) / kScanTile; }
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* lds, int* total) {
+  // inclusive scan within the wave
+  const int lane = threadIdx.x % kWave;
+  const int wave = threadIdx.x / kWave;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    int y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) lds[wave] = x;
+  __syncthreads();
+  int base = 0, tot = 0;
+  for (int w = 0; w < kBlock / kWave; ++w) {
+    if (w < wave) base += lds[w];
+    tot += lds[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_reduce_kernel(int ncells, const int* __restrict__ counts,
+                                                             int* __restrict__ block_sums) {
+  __shared__ int lds[kBlock / kWave];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int s = 0;
+#pragma unroll
+  for (int t = 0; t < kScanItems; ++t) s += (base + t < ncells) ? counts[base + t] : 0;
+  int total;
+  block_exclusive_scan(s, lds, &total);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_top_kernel(int nb, int* __restrict__ block_sums) {
+  // exclusive scan of nb <= kScanTile block totals in place; block_sums[nb] = grand total
+  __shared__ int lds[kBlock / kWave];
+  const int base = threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int s = 0;
+#pragma unroll
+  for (int t = 0; t < kScanItems; ++t) {
+    v[t] = (base + t < nb) ? block_sums[base + t] : 0;
+    s += v[t];
+  }
+  int total;
+  int run = block_exclusive_scan(s, lds, &total);
+#pragma unroll
+  for (int t = 0; t < kScanItems; ++t) {
+    if (base + t < nb) block_sums[base + t] = run;
+    run += v[t];
+  }
+  if (threadIdx.x == 0) block_sums[nb] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_apply_kernel(int ncells, const int* __restrict__ counts,
+                                                            const int* __restrict__ block_sums,
+                                                            int* __restrict__ cs, int nb) {
+  __shared__ int lds[kBlock / kWave];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int s = 0;
+#pragma unroll
+  for (int t = 0; t < kScanItems; ++t) {
+    v[t] = (base + t < ncells) ? counts[base + t] : 0;
+    s += v[t];
+  }
+  int total;
+  int run = block_exclusive_scan(s, lds, &total) + block_sums[blockIdx.x];
+#pragma unroll
+  for (int t = 0; t < kScanItems; ++t) {
+    if (base + t < ncells) cs[base + t] = run;
+    run += v[t];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) cs[ncells] = block_sums[nb];
+}
+
+void launch_scan(hipStream_t s, int ncells, const int* counts, int* block_sums, int* cs) {
+  const int nb = scan_blocks(ncells);
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(kBlock), 0, s, ncells, counts, block_sums);
+  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kBlock), 0, s, nb, block_sums);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(kBlock), 0, s, ncells, counts, block_sums,
+                     cs, nb);
+}
+
+// ------------------------------------------------------------------ scatter
+__global__ __launch_bounds__(kBlock) void scatter_kernel(int n, const int* __restrict__ cell,
+                                                         const int* __restrict__ slot,
+                                                         const int* __restrict__ cs,
+                                                         int* __restrict__ tmp) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) tmp[cs[cell[i]] + slot[i]] = i;
+}
+
+void launch_scatter(hipStream_t s, int n, const int* cell, const int* slot, const int* cs, int* tmp) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, cell, slot, cs,
+                     tmp);
+}
+
+// ------------------------------------------------------------------ rank + gather
+// tmp[p] holds the old index of the particle in slot p of its cell; its final
+// position is cell_start + (number of cell members with a smaller id).
+template <int D, typename T>
+__global__ __launch_bounds__(kBlock) void rank_gather_kernel(int n, const int* __restrict__ tmp,
+                                                             const int* __restrict__ cs,
+                                                             PArrays<T> stg, PArrays<T> dst,
+                                                             int* __restrict__ perm) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n) return;
+  const int src = tmp[p];
+  const int c = stg.cell[src];
+  const int idk = stg.id[src];
+  const int b = cs[c], e = cs[c + 1];
+  int rank = 0;
+  for (int q = b; q < e; ++q) rank += stg.id[tmp[q]] < idk ? 1 : 0;
+  const int to = b + rank;
+  if (perm) perm[to] = src;
+  dst.cell[to] = c;
+  dst.id[to] = idk;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    dst.off[d * n + to] = stg.off[d * n + src];
+    if (dst.vel) dst.vel[d * n + to] = stg.vel[d * n + src];
+    if (dst.acc) dst.acc[d * n + to] = stg.acc[d * n + src];
+  }
+  if (dst.rho) dst.rho[to] = stg.rho[src];
+  if (dst.mass) dst.mass[to] = stg.mass[src];
+  if (dst.h) dst.h[to] = stg.h[src];
+}
+
+template <typename T>
+void launch_rank_gather(const Launch& l, int n, const int* tmp, const int* cs,
+                        const PArrays<T>& stg, const PArrays<T>& dst, int* perm) {
+  if (n == 0) return;
+  if (l.dim == 2)
+    hipLaunchKernelGGL((rank_gather_kernel<2, T>), dim3(blocks_for(n)), dim3(kBlock), 0, l.stream,
+                       n, tmp, cs, stg, dst, perm);
+  else
+    hipLaunchKernelGGL((rank_gather_kernel<3, T>), dim3(blocks_for(n)), dim3(kBlock), 0, l.stream,
+                       n, tmp, cs, stg, dst, perm);
+}
+
+#define SPH_INST(T)                                                                          \
+  template void launch_bin<T>(const Launch&, const Grid&, const Coeffs<T>&, const double*,   \
+                              int*, T*, unsigned*);                                          \
+  template void launch_rank_gather<T>(const Launch&, int, const int*, const int*,            \
+                                      const PArrays<T>&, const PArrays<T>&, int*);
+SPH_INST(float)
+SPH_INST(double)
+#undef SPH_INST
+
+}  // namespace sph

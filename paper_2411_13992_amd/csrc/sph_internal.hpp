@@ -1,0 +1,99 @@
+// Launchers shared between the libsph translation units (not part of the ABI).
+#pragma once
+
+#include "sph_dev.hpp"
+
+namespace sph {
+
+// Device flag bits (mirrors include/sph.h)
+constexpr unsigned kFlagNonfinite = 1u;
+constexpr unsigned kFlagCfl = 2u;
+constexpr unsigned kFlagOutOfBox = 4u;
+
+struct Launch {
+  int dim;
+  bool var;            // per-particle mass and h present
+  hipStream_t stream;
+  int nblk;            // particle blocks: ceil(n / kBlock)
+};
+
+inline int blocks_for(long n) { return (int)((n + kBlock - 1) / kBlock); }
+
+// Particle arrays in the sweep precision T.
+template <typename T>
+struct PArrays {
+  int* cell;
+  int* id;
+  T* off;
+  T* vel;
+  T* acc;
+  T* rho;
+  T* mass;   // null for uniform
+  T* h;      // null for uniform
+};
+
+// ---- sweeps (sweeps.hip)
+template <typename T>
+void launch_density(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
+                    const int* cs, T* rho_out, double* partials, int* counts, unsigned* flags);
+template <typename T>
+void launch_tv(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
+               const int* cs, T* dr, T* beta, double* s_out, T* g_out, double* partials);
+template <typename T>
+void launch_forces(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
+                   const int* cs, const T* vel, T* acc_out, unsigned* flags);
+
+// ---- cells (cells.hip)
+template <typename T>
+void launch_bin(const Launch& l, const Grid& g, const Coeffs<T>& k, const double* pos,
+                int* cell, T* off, unsigned* flags);
+void launch_fill(hipStream_t s, int* p, long n, int v);
+void launch_histogram(hipStream_t s, int n, const int* cell, int* counts, int* slot);
+// exclusive scan of counts[ncells] into cs[ncells + 1]; block_sums has
+// scan_blocks(ncells) + 1 entries
+int scan_blocks(int ncells);
+void launch_scan(hipStream_t s, int ncells, const int* counts, int* block_sums, int* cs);
+void launch_scatter(hipStream_t s, int n, const int* cell, const int* slot, const int* cs, int* tmp);
+// Moves staged arrays (old order) into dst arrays (new order); null pointers skip.
+template <typename T>
+void launch_rank_gather(const Launch& l, int n, const int* tmp, const int* cs,
+                        const PArrays<T>& stg, const PArrays<T>& dst, int* perm);
+
+// ---- integration (kdk.hip)
+template <typename T>
+void launch_stage_copy(const Launch& l, int n, const PArrays<T>& src, const PArrays<T>& stg,
+                       int* counts, int* slot);
+template <typename T>
+void launch_drift(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
+                  const T* dr, const PArrays<T>& stg, int* counts, int* slot, unsigned* flags);
+template <typename T>
+void launch_kick(const Launch& l, const Coeffs<T>& k, int n, T* vel, const T* acc,
+                 const T* mass, double* partials, bool write, unsigned* flags);
+void launch_diag_final(hipStream_t s, int nblk, const double* partials, double* diag);
+void launch_zero_partials(hipStream_t s, int nblk, double* partials);
+template <typename T>
+void launch_zero(hipStream_t s, T* p, long n);
+
+// ---- adjoint (adjoint.hip)
+template <typename T>
+void launch_force_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
+                      const int* cs, const T* vel, const T* a_bar, T* r_bar, T* v_bar, T* rho_bar);
+template <typename T>
+void launch_density_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
+                        const int* cs, const T* rho_bar, T* r_bar, T* v_bar, T vcoef);
+template <typename T>
+void launch_tv_ghat(const Launch& l, const Coeffs<T>& k, int n, const T* gsum, const T* beta,
+                    const T* r_bar, T* ghat, double* partials);
+template <typename T>
+void launch_tv_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
+                   const int* cs, const T* ghat, const T* r_in, T* r_out, T* rho_out);
+template <typename T>
+void launch_unpermute(const Launch& l, int n, const int* perm, const T* src, T* dst, int ncomp);
+template <typename T>
+void launch_adj_finish(const Launch& l, const Coeffs<T>& k, int n, const T* vhalf_bar,
+                       T* v_bar, T* a_bar);
+template <typename T>
+void launch_adj_kick(const Launch& l, const Coeffs<T>& k, int n, const T* v_bar, T* a_bar);
+void launch_xi_final(hipStream_t s, int nblk, const double* partials, double* xi_bar);
+
+}  // namespace sph

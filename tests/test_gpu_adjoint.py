@@ -1,0 +1,235 @@
+"""Hand-written adjoint (sph_adjoint_step / sph_adjoint_init) against finite
+differences: of the GPU's own FP64 forward for single maps, and of the FP64
+oracle for whole rollouts.  The neighbour sets are locally constant and the
+limiter jump has zero derivative, so every finite difference here checks that
+no limiter branch flips between its two evaluations."""
+import numpy as np
+import pytest
+
+import cases
+import oracle
+from tests import parity_utils as pu
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(case, dtype, **kw):
+    import torch
+    from paper_2411_13992_amd import Simulation
+    sim = Simulation.from_case(case, dtype=dtype, **kw)
+    torch.cuda.synchronize()
+    return sim
+
+
+def central_fd(f, eps0, tries=5):
+    """Central difference (f(+eps) - f(-eps)) / (2 eps) of f(x) returning
+    (value, limiter pattern); halves eps until both evaluations take the same
+    limiter branches at every step (a branch flip is a jump, not a slope)."""
+    eps = eps0
+    for _ in range(tries):
+        vp, pp = f(eps)
+        vm, pm = f(-eps)
+        if np.array_equal(pp, pm):
+            return (vp - vm) / (2 * eps)
+        eps *= 0.25
+    raise AssertionError("limiter branch flips at every tried step size")
+
+
+def _init_cases():
+    return {
+        "tg2d_jit": cases.taylor_green_2d(24, jitter=0.2, seed=12),
+        "tg3d_jit": cases.taylor_green_3d(10, jitter=0.2, seed=13),
+        "varres": cases.variable_resolution_2d(dp_min=1.0 / 60, jitter=0.1, seed=14),
+    }
+
+
+INIT = _init_cases()
+
+
+@pytest.mark.parametrize("name", list(INIT))
+def test_init_vjp_matches_fd(name):
+    """(r, v) -> (rho = R(r), a = A(r, v, rho)): <abar, da> + <rhobar, drho> along
+    a random direction equals <rbar, dr> + <vbar, dv> from sph_adjoint_init."""
+    import torch
+    from paper_2411_13992_amd.adjoint import Adjoint, adjoint_init
+    case = INIT[name]
+    sim = _sim(case, "f64", eta=0.05)
+    g = torch.Generator(device="cpu").manual_seed(3)
+    d, n = sim.dim, sim.n
+    abar = torch.randn((d, n), generator=g, dtype=torch.float64).cuda()
+    rbar_in = torch.randn(n, generator=g, dtype=torch.float64).cuda()
+    dr = torch.randn((d, n), generator=g, dtype=torch.float64).cuda() * case.dx
+    dv = torch.randn((d, n), generator=g, dtype=torch.float64).cuda()
+    adj = Adjoint(sim)
+    adj.a.copy_(abar)
+    adj.rho.copy_(rbar_in)
+    adjoint_init(sim, adj)
+    pred = float((adj.r * dr).sum() + (adj.v * dv).sum())
+    base_off, base_vel = sim.off.clone(), sim.vel.clone()
+    vals = []
+    eps = 1e-6
+    for sgn in (1.0, -1.0):
+        sim.off.copy_(base_off + sgn * eps * dr)
+        sim.vel.copy_(base_vel + sgn * eps * dv)
+        rho = sim.density(out=torch.empty_like(sim.rho))
+        saved = sim.rho.clone()
+        sim.rho.copy_(rho)
+        acc = sim.forces(out=torch.empty_like(sim.acc))
+        sim.rho.copy_(saved)
+        vals.append(float((abar * acc).sum() + (rbar_in * rho).sum()))
+    fd = (vals[0] - vals[1]) / (2 * eps)
+    assert abs(pred - fd) <= 1e-6 * abs(fd), (pred, fd)
+
+
+def _step_loss(sim, c, base_snap):
+    """<c_r, r^{n+1}> + <c_v, v^{n+1}> + <c_a, a^{n+1}> + <c_rho, rho^{n+1}>
+    (c in id order; positions relative to the start for continuity)."""
+    import torch
+    sim.step(1)
+    ex = sim.export()
+    r = pu.min_image(ex["pos"], c["r0"], c["box"]) + c["r0"]
+    return float(np.sum(c["r"] * r) + np.sum(c["v"] * ex["vel"]) + np.sum(c["a"] * ex["acc"])
+                 + np.sum(c["rho"] * ex["rho"]))
+
+
+@pytest.mark.parametrize("name", list(INIT))
+def test_step_vjp_matches_fd(name):
+    """One kick-drift-kick step as a map of (r^n, v^n, a^n, rho^n, xi): the
+    reverse step agrees with a central difference of the FP64 forward, with
+    the correction active (jittered input, limiter in all three branches)."""
+    import torch
+    from paper_2411_13992_amd.adjoint import Adjoint, adjoint_step
+    case = INIT[name]
+    sim = _sim(case, "f64")
+    d, n = sim.dim, sim.n
+    rng = np.random.default_rng(5)
+    start = sim.snapshot()
+    ex0 = sim.export()
+    c = {"r": rng.normal(size=(d, n)), "v": rng.normal(size=(d, n)),
+         "a": rng.normal(size=(d, n)) * 1e-2, "rho": rng.normal(size=n) * 1e-2,
+         "r0": ex0["pos"], "box": case.box}
+    # reverse step from the recorded tape
+    tape = torch.empty(sim.tape_bytes(), dtype=torch.uint8, device=sim.device)
+    sim.step(1, tape=tape)
+    ids1 = sim.id.long()
+    adj = Adjoint(sim)
+    for buf, key in ((adj.r, "r"), (adj.v, "v"), (adj.a, "a")):
+        buf.copy_(torch.from_numpy(c[key]).cuda()[:, ids1])
+    adj.rho.copy_(torch.from_numpy(c["rho"]).cuda()[ids1])
+    xi_bar = torch.zeros(1, dtype=torch.float64, device=sim.device)
+    adjoint_step(sim, tape, adj, xi_bar)
+    sim.restore(start)
+    # random input direction, sorted order n
+    g = torch.Generator(device="cpu").manual_seed(8)
+    dr = torch.randn((d, n), generator=g, dtype=torch.float64).cuda() * case.dx
+    dv = torch.randn((d, n), generator=g, dtype=torch.float64).cuda()
+    da = torch.randn((d, n), generator=g, dtype=torch.float64).cuda()
+    drho = torch.randn(n, generator=g, dtype=torch.float64).cuda() * 1e-3
+    dxi = 0.3
+    pred = float((adj.r * dr).sum() + (adj.v * dv).sum() + (adj.a * da).sum()
+                 + (adj.rho * drho).sum()) + xi_bar.item() * dxi
+    xi0 = sim.params.xi
+    vals, nbeta = [], []
+    eps = 1e-6
+    for sgn in (1.0, -1.0):
+        sim.restore(start)
+        sim.off.add_(sgn * eps * dr)
+        sim.vel.add_(sgn * eps * dv)
+        sim.acc.add_(sgn * eps * da)
+        sim.rho.add_(sgn * eps * drho)
+        sim.set_xi(xi0 + sgn * eps * dxi)
+        vals.append(_step_loss(sim, c, start))
+        nbeta.append(sim.diagnostics()["nbeta"])
+    sim.set_xi(xi0)
+    assert nbeta[0] == nbeta[1], "a limiter branch flipped inside the difference"
+    fd = (vals[0] - vals[1]) / (2 * eps)
+    assert abs(pred - fd) <= 1e-6 * abs(fd), (pred, fd)
+    assert xi_bar.item() != 0.0
+
+
+def _oracle_ke(case, pos, v0, xi, nsteps, tv_every=1):
+    st = oracle.State(case, pos=pos, vel=v0, xi=xi, tv_every=tv_every)
+    d = st.run(nsteps)
+    return st.kinetic_energy(), d[:, 6]
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-6), ("f32", 1e-4)])
+def test_rollout_gradient_matches_oracle_fd(dtype, tol):
+    """Gradient of KE(v^N) after 12 steps (checkpoints every 5: segments 5, 5, 2)
+    with respect to v^0 (three random directions) and xi, against central
+    differences of the FP64 oracle started from the same particles."""
+    import torch
+    from paper_2411_13992_amd.adjoint import rollout, kinetic_energy
+    case = cases.taylor_green_2d(16, jitter=0.15, seed=21, vel_perturb=0.01)
+    sim = _sim(case, dtype)
+    pos0 = sim.positions_fp64(sim.initial["cell"], sim.initial["off"])
+    ids0 = sim.initial["id"].cpu().numpy()
+    pos_by_id = np.empty_like(pos0)
+    pos_by_id[:, ids0] = pos0
+    v0 = torch.tensor(case.vel, dtype=torch.float64, device="cuda", requires_grad=True)
+    xi = torch.tensor(case.xi, dtype=torch.float64, device="cuda", requires_grad=True)
+    nsteps = 12
+    vN = rollout(sim, v0, xi, nsteps, every=5)
+    loss = kinetic_energy(sim, vN)
+    loss.backward()
+    gv = v0.grad.cpu().numpy()
+    gxi = xi.grad.item()
+    rng = np.random.default_rng(4)
+    for k in range(3):
+        u = rng.normal(size=case.vel.shape)
+        fd = central_fd(lambda e: _oracle_ke(case, pos_by_id, case.vel + e * u, case.xi,
+                                             nsteps), 1e-6)
+        assert abs(np.sum(gv * u) - fd) <= tol * abs(fd), (k, np.sum(gv * u), fd)
+    fd = central_fd(lambda e: _oracle_ke(case, pos_by_id, case.vel, case.xi + e, nsteps), 1e-6)
+    assert fd != 0.0
+    assert abs(gxi - fd) <= tol * abs(fd), (gxi, fd)
+
+
+def _gpu_ke(sim, v0, xi, nsteps):
+    """KE(v^N) of an FP64 GPU run and its per-step count of beta > 0."""
+    import torch
+    from paper_2411_13992_amd.adjoint import kinetic_energy
+    sim.set_xi(xi)
+    sim.restore(sim.initial)
+    sim.set_velocity(v0)
+    sim.init_fields()
+    nbeta = torch.zeros(nsteps, dtype=torch.float64, device=sim.device)
+    for s in range(nsteps):
+        sim.step(1)
+        nbeta[s] = sim.diag[6]
+    return float(kinetic_energy(sim, sim.velocity_by_id())), nbeta.cpu().numpy()
+
+
+@pytest.mark.parametrize("jitter", [0.0, 0.05])
+def test_adjoint_workload_fp32_vs_fp64_fd(jitter):
+    """The differentiation workload: 200x200 Taylor-Green (40k particles),
+    +-1% velocity perturbation, 200 FP32 steps, checkpoints every 20.  The FP32
+    adjoint's directional derivatives of KE(v^N) (8 random directions) and its
+    xi derivative agree with FP64 central differences of the GPU's FP64
+    forward (itself matched to the oracle step by step) to 1e-4."""
+    import torch
+    from paper_2411_13992_amd.adjoint import rollout, kinetic_energy
+    case = cases.taylor_green_2d(200, jitter=jitter, vel_perturb=0.01, seed=1, steps=200)
+    nsteps, every = case.steps, 20
+    sim32 = _sim(case, "f32")
+    v0 = torch.tensor(case.vel, dtype=torch.float64, device="cuda", requires_grad=True)
+    xi = torch.tensor(case.xi, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = kinetic_energy(sim32, rollout(sim32, v0, xi, nsteps, every))
+    loss.backward()
+    gv = v0.grad
+    gxi = xi.grad.item()
+    sim64 = _sim(case, "f64")
+    base = torch.tensor(case.vel, dtype=torch.float64, device="cuda")
+    g = torch.Generator(device="cpu").manual_seed(9)
+    derivs, fds = [], []
+    for k in range(8):
+        u = torch.randn(base.shape, generator=g, dtype=torch.float64).cuda()
+        fds.append(central_fd(lambda e: _gpu_ke(sim64, base + e * u, case.xi, nsteps), 1e-6))
+        derivs.append(float((gv * u).sum()))
+    scale = max(abs(x) for x in fds)
+    for a, b in zip(derivs, fds):
+        assert abs(a - b) <= 1e-4 * max(abs(b), 1e-2 * scale), (a, b)
+    fd = central_fd(lambda e: _gpu_ke(sim64, base, case.xi + e, nsteps), 1e-6)
+    print(f"jitter {jitter}: dKE/dxi adjoint {gxi:.6e} fd {fd:.6e}; "
+          f"directional {derivs[0]:.6e} fd {fds[0]:.6e}")
+    assert abs(gxi - fd) <= 1e-4 * max(abs(fd), 1e-3 * scale)
