@@ -57,11 +57,14 @@ def _events_time(fn, reps):
 
 
 def time_steps(sim, steps, warmup):
+    """Seconds per step of `steps` consecutive steps (one fused run, every
+    step's diagnostics kept on the device) and the mean ordered pair count."""
     import torch
-    sim.step(warmup)
+    sim.run(warmup)
+    rows = sim.diag_rows(steps)
     torch.cuda.synchronize()
-    t = _events_time(lambda: sim.step(1), steps)
-    pairs = float(sim.diagnostics()["npairs"])
+    t = _events_time(lambda: sim.run(steps, diag=rows), 1) / steps
+    pairs = float(rows[:, 5].mean().item())
     return t, pairs
 
 

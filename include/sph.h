@@ -64,6 +64,8 @@ extern "C" {
 #define SPH_FLAG_NONFINITE  1u  /* a velocity, acceleration or density is NaN/Inf */
 #define SPH_FLAG_CFL        2u  /* a particle moved more than one cell in a step  */
 #define SPH_FLAG_OUT_OF_BOX 4u  /* an input position lies outside [0, box)        */
+#define SPH_FLAG_INTERNAL   8u  /* a bounded internal wait gave up (results of the
+                                   call are invalid; should not happen)         */
 
 /* dtype */
 #define SPH_F32 0
@@ -77,7 +79,7 @@ extern "C" {
 typedef struct {
     int32_t dim;          /* 2 or 3                                              */
     int32_t dtype;        /* SPH_F32 or SPH_F64: storage and sweep precision     */
-    int64_t n;            /* number of particles, 0 <= n < 2^31                  */
+    int64_t n;            /* number of particles, 0 <= n < 2^28                  */
     int32_t ncell[3];     /* cells per axis (>= 3); unused axes ignored          */
     int32_t tv_every;     /* apply the correction on steps with index % k == 0;
                              0 disables it                                       */
@@ -186,6 +188,18 @@ int32_t sph_tv_correction(const sph_params *p, const sph_particles *parts,
 int32_t sph_kdk_step(const sph_params *p, sph_particles *parts, int32_t *cell_start,
                      int64_t step_index, void *ws, size_t ws_bytes, void *tape,
                      double *diag, void *stream);
+
+/* nsteps consecutive kick-drift-kick steps from step index step_index, with
+ * the same arithmetic as nsteps calls of sph_kdk_step (bit-identical
+ * results), but fused across steps: the force sweep of step n also evaluates
+ * the correction sum of step n+1 at the same positions and densities (the
+ * pairs, kernel values and volumes of Eq. 14 are those of the force sum),
+ * then applies the second half kick of step n and the first half kick,
+ * correction and drift of step n+1.  diag (optional, device) receives
+ * nsteps rows of SPH_NDIAG doubles, one per step.  No tape. */
+int32_t sph_kdk_run(const sph_params *p, sph_particles *parts, int32_t *cell_start,
+                    int64_t step_index, int64_t nsteps, void *ws, size_t ws_bytes,
+                    double *diag, void *stream);
 
 /* Diagnostics of the current state alone (KE, momentum, max|v|, pairs);
  * entries 6-8 are zero. */

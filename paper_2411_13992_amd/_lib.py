@@ -27,7 +27,7 @@ DIAG_NAMES = ("ke", "px", "py", "pz", "vmax", "npairs", "nbeta", "nband", "trans
 EXPORTS = (
     "sph_workspace_size", "sph_tape_size", "sph_lattice_kappa", "sph_bin_positions",
     "sph_build_cells", "sph_density", "sph_forces", "sph_tv_correction", "sph_kdk_step",
-    "sph_diagnostics", "sph_adjoint_step", "sph_adjoint_init", "sph_neighbor_counts",
+    "sph_kdk_run", "sph_diagnostics", "sph_adjoint_step", "sph_adjoint_init", "sph_neighbor_counts",
     "sph_get_flags", "sph_clear_flags", "sph_status_string",
 )
 
@@ -88,6 +88,8 @@ def load():
         "sph_tv_correction": [pp, P(SphParticles), vp, vp, vp, vp, vp, vp],
         "sph_kdk_step": [pp, P(SphParticles), vp, ctypes.c_int64, vp, ctypes.c_size_t, vp, vp,
                          vp],
+        "sph_kdk_run": [pp, P(SphParticles), vp, ctypes.c_int64, ctypes.c_int64, vp,
+                        ctypes.c_size_t, vp, vp],
         "sph_diagnostics": [pp, P(SphParticles), vp, vp, ctypes.c_size_t, vp, vp],
         "sph_adjoint_step": [pp, vp, P(SphAdjoint), vp, vp, ctypes.c_size_t, vp],
         "sph_adjoint_init": [pp, P(SphParticles), vp, P(SphAdjoint), vp, ctypes.c_size_t, vp],

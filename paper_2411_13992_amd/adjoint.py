@@ -55,10 +55,13 @@ def forward_run(sim: Simulation, v0: torch.Tensor, xi: float, nsteps: int, every
     sim.set_velocity(v0)
     sim.init_fields()
     ckpts = []
-    for s in range(nsteps):
-        if every and s % every == 0:
+    s = 0
+    while s < nsteps:
+        chunk = min(every, nsteps - s) if every else nsteps - s
+        if every:
             ckpts.append(sim.snapshot())
-        sim.step(1, diag=False)
+        sim.run(chunk, diag=False)
+        s += chunk
     return ckpts
 
 

@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libsph.so")
 ARCH = os.environ.get("SPH_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-CFLAGS = ["-std=c++17", "-O3", f"--offload-arch={ARCH}", "-fPIC", "-Wall",
+CFLAGS = ["-std=c++17", "-O3", "-ffp-contract=off", f"--offload-arch={ARCH}", "-fPIC", "-Wall",
           "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

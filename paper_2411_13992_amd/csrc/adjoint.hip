@@ -23,22 +23,13 @@ struct PairKernel {
 template <int D, typename T, bool VAR>
 __device__ __forceinline__ bool pair_kernel(const Coeffs<T>& k, T r2, T hi, T hj,
                                             PairKernel<D, T>& pk, T& inv_r) {
-  T sup2, inv_h, fc;
-  if constexpr (VAR) {
-    const T sup = hi + hj;
-    sup2 = sup * sup;
-    inv_h = frcp(T(0.5) * sup);
-    fc = T(-5) * wendland_alpha<D>(inv_h) * inv_h * inv_h;
-  } else {
-    sup2 = k.sup2;
-    inv_h = k.inv_h;
-    fc = k.fcoef;
-  }
-  if (!(r2 < sup2)) return false;
-  inv_r = r2 > T(0) ? frsq(r2) : T(0);
-  const T t = T(1) - T(0.5) * (r2 * inv_r) * inv_h;
-  pk.F = fc * t * t * t;
-  pk.Fpr = T(-1.5) * fc * t * t * inv_h * inv_r;
+  const PairH<D, T, VAR> ph = pair_h<D, T, VAR>(k, hi, hj);
+  if (!(r2 < ph.sup2)) return false;
+  const PairGeo<T> pg = pair_geo(r2);
+  inv_r = pg.inv_r;
+  const T t = kernel_t(pg.r, ph.inv_h);
+  pk.F = ph.fc * (t * t * t);
+  pk.Fpr = T(-1.5) * ph.fc * (t * t) * ph.inv_h * pg.inv_r;
   return true;
 }
 
@@ -84,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void force_vjp_kernel(
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       r[d] = (oi[d] - off[d * n + j]) - sh[d];
-      r2 += r[d] * r[d];
+      r2 = tfma(r[d], r[d], r2);
     }
     if (j == i) return;
     PairKernel<D, T> pk;
@@ -99,8 +90,8 @@ __global__ __launch_bounds__(kBlock) void force_vjp_kernel(
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       vij[d] = vi[d] - vel[d * n + j];
-      vr += vij[d] * r[d];
-      w[d] = ai[d] - mratio * a_bar[d * n + j];
+      vr = tfma(vij[d], r[d], vr);
+      w[d] = tfma(-mratio, a_bar[d * n + j], ai[d]);
     }
     const T du = -vr * inv_r;
     const T x = k.riemann_eta * du * k.inv_c0;
@@ -115,9 +106,9 @@ __global__ __launch_bounds__(kBlock) void force_vjp_kernel(
     T Bw = T(0), rw = T(0);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      const T B = k.eta * vij[d] - pstar * r[d];
-      Bw += B * w[d];
-      rw += r[d] * w[d];
+      const T B = tfma(-pstar, r[d], k.eta * vij[d]);
+      Bw = tfma(B, w[d], Bw);
+      rw = tfma(r[d], w[d], rw);
     }
     const T vperp_coef = vr * inv_r * inv_r;   // (v_ij . r) / |r|^2
 #pragma unroll
@@ -162,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void density_vjp_kernel(
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       r[d] = (oi[d] - off[d * n + j]) - sh[d];
-      r2 += r[d] * r[d];
+      r2 = tfma(r[d], r[d], r2);
     }
     if (j == i) return;
     PairKernel<D, T> pk;
@@ -249,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void tv_vjp_kernel(
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       r[d] = (oi[d] - off[d * n + j]) - sh[d];
-      r2 += r[d] * r[d];
+      r2 = tfma(r[d], r[d], r2);
     }
     if (j == i) return;
     PairKernel<D, T> pk;

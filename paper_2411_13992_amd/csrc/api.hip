@@ -21,9 +21,9 @@ struct Sizes {
 
 // Workspace regions (byte offsets from the workspace base).
 struct WsLayout {
-  size_t flags, counts, block_sums, slot, tmp, perm;
+  size_t flags, cellbuf, slot, tmp, perm;
   size_t stg_cell, stg_id, stg_off, stg_vel, stg_acc, stg_rho, stg_mass, stg_h;
-  size_t dr, partials;
+  size_t dr, partials, partials2;
   size_t adj_r, adj_v, adj_rho, adj_g, adj_r2;
   size_t total;
 };
@@ -37,6 +37,30 @@ struct TapeLayout {
   size_t post_cell, post_off, post_vhalf, post_rho, post_mass, post_h, post_cs;
   size_t total;
 };
+
+// One region holds everything the cell build and the diagnostics fold keep
+// between launches, so a single fill zeroes it: counts[ncells], a spare word,
+// the diagnostics ticket, two scan tickets, then 8-byte look-back tile states.
+size_t cellbuf_head(int ncells) { return ((sizeof(int) * ((size_t)ncells + 4)) + 7) / 8 * 8; }
+size_t cellbuf_bytes(int ncells) { return cellbuf_head(ncells) + 8 * (size_t)scan_blocks(ncells); }
+
+struct CellBuf {
+  int* counts;
+  unsigned* counter;
+  ScanState scan;
+  long fill_ints;
+};
+
+CellBuf cellbuf_of(char* ws, size_t off, int ncells) {
+  CellBuf b;
+  int* base = (int*)(ws + off);
+  b.counts = base;
+  b.counter = (unsigned*)(base + ncells + 1);
+  b.scan.tickets = (unsigned*)(base + ncells + 2);
+  b.scan.tile_state = (unsigned long long*)((char*)base + cellbuf_head(ncells));
+  b.fill_ints = (long)(cellbuf_bytes(ncells) / sizeof(int));
+  return b;
+}
 
 struct Cursor {
   size_t o = 0;
@@ -63,8 +87,8 @@ WsLayout ws_layout(const Sizes& s) {
   WsLayout w;
   const size_t n = (size_t)s.n, dn = (size_t)s.dim * n, t = s.tsz;
   w.flags = c.take(kAlign);
-  w.counts = c.take(sizeof(int) * ((size_t)s.ncells + 1));
-  w.block_sums = c.take(sizeof(int) * ((size_t)scan_blocks(s.ncells) + 1));
+  // cell histogram, diagnostics ticket, scan tickets and look-back tile states
+  w.cellbuf = c.take(cellbuf_bytes(s.ncells));
   w.slot = c.take(sizeof(int) * n);
   w.tmp = c.take(sizeof(int) * n);
   w.perm = c.take(sizeof(int) * n);
@@ -78,6 +102,7 @@ WsLayout ws_layout(const Sizes& s) {
   w.stg_h = c.take(t * n);
   w.dr = c.take(t * dn);
   w.partials = c.take(sizeof(double) * kNumPartials * (size_t)(s.nblk > 0 ? s.nblk : 1));
+  w.partials2 = c.take(sizeof(double) * kNumPartials * (size_t)(s.nblk > 0 ? s.nblk : 1));
   w.adj_r = c.take(t * dn);
   w.adj_v = c.take(t * dn);
   w.adj_rho = c.take(t * n);
@@ -118,7 +143,9 @@ int32_t check_params(const sph_params* p) {
   if (!p) return SPH_E_ARG;
   if (p->dim != 2 && p->dim != 3) return SPH_E_UNSUPPORTED;
   if (p->dtype != SPH_F32 && p->dtype != SPH_F64) return SPH_E_UNSUPPORTED;
-  if (p->n < 0 || p->n >= (int64_t(1) << 31)) return SPH_E_ARG;
+  if (p->n < 0) return SPH_E_ARG;
+  // neighbour-list entries hold particle indices in 28 bits
+  if (p->n >= (int64_t(1) << 28)) return SPH_E_UNSUPPORTED;
   if (p->tv_every < 0) return SPH_E_ARG;
   if (p->per_particle != 0 && p->per_particle != 1) return SPH_E_ARG;
   const double vals[] = {p->rho0, p->c0, p->h_min, p->h_max, p->kappa, p->mass};
@@ -265,24 +292,30 @@ int32_t build_cells_t(const sph_params* p, sph_particles* parts, int32_t* cs, in
   const Sizes sz = sizes_of(p, var);
   const WsLayout w = ws_layout(sz);
   Launch l = launch_of(p, var, stream);
-  int* counts = (int*)(ws + w.counts);
-  launch_fill(stream, counts, sz.ncells, 0);
+  const CellBuf cb = cellbuf_of(ws, w.cellbuf, sz.ncells);
+  int* counts = cb.counts;
+  launch_fill(stream, counts, cb.fill_ints, 0);
   PArrays<T> src = arrays_of<T>(parts);
   PArrays<T> stg = staging_of<T>(ws, w, var);
   if (!src.vel) stg.vel = nullptr;
   if (!src.acc) stg.acc = nullptr;
   if (!src.rho) stg.rho = nullptr;
   launch_stage_copy<T>(l, sz.n, src, stg, counts, (int*)(ws + w.slot));
-  launch_scan(stream, sz.ncells, counts, (int*)(ws + w.block_sums), cs);
+  launch_scan(stream, sz.ncells, counts, cb.scan, 0u, cs, (unsigned*)(ws + w.flags), DiagFold{});
   launch_scatter(stream, sz.n, stg.cell, (int*)(ws + w.slot), cs, (int*)(ws + w.tmp));
   launch_rank_gather<T>(l, sz.n, (int*)(ws + w.tmp), cs, stg, src, perm);
   return hip_status();
 }
 
-// ---------------------------------------------------------------- step
+// ---------------------------------------------------------------- steps
+// nsteps kick-drift-kick steps from step index step0.  The first step
+// evaluates the correction with the standalone sweep and drifts with the
+// standalone kernel; every later step takes both from the fused force sweep of
+// the step before.  The last step finishes with the standalone kick.  Per step:
+// scan, scatter, rank + gather, density, forces (fused except the last).
 template <typename T>
-int32_t kdk_step_t(const sph_params* p, sph_particles* parts, int32_t* cs, int64_t step_index,
-                   char* ws, char* tape, double* diag, hipStream_t stream) {
+int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int64_t step0,
+                    int64_t nsteps, char* ws, char* tape, double* diag, hipStream_t stream) {
   const bool var = is_var(p);
   const Sizes sz = sizes_of(p, var);
   const WsLayout w = ws_layout(sz);
@@ -290,12 +323,17 @@ int32_t kdk_step_t(const sph_params* p, sph_particles* parts, int32_t* cs, int64
   const Coeffs<T> k = coeffs_of<T>(p, g);
   const Launch l = launch_of(p, var, stream);
   unsigned* flags = (unsigned*)(ws + w.flags);
-  double* partials = diag ? (double*)(ws + w.partials) : nullptr;
+  double* part[2] = {(double*)(ws + w.partials), (double*)(ws + w.partials2)};
   PArrays<T> a = arrays_of<T>(parts);
   PArrays<T> stg = staging_of<T>(ws, w, var);
+  const CellBuf cb = cellbuf_of(ws, w.cellbuf, sz.ncells);
+  int* counts = cb.counts;
+  int* slot = (int*)(ws + w.slot);
+  int* tmp = (int*)(ws + w.tmp);
+  int* perm = (int*)(ws + w.perm);
   const size_t n = (size_t)sz.n, dn = (size_t)sz.dim * n, t = sz.tsz;
   const size_t csb = sizeof(int) * ((size_t)sz.ncells + 1);
-  const bool apply = p->tv_every > 0 && (step_index % p->tv_every) == 0;
+  auto applies = [&](int64_t s) { return p->tv_every > 0 && (s % p->tv_every) == 0; };
   TapeLayout tl;
   if (tape) {
     tl = tape_layout(sz);
@@ -310,54 +348,71 @@ int32_t kdk_step_t(const sph_params* p, sph_particles* parts, int32_t* cs, int64
     e = e ? e : copy_d2d(tape + tl.pre_cs, cs, csb, stream);
     if (e != hipSuccess) return SPH_E_HIP;
   }
-  if (partials) launch_zero_partials(stream, sz.nblk, partials);
+  launch_fill(stream, counts, cb.fill_ints, 0);
+  if (diag) launch_zero_partials(stream, sz.nblk, part[0]);
 
-  // 1. transport-velocity correction at r^n (Eq. 14-16)
+  // first step: 1. correction at r^n (Eq. 14-16), 2. half kick + drift + rebin
   T* dr = nullptr;
-  if (apply) {
+  if (applies(step0)) {
     dr = (T*)(ws + w.dr);
     launch_tv<T>(l, g, k, a, cs, dr, tape ? (T*)(tape + tl.beta) : nullptr, nullptr,
-                 tape ? (T*)(tape + tl.g) : nullptr, partials);
+                 tape ? (T*)(tape + tl.g) : nullptr, diag ? part[0] : nullptr);
   } else if (tape) {
     // no correction this step: record g = 0, beta = 0 (the reverse then adds nothing)
     launch_zero<T>(stream, (T*)(tape + tl.g), (long)dn);
     launch_zero<T>(stream, (T*)(tape + tl.beta), (long)n);
   }
-  // 2. half kick + drift + rebin, 3. cell build
-  int* counts = (int*)(ws + w.counts);
-  int* slot = (int*)(ws + w.slot);
-  launch_fill(stream, counts, sz.ncells, 0);
   launch_drift<T>(l, g, k, a, dr, stg, counts, slot, flags);
-  launch_scan(stream, sz.ncells, counts, (int*)(ws + w.block_sums), cs);
-  launch_scatter(stream, sz.n, stg.cell, slot, cs, (int*)(ws + w.tmp));
-  PArrays<T> dst = a;
-  dst.acc = nullptr;
-  dst.rho = nullptr;
+
   PArrays<T> src = stg;
   src.acc = nullptr;
   src.rho = nullptr;
-  int* perm = (int*)(ws + w.perm);
-  launch_rank_gather<T>(l, sz.n, (int*)(ws + w.tmp), cs, src, dst, perm);
-  // 4. density summation (Eq. 8), 5-6. accelerations at (r^{n+1}, v', rho^{n+1})
-  launch_density<T>(l, g, k, a, cs, a.rho, partials, nullptr, flags);
-  launch_forces<T>(l, g, k, a, cs, a.vel, a.acc, flags);
-  if (tape) {
-    hipError_t e = hipSuccess;
-    e = e ? e : copy_d2d(tape + tl.perm, perm, sizeof(int) * n, stream);
-    e = e ? e : copy_d2d(tape + tl.post_cell, a.cell, sizeof(int) * n, stream);
-    e = e ? e : copy_d2d(tape + tl.post_off, a.off, t * dn, stream);
-    e = e ? e : copy_d2d(tape + tl.post_vhalf, a.vel, t * dn, stream);
-    e = e ? e : copy_d2d(tape + tl.post_rho, a.rho, t * n, stream);
-    if (var) {
-      e = e ? e : copy_d2d(tape + tl.post_mass, a.mass, t * n, stream);
-      e = e ? e : copy_d2d(tape + tl.post_h, a.h, t * n, stream);
+  PArrays<T> dst = a;
+  dst.acc = nullptr;
+  dst.rho = nullptr;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    double* cur = diag ? part[s & 1] : nullptr;
+    double* nxt = diag ? part[(s + 1) & 1] : nullptr;
+    // the previous step's diagnostics are folded by the scan of this step
+    DiagFold fold{};
+    if (diag && s > 0) fold = DiagFold{part[(s - 1) & 1], sz.nblk, diag + (size_t)SPH_NDIAG * (s - 1)};
+    // 3. cell build
+    launch_scan(stream, sz.ncells, counts, cb.scan, (unsigned)s, cs, flags, fold);
+    launch_scatter(stream, sz.n, stg.cell, slot, cs, tmp);
+    launch_rank_gather<T>(l, sz.n, tmp, cs, src, dst, perm);
+    // 4. density summation (Eq. 8)
+    launch_density<T>(l, g, k, a, cs, a.rho, cur, nullptr, flags);
+    if (s + 1 < nsteps) {
+      // 5-6. accelerations, 7. kick; the next step's correction and drift
+      FusedOut<T> fo;
+      fo.apply_next = applies(step0 + s + 1) ? 1 : 0;
+      fo.stg = stg;
+      fo.counts = counts;
+      fo.slot = slot;
+      fo.part_cur = cur;
+      fo.part_next = nxt;
+      launch_forces_fused<T>(l, g, k, a, cs, fo, flags);
+    } else {
+      // 5-6. accelerations at (r^{n+1}, v', rho^{n+1}), 7. second half kick
+      launch_forces<T>(l, g, k, a, cs, a.vel, a.acc, flags);
+      if (tape) {
+        hipError_t e = hipSuccess;
+        e = e ? e : copy_d2d(tape + tl.perm, perm, sizeof(int) * n, stream);
+        e = e ? e : copy_d2d(tape + tl.post_cell, a.cell, sizeof(int) * n, stream);
+        e = e ? e : copy_d2d(tape + tl.post_off, a.off, t * dn, stream);
+        e = e ? e : copy_d2d(tape + tl.post_vhalf, a.vel, t * dn, stream);
+        e = e ? e : copy_d2d(tape + tl.post_rho, a.rho, t * n, stream);
+        if (var) {
+          e = e ? e : copy_d2d(tape + tl.post_mass, a.mass, t * n, stream);
+          e = e ? e : copy_d2d(tape + tl.post_h, a.h, t * n, stream);
+        }
+        e = e ? e : copy_d2d(tape + tl.post_cs, cs, csb, stream);
+        if (e != hipSuccess) return SPH_E_HIP;
+      }
+      launch_kick<T>(l, k, sz.n, a.vel, a.acc, a.mass, cur, true, flags);
+      if (diag) launch_diag_fold(stream, DiagFold{cur, sz.nblk, diag + (size_t)SPH_NDIAG * s});
     }
-    e = e ? e : copy_d2d(tape + tl.post_cs, cs, csb, stream);
-    if (e != hipSuccess) return SPH_E_HIP;
   }
-  // 7. second half kick with FP64 diagnostics
-  launch_kick<T>(l, k, sz.n, a.vel, a.acc, a.mass, partials, true, flags);
-  if (diag) launch_diag_final(stream, sz.nblk, partials, diag);
   return hip_status();
 }
 
@@ -599,31 +654,39 @@ int32_t sph_tv_correction(const sph_params* p, const sph_particles* parts,
   });
 }
 
-int32_t sph_kdk_step(const sph_params* p, sph_particles* parts, int32_t* cell_start,
-                     int64_t step_index, void* ws, size_t ws_bytes, void* tape, double* diag,
-                     void* stream) {
+static int32_t kdk_common(const sph_params* p, sph_particles* parts, int32_t* cell_start,
+                          int64_t step_index, int64_t nsteps, void* ws, size_t ws_bytes,
+                          void* tape, double* diag, void* stream) {
   int32_t st = check_params(p);
   if (st != SPH_OK) return st;
   st = check_particles(p, parts, true);
   if (st != SPH_OK) return st;
-  if (!cell_start || !ws || step_index < 0) return SPH_E_ARG;
+  if (!cell_start || !ws || step_index < 0 || nsteps < 0) return SPH_E_ARG;
   size_t need = 0;
   sph_workspace_size(p, &need);
   if (ws_bytes < need) return SPH_E_WORKSPACE;
+  if (nsteps == 0) return SPH_OK;
   if (p->n == 0) {
-    if (diag) {
-      const WsLayout w = ws_layout(sizes_of(p, true));
-      double* partials = (double*)((char*)ws + w.partials);
-      launch_zero_partials((hipStream_t)stream, 1, partials);
-      launch_diag_final((hipStream_t)stream, 0, partials, diag);
-    }
+    if (diag) launch_zero<double>((hipStream_t)stream, diag, (long)SPH_NDIAG * nsteps);
     return hip_status();
   }
   return dispatch(p, [&](auto tag) {
     using T = decltype(tag);
-    return kdk_step_t<T>(p, parts, cell_start, step_index, (char*)ws, (char*)tape, diag,
-                         (hipStream_t)stream);
+    return run_steps_t<T>(p, parts, cell_start, step_index, nsteps, (char*)ws, (char*)tape, diag,
+                          (hipStream_t)stream);
   });
+}
+
+int32_t sph_kdk_step(const sph_params* p, sph_particles* parts, int32_t* cell_start,
+                     int64_t step_index, void* ws, size_t ws_bytes, void* tape, double* diag,
+                     void* stream) {
+  return kdk_common(p, parts, cell_start, step_index, 1, ws, ws_bytes, tape, diag, stream);
+}
+
+int32_t sph_kdk_run(const sph_params* p, sph_particles* parts, int32_t* cell_start,
+                    int64_t step_index, int64_t nsteps, void* ws, size_t ws_bytes, double* diag,
+                    void* stream) {
+  return kdk_common(p, parts, cell_start, step_index, nsteps, ws, ws_bytes, nullptr, diag, stream);
 }
 
 int32_t sph_diagnostics(const sph_params* p, const sph_particles* parts, const int32_t* cell_start,
@@ -638,26 +701,29 @@ int32_t sph_diagnostics(const sph_params* p, const sph_particles* parts, const i
   if (ws_bytes < need) return SPH_E_WORKSPACE;
   const bool var = is_var(p);
   const Sizes sz = sizes_of(p, var);
-  const WsLayout w = ws_layout(sizes_of(p, true));
-  double* partials = (double*)((char*)ws + w.partials);
+  const WsLayout w = ws_layout(sz);
   hipStream_t s = (hipStream_t)stream;
-  launch_zero_partials(s, sz.nblk, partials);
-  if (p->n > 0) {
-    if (!cell_start) return SPH_E_ARG;
-    const Grid g = grid_of(p);
-    const Launch l = launch_of(p, var, stream);
-    st = dispatch(p, [&](auto tag) {
-      using T = decltype(tag);
-      const Coeffs<T> k = coeffs_of<T>(p, g);
-      PArrays<T> a = arrays_of<T>(parts);
-      // pair count from a density sweep into the staging buffer (state untouched)
-      launch_density<T>(l, g, k, a, cell_start, (T*)((char*)ws + w.stg_rho), partials, nullptr,
-                        nullptr);
-      launch_kick<T>(l, k, sz.n, a.vel, a.acc, a.mass, partials, false, nullptr);
-      return SPH_OK;
-    });
+  if (p->n == 0) {
+    launch_zero<double>(s, diag, SPH_NDIAG);
+    return hip_status();
   }
-  launch_diag_final(s, sz.nblk, partials, diag);
+  if (!cell_start) return SPH_E_ARG;
+  double* partials = (double*)((char*)ws + w.partials);
+  launch_zero_partials(s, sz.nblk, partials);
+  const Grid g = grid_of(p);
+  const Launch l = launch_of(p, var, stream);
+  st = dispatch(p, [&](auto tag) {
+    using T = decltype(tag);
+    const Coeffs<T> k = coeffs_of<T>(p, g);
+    PArrays<T> a = arrays_of<T>(parts);
+    // pair count from a density sweep into the staging buffer (state untouched)
+    launch_density<T>(l, g, k, a, cell_start, (T*)((char*)ws + w.stg_rho), partials, nullptr,
+                      nullptr);
+    launch_kick<T>(l, k, sz.n, a.vel, a.acc, a.mass, partials, false, nullptr);
+    launch_diag_fold(s, DiagFold{partials, sz.nblk, diag});
+    return SPH_OK;
+  });
+  if (st != SPH_OK) return st;
   return hip_status();
 }
 

@@ -78,30 +78,16 @@ void launch_fill(hipStream_t s, int* p, long n, int v) {
   hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, p, n, v);
 }
 
-// ------------------------------------------------------------------ histogram
-__global__ __launch_bounds__(kBlock) void histogram_kernel(int n, const int* __restrict__ cell,
-                                                           int* __restrict__ counts,
-                                                           int* __restrict__ slot) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) slot[i] = atomicAdd(&counts[cell[i]], 1);
-}
-
-void launch_histogram(hipStream_t s, int n, const int* cell, int* counts, int* slot) {
-  if (n == 0) return;
-  hipLaunchKernelGGL(histogram_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, cell, counts,
-                     slot);
-}
-
 // ------------------------------------------------------------------ scan
-// Three passes: per-block totals, a one-block scan of the totals, then a
-// per-block exclusive scan offset by the scanned totals.
+// Exclusive scan of the cell histogram into cell_start, leaving the
+// histogram zeroed for the next build.
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kBlock * kScanItems;
 
 int scan_blocks(int ncells) { return (ncells + kScanTile - 1) / kScanTile; }
 
+template <int BLOCK>
 __device__ __forceinline__ int block_exclusive_scan(int v, int* lds, int* total) {
-  // inclusive scan within the wave
   const int lane = threadIdx.x % kWave;
   const int wave = threadIdx.x / kWave;
   int x = v;
@@ -113,7 +99,7 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* lds, int* total)
   if (lane == kWave - 1) lds[wave] = x;
   __syncthreads();
   int base = 0, tot = 0;
-  for (int w = 0; w < kBlock / kWave; ++w) {
+  for (int w = 0; w < BLOCK / kWave; ++w) {
     if (w < wave) base += lds[w];
     tot += lds[w];
   }
@@ -122,44 +108,36 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* lds, int* total)
   return base + x - v;
 }
 
-__global__ __launch_bounds__(kBlock) void scan_reduce_kernel(int ncells, const int* __restrict__ counts,
-                                                             int* __restrict__ block_sums) {
-  __shared__ int lds[kBlock / kWave];
-  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  int s = 0;
-#pragma unroll
-  for (int t = 0; t < kScanItems; ++t) s += (base + t < ncells) ? counts[base + t] : 0;
-  int total;
-  block_exclusive_scan(s, lds, &total);
-  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+// Single pass with decoupled look-back: each block scans one tile of the
+// histogram, publishes its tile total, then walks back over the tiles before
+// it, adding their totals until it meets one that already carries its
+// inclusive prefix.  Tiles are numbered in the order blocks start (an atomic
+// ticket), so every tile a block waits on belongs to a block that is already
+// running and publishes without waiting; the wait is bounded anyway (a block
+// that gives up raises SPH_FLAG_INTERNAL instead of hanging).  Tile words
+// carry the launch's epoch, so words left by earlier launches read as
+// unpublished and nothing has to be re-armed between launches: no fences.
+constexpr unsigned long long kTileAgg = 1ull << 62;
+constexpr unsigned long long kTileInc = 2ull << 62;
+constexpr unsigned long long kTileFlags = 3ull << 62;
+constexpr long kSpinLimit = 1L << 22;
+
+__device__ __forceinline__ unsigned long long tile_word(unsigned long long flag, unsigned epoch,
+                                                        unsigned value) {
+  return flag | ((unsigned long long)(epoch & 0x3fffffffu) << 32) | value;
 }
 
-__global__ __launch_bounds__(kBlock) void scan_top_kernel(int nb, int* __restrict__ block_sums) {
-  // exclusive scan of nb <= kScanTile block totals in place; block_sums[nb] = grand total
+__global__ __launch_bounds__(kBlock) void scan_lookback_kernel(
+    int ncells, int ntiles, int* __restrict__ counts, int* __restrict__ cs,
+    unsigned long long* __restrict__ tile_state, unsigned* __restrict__ tickets, unsigned epoch,
+    unsigned* __restrict__ flags, DiagFold fold) {
   __shared__ int lds[kBlock / kWave];
-  const int base = threadIdx.x * kScanItems;
-  int v[kScanItems];
-  int s = 0;
-#pragma unroll
-  for (int t = 0; t < kScanItems; ++t) {
-    v[t] = (base + t < nb) ? block_sums[base + t] : 0;
-    s += v[t];
-  }
-  int total;
-  int run = block_exclusive_scan(s, lds, &total);
-#pragma unroll
-  for (int t = 0; t < kScanItems; ++t) {
-    if (base + t < nb) block_sums[base + t] = run;
-    run += v[t];
-  }
-  if (threadIdx.x == 0) block_sums[nb] = total;
-}
-
-__global__ __launch_bounds__(kBlock) void scan_apply_kernel(int ncells, const int* __restrict__ counts,
-                                                            const int* __restrict__ block_sums,
-                                                            int* __restrict__ cs, int nb) {
-  __shared__ int lds[kBlock / kWave];
-  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  __shared__ int tile_s, prefix_s;
+  if (threadIdx.x == 0)
+    tile_s = (int)(atomicAdd(&tickets[0], 1u) - epoch * (unsigned)ntiles);
+  __syncthreads();
+  const int tile = tile_s;
+  const int base = tile * kScanTile + threadIdx.x * kScanItems;
   int v[kScanItems];
   int s = 0;
 #pragma unroll
@@ -168,21 +146,57 @@ __global__ __launch_bounds__(kBlock) void scan_apply_kernel(int ncells, const in
     s += v[t];
   }
   int total;
-  int run = block_exclusive_scan(s, lds, &total) + block_sums[blockIdx.x];
+  const int excl = block_exclusive_scan<kBlock>(s, lds, &total);
+  if (threadIdx.x == 0) {
+    const unsigned long long ep = (unsigned long long)(epoch & 0x3fffffffu) << 32;
+    unsigned prefix = 0;
+    if (tile == 0) {
+      __hip_atomic_store(&tile_state[0], tile_word(kTileInc, epoch, (unsigned)total),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_store(&tile_state[tile], tile_word(kTileAgg, epoch, (unsigned)total),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int p = tile - 1;
+      long spins = 0;
+      while (p >= 0) {
+        const unsigned long long st =
+            __hip_atomic_load(&tile_state[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long f = st & kTileFlags;
+        if (f == 0 || (st & (0x3fffffffull << 32)) != ep) {
+          if (++spins > kSpinLimit) {
+            atomicOr(flags, kFlagInternal);
+            break;
+          }
+          continue;
+        }
+        prefix += (unsigned)(st & 0xffffffffull);
+        if (f == kTileInc) break;
+        --p;
+      }
+      __hip_atomic_store(&tile_state[tile], tile_word(kTileInc, epoch, prefix + (unsigned)total),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    prefix_s = (int)prefix;
+  }
+  __syncthreads();
+  int run = prefix_s + excl;
 #pragma unroll
   for (int t = 0; t < kScanItems; ++t) {
-    if (base + t < ncells) cs[base + t] = run;
+    if (base + t < ncells) {
+      cs[base + t] = run;
+      counts[base + t] = 0;
+    }
     run += v[t];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) cs[ncells] = block_sums[nb];
+  if (tile == ntiles - 1 && threadIdx.x == 0) cs[ncells] = prefix_s + total;
+  if (fold.partials && blockIdx.x == 0) fold_diag(fold.partials, fold.nblk, fold.diag);
 }
 
-void launch_scan(hipStream_t s, int ncells, const int* counts, int* block_sums, int* cs) {
-  const int nb = scan_blocks(ncells);
-  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(kBlock), 0, s, ncells, counts, block_sums);
-  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kBlock), 0, s, nb, block_sums);
-  hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(kBlock), 0, s, ncells, counts, block_sums,
-                     cs, nb);
+void launch_scan(hipStream_t s, int ncells, int* counts, ScanState st, unsigned epoch, int* cs,
+                 unsigned* flags, DiagFold fold) {
+  const int nt = scan_blocks(ncells);
+  hipLaunchKernelGGL(scan_lookback_kernel, dim3(nt), dim3(kBlock), 0, s, ncells, nt, counts, cs,
+                     st.tile_state, st.tickets, epoch, flags, fold);
 }
 
 // ------------------------------------------------------------------ scatter

@@ -15,20 +15,24 @@ __global__ __launch_bounds__(kBlock) void stage_copy_kernel(int n, PArrays<T> sr
                                                             int* __restrict__ counts,
                                                             int* __restrict__ slot) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const int c = src.cell[i];
-  stg.cell[i] = c;
-  stg.id[i] = src.id[i];
+  const bool valid = i < n;
+  int c = 0;
+  if (valid) {
+    c = src.cell[i];
+    stg.cell[i] = c;
+    stg.id[i] = src.id[i];
 #pragma unroll
-  for (int d = 0; d < D; ++d) {
-    stg.off[d * n + i] = src.off[d * n + i];
-    if (src.vel) stg.vel[d * n + i] = src.vel[d * n + i];
-    if (src.acc) stg.acc[d * n + i] = src.acc[d * n + i];
+    for (int d = 0; d < D; ++d) {
+      stg.off[d * n + i] = src.off[d * n + i];
+      if (src.vel) stg.vel[d * n + i] = src.vel[d * n + i];
+      if (src.acc) stg.acc[d * n + i] = src.acc[d * n + i];
+    }
+    if (src.rho) stg.rho[i] = src.rho[i];
+    if (src.mass) stg.mass[i] = src.mass[i];
+    if (src.h) stg.h[i] = src.h[i];
   }
-  if (src.rho) stg.rho[i] = src.rho[i];
-  if (src.mass) stg.mass[i] = src.mass[i];
-  if (src.h) stg.h[i] = src.h[i];
-  slot[i] = atomicAdd(&counts[c], 1);
+  const int sl = wave_claim_slot(valid, c, counts);
+  if (valid) slot[i] = sl;
 }
 
 template <typename T>
@@ -44,9 +48,8 @@ void launch_stage_copy(const Launch& l, int n, const PArrays<T>& src, const PArr
 }
 
 // ------------------------------------------------------------------ kick + drift + rebin
-// v' = v + dt/2 a;  o' = o + dt v' + dr;  a particle may cross at most one
-// cell face per axis per step (else SPH_FLAG_CFL).  Offsets stay in
-// [0, L_T): a value that rounds onto a face starts the next cell at 0.
+// v' = v + dt/2 a; o' = o + dt v' + dr, rebinned (drift_rebin); the moved
+// particle goes to the staging buffers and claims a slot in its new cell.
 template <int D, typename T, bool VAR>
 __global__ __launch_bounds__(kBlock) void drift_kernel(Grid g, Coeffs<T> k, PArrays<T> p,
                                                        const T* __restrict__ dr, PArrays<T> stg,
@@ -55,52 +58,33 @@ __global__ __launch_bounds__(kBlock) void drift_kernel(Grid g, Coeffs<T> k, PArr
                                                        unsigned* __restrict__ flags) {
   const int n = g.n;
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  int c[3];
-  decode_cell<D>(g, p.cell[i], c);
-  unsigned f = 0;
+  const bool valid = i < n;
+  int lin = 0;
+  if (valid) {
+    T o[3], vh[3], dri[3] = {T(0), T(0), T(0)};
 #pragma unroll
-  for (int d = 0; d < D; ++d) {
-    const T v = p.vel[d * n + i] + k.half_dt * p.acc[d * n + i];
-    T o = p.off[d * n + i] + k.dt * v + (dr ? dr[d * n + i] : T(0));
-    if (!isfinite(v) || !isfinite(o)) {
-      f |= kFlagNonfinite;
-      o = T(0);
-    } else if (o < T(0)) {
-      const T m = (T)((double)o + g.L[d]);
-      if (m >= k.L[d]) {
-        o = T(0);                     // rounds back onto this cell's lower face
-      } else {
-        c[d] -= 1;
-        o = m;
-        if (o < T(0)) {
-          f |= kFlagCfl;
-          o = T(0);
-        }
-      }
-    } else if (o >= k.L[d]) {
-      T m = (T)((double)o - g.L[d]);
-      c[d] += 1;
-      if (m < T(0)) m = T(0);         // inside [L_T, L): next cell's lower face
-      if (m >= k.L[d]) {
-        f |= kFlagCfl;
-        m = T(0);
-      }
-      o = m;
+    for (int d = 0; d < D; ++d) {
+      vh[d] = tfma(k.half_dt, p.acc[d * n + i], p.vel[d * n + i]);
+      o[d] = p.off[d * n + i];
+      if (dr) dri[d] = dr[d * n + i];
     }
-    c[d] = wrap_index(c[d], g.nc[d]);
-    stg.off[d * n + i] = o;
-    stg.vel[d * n + i] = v;
+    unsigned f = 0;
+    lin = drift_rebin<D>(g, k, p.cell[i], o, vh, dri, f);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      stg.off[d * n + i] = o[d];
+      stg.vel[d * n + i] = vh[d];
+    }
+    stg.cell[i] = lin;
+    stg.id[i] = p.id[i];
+    if constexpr (VAR) {
+      stg.mass[i] = p.mass[i];
+      stg.h[i] = p.h[i];
+    }
+    if (f) atomicOr(flags, f);
   }
-  const int lin = c[0] + g.nc[0] * (c[1] + g.nc[1] * c[2]);
-  stg.cell[i] = lin;
-  stg.id[i] = p.id[i];
-  if constexpr (VAR) {
-    stg.mass[i] = p.mass[i];
-    stg.h[i] = p.h[i];
-  }
-  slot[i] = atomicAdd(&counts[lin], 1);
-  if (f) atomicOr(flags, f);
+  const int sl = wave_claim_slot(valid, lin, counts);
+  if (valid) slot[i] = sl;
 }
 
 template <typename T>
@@ -115,16 +99,16 @@ void launch_drift(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArr
 #undef SPH_DRIFT
 }
 
-// ------------------------------------------------------------------ kick + partials
+// ------------------------------------------------------------------ kick + diagnostics
 // v = v + dt/2 a (when `write`), then per-block FP64 partials of the kinetic
-// energy, momentum and max |v| of the resulting velocity.
+// energy, momentum and max |v| of the resulting velocity, folded into diag
+// by the last block.
 template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void kick_kernel(Coeffs<T> k, int n, T* __restrict__ vel,
                                                       const T* __restrict__ acc,
                                                       const T* __restrict__ mass,
                                                       double* __restrict__ partials, int write,
                                                       unsigned* __restrict__ flags) {
-  __shared__ double red[kBlock / kWave];
   const int i = blockIdx.x * kBlock + threadIdx.x;
   double ke = 0.0, mom[3] = {0.0, 0.0, 0.0}, vmax = 0.0;
   if (i < n) {
@@ -135,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void kick_kernel(Coeffs<T> k, int n, T* __r
     for (int d = 0; d < D; ++d) {
       T v = vel[d * n + i];
       if (write) {
-        v = v + k.half_dt * acc[d * n + i];
+        v = tfma(k.half_dt, acc[d * n + i], v);
         vel[d * n + i] = v;
       }
       bad |= !isfinite(v);
@@ -144,21 +128,15 @@ __global__ __launch_bounds__(kBlock) void kick_kernel(Coeffs<T> k, int n, T* __r
     }
     ke = 0.5 * m * v2;
     vmax = sqrt(v2);
-    if (bad) atomicOr(flags, kFlagNonfinite);
+    if (bad && flags) atomicOr(flags, kFlagNonfinite);
   }
   if (partials) {
-    double a = block_reduce<double, false>(ke, red);
-    double b = block_reduce<double, false>(mom[0], red);
-    double c = block_reduce<double, false>(mom[1], red);
-    double d = block_reduce<double, false>(mom[2], red);
-    double e = block_reduce<double, true>(vmax, red);
+    __shared__ double red5[5][kBlock / kWave];
+    double v[5] = {ke, mom[0], mom[1], mom[2], vmax};
+    block_reduce_multi<5>(v, 1u << 4, red5);
     if (threadIdx.x == 0) {
       double* o = partials + blockIdx.x * kNumPartials;
-      o[0] = a;
-      o[1] = b;
-      o[2] = c;
-      o[3] = d;
-      o[4] = e;
+      for (int q = 0; q < 5; ++q) o[q] = v[q];
     }
   }
 }
@@ -175,25 +153,15 @@ void launch_kick(const Launch& l, const Coeffs<T>& k, int n, T* vel, const T* ac
                        acc, mass, partials, write ? 1 : 0, flags);
 }
 
-// ------------------------------------------------------------------ final reduction
-// One block folds the per-block partials in a fixed order: deterministic.
-__global__ __launch_bounds__(kBlock) void diag_final_kernel(int nblk, const double* __restrict__ partials,
-                                                            double* __restrict__ diag) {
-  __shared__ double red[kBlock / kWave];
-  for (int col = 0; col < kNumPartials; ++col) {
-    const bool is_max = (col == 4 || col == 8);
-    double v = 0.0;
-    for (int r = threadIdx.x; r < nblk; r += kBlock) {
-      const double x = partials[r * kNumPartials + col];
-      v = is_max ? (x > v ? x : v) : v + x;
-    }
-    double t = is_max ? block_reduce<double, true>(v, red) : block_reduce<double, false>(v, red);
-    if (threadIdx.x == 0) diag[col] = t;
-  }
+__global__ __launch_bounds__(kBlock) void diag_fold_kernel(const double* __restrict__ partials,
+                                                           int nblk, double* __restrict__ diag) {
+  fold_diag(partials, nblk, diag);
 }
 
-void launch_diag_final(hipStream_t s, int nblk, const double* partials, double* diag) {
-  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(kBlock), 0, s, nblk, partials, diag);
+void launch_diag_fold(hipStream_t s, DiagFold fold) {
+  if (!fold.partials) return;
+  hipLaunchKernelGGL(diag_fold_kernel, dim3(1), dim3(kBlock), 0, s, fold.partials, fold.nblk,
+                     fold.diag);
 }
 
 __global__ __launch_bounds__(kBlock) void zero_double_kernel(double* __restrict__ p, long n) {

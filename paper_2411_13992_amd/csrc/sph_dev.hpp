@@ -48,6 +48,12 @@ __device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double frsq(double x) { return 1.0 / __builtin_sqrt(x); }
 
+// Fused multiply-add written out: the library is built without automatic
+// contraction, so every FMA is explicit and the same expression rounds the
+// same way in every kernel that evaluates it.
+__device__ __forceinline__ float tfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double tfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T>
 __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
 template <typename T>
@@ -63,9 +69,9 @@ __device__ __forceinline__ T wendland_alpha(T inv_h) {
 // (1 - q/2)^4 (1 + 2q): W / alpha for q < 2
 template <typename T>
 __device__ __forceinline__ T wendland_shape(T q) {
-  T t = T(1) - T(0.5) * q;
-  T t2 = t * t;
-  return t2 * t2 * (T(1) + T(2) * q);
+  const T t = tfma(q, T(-0.5), T(1));
+  const T t2 = t * t;
+  return t2 * t2 * tfma(q, T(2), T(1));
 }
 
 // ---------------------------------------------------------------- sums
@@ -115,7 +121,11 @@ __device__ __forceinline__ void decode_cell(const Grid& g, int cell, int c[3]) {
 // Calls body(j, shift) for every particle j of the 3^D cells around `cell`
 // (the particle's own cell included, so j == i is visited once).  shift[k]
 // is the offset of j's cell origin from i's cell origin: r_i - r_j =
-// (o_i - o_j) - shift.
+// (o_i - o_j) - shift.  Cells x-1, x, x+1 of a row are contiguous in the
+// sorted order unless the row wraps at the periodic x faces, so away from
+// those faces each row is one loop over [start(x-1), end(x+1)) with the x
+// shift read off the cell boundaries.  The visiting order (rows, then x,
+// then ascending j) is the same either way.
 template <int D, typename T, typename Body>
 __device__ __forceinline__ void for_each_candidate(const Grid& g, const Coeffs<T>& k, int cell,
                                                    const int* __restrict__ cs, Body&& body) {
@@ -123,23 +133,274 @@ __device__ __forceinline__ void for_each_candidate(const Grid& g, const Coeffs<T
   decode_cell<D>(g, cell, c);
   constexpr int zlo = (D == 3) ? -1 : 0;
   constexpr int zhi = (D == 3) ? 1 : 0;
+  const bool interior = c[0] >= 1 && c[0] <= g.nc[0] - 2;
 #pragma unroll
   for (int dz = zlo; dz <= zhi; ++dz) {
-    int z = (D == 3) ? wrap_index(c[2] + dz, g.nc[2]) : 0;
+    const int z = (D == 3) ? wrap_index(c[2] + dz, g.nc[2]) : 0;
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
-      int y = wrap_index(c[1] + dy, g.nc[1]);
-      int row = g.nc[0] * (y + g.nc[1] * z);
+      const int y = wrap_index(c[1] + dy, g.nc[1]);
+      const int row = g.nc[0] * (y + g.nc[1] * z);
+      const T sy = T(dy) * k.L[1];
+      const T sz = T(dz) * k.L[2];
+      if (interior) {
+        const int cc = row + c[0];
+        const int b = cs[cc - 1];
+        const int m1 = cs[cc];
+        const int m2 = cs[cc + 1];
+        const int e = cs[cc + 2];
+        for (int j = b; j < e; ++j) {
+          const T sx = j < m1 ? -k.L[0] : (j < m2 ? T(0) : k.L[0]);
+          const T shift[3] = {sx, sy, sz};
+          body(j, shift);
+        }
+      } else {
 #pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        int x = wrap_index(c[0] + dx, g.nc[0]);
-        int cc = row + x;
-        int b = cs[cc];
-        int e = cs[cc + 1];
-        T shift[3] = {T(dx) * k.L[0], T(dy) * k.L[1], T(dz) * k.L[2]};
-        for (int j = b; j < e; ++j) body(j, shift);
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int cc = row + wrap_index(c[0] + dx, g.nc[0]);
+          const int b = cs[cc];
+          const int e = cs[cc + 1];
+          const T shift[3] = {T(dx) * k.L[0], sy, sz};
+          for (int j = b; j < e; ++j) body(j, shift);
+        }
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------- pair terms
+// Per-pair kernel quantities shared by every sweep, so that the same pair
+// gives bit-identical values wherever it is evaluated.
+template <typename T>
+struct PairGeo {
+  T inv_r;   // 1/|r| (0 for coincident particles)
+  T r;       // |r|
+};
+
+template <typename T>
+__device__ __forceinline__ PairGeo<T> pair_geo(T r2) {
+  PairGeo<T> pg;
+  pg.inv_r = r2 > T(0) ? frsq(r2) : T(0);
+  pg.r = r2 * pg.inv_r;
+  return pg;
+}
+
+// Smoothing-length data of a pair: uniform h, or h_ij = (h_i + h_j)/2.
+template <int D, typename T, bool VAR>
+struct PairH {
+  T sup2;    // (2 h_ij)^2
+  T inv_h;   // 1/h_ij
+  T fc;      // -5 alpha(h_ij) / h_ij^2, so that W'(r)/r = fc (1 - q/2)^3
+};
+
+template <int D, typename T, bool VAR>
+__device__ __forceinline__ PairH<D, T, VAR> pair_h(const Coeffs<T>& k, T hi, T hj) {
+  PairH<D, T, VAR> ph;
+  if constexpr (VAR) {
+    const T sup = hi + hj;
+    ph.sup2 = sup * sup;
+    ph.inv_h = frcp(T(0.5) * sup);
+    ph.fc = T(-5) * wendland_alpha<D>(ph.inv_h) * ph.inv_h * ph.inv_h;
+  } else {
+    ph.sup2 = k.sup2;
+    ph.inv_h = k.inv_h;
+    ph.fc = k.fcoef;
+  }
+  return ph;
+}
+
+// t = 1 - q/2 for q = |r| / h
+template <typename T>
+__device__ __forceinline__ T kernel_t(T r, T inv_h) { return tfma(r * T(-0.5), inv_h, T(1)); }
+
+// Term of the transport-velocity sum g_i = sum_j V_j F_ij r_ij, as the weight
+// multiplying r_ij.  Uniform resolution leaves out the constant fcoef * m,
+// applied once per particle (tv_finish).
+template <int D, typename T, bool VAR>
+__device__ __forceinline__ T tv_weight(const PairH<D, T, VAR>& ph, T t3, T rinv_rhoj, T mj) {
+  if constexpr (VAR) return mj * rinv_rhoj * (ph.fc * t3);
+  else return t3 * rinv_rhoj;
+}
+
+template <typename T, bool VAR>
+__device__ __forceinline__ T tv_finish(const Coeffs<T>& k, T acc) {
+  return VAR ? acc : acc * (k.fcoef * k.mass);
+}
+
+// ---------------------------------------------------------------- drift
+// o' = o + dt v' + dr per axis, then rebinning: a particle may cross at most
+// one cell face per axis (else flag bit 2).  Offsets stay in [0, L_T): a
+// value that rounds onto a face starts the next cell at 0.  Returns the new
+// linear cell; `o` is updated in place.  Flag bit 1: non-finite.
+template <int D, typename T>
+__device__ __forceinline__ int drift_rebin(const Grid& g, const Coeffs<T>& k, int cell, T* o,
+                                           const T* vh, const T* dr, unsigned& f) {
+  int c[3];
+  decode_cell<D>(g, cell, c);
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    T x = tfma(k.dt, vh[d], o[d]) + dr[d];
+    if (!isfinite(vh[d]) || !isfinite(x)) {
+      f |= 1u;
+      x = T(0);
+    } else if (x < T(0)) {
+      const T m = (T)((double)x + g.L[d]);
+      if (m >= k.L[d]) {
+        x = T(0);                   // rounds back onto this cell's lower face
+      } else {
+        c[d] -= 1;
+        x = m;
+        if (x < T(0)) {
+          f |= 2u;                  // moved more than one cell
+          x = T(0);
+        }
+      }
+    } else if (x >= k.L[d]) {
+      T m = (T)((double)x - g.L[d]);
+      c[d] += 1;
+      if (m < T(0)) m = T(0);       // inside [L_T, L): next cell's lower face
+      if (m >= k.L[d]) {
+        f |= 2u;
+        m = T(0);
+      }
+      x = m;
+    }
+    c[d] = wrap_index(c[d], g.nc[d]);
+    o[d] = x;
+  }
+  return c[0] + g.nc[0] * (c[1] + g.nc[1] * c[2]);
+}
+
+// ---------------------------------------------------------------- limiter
+// Eq. 15-16 from the raw sum g (FP64 test): s = h_min^2 |g|^2,
+// beta = min(C s, 1) if s > s0 else 0, dr = xi beta h_min^2 g.
+struct Limited {
+  double s, beta;
+};
+
+template <int D, typename T>
+__device__ __forceinline__ Limited limit_correction(const Coeffs<T>& k, const T* gi, T* dr) {
+  double g2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) g2 += (double)gi[d] * (double)gi[d];
+  Limited out;
+  out.s = k.hmin2 * g2;
+  out.beta = out.s > k.lim_s0 ? fmin(k.lim_c * out.s, 1.0) : 0.0;
+  const double f = k.xi * out.beta * k.hmin2;
+#pragma unroll
+  for (int d = 0; d < D; ++d) dr[d] = (T)(f * (double)gi[d]);
+  return out;
+}
+
+// ---------------------------------------------------------------- histogram
+// Claims a slot in counts[c] for every valid lane.  Lanes are split into runs
+// of consecutive lanes with the same cell (particles arrive sorted by their
+// previous cell and move by at most one, so runs are long); the first lane of
+// each run adds the run length to the cell's counter, all runs of the wave in
+// one atomic instruction, and the run's lanes take consecutive slots.
+__device__ __forceinline__ int wave_claim_slot(bool valid, int c, int* __restrict__ counts) {
+  const int lane = threadIdx.x % kWave;
+  const int key = valid ? c : -1 - lane;             // invalid lanes form their own runs
+  const int prev = __shfl_up(key, 1, kWave);
+  const bool lead = (lane == 0) || (key != prev);
+  const unsigned long long leaders = __ballot(lead);
+  const unsigned long long upto = (lane == kWave - 1) ? ~0ull : ((2ull << lane) - 1);
+  const int start = 63 - __clzll((long long)(leaders & upto));
+  const unsigned long long after = (lane == kWave - 1) ? 0ull : (leaders >> (lane + 1));
+  const int next = after ? lane + __ffsll((long long)after) : kWave;
+  int base = 0;
+  if (lead && valid) base = atomicAdd(&counts[c], next - lane);
+  base = __shfl(base, start, kWave);
+  return base + (lane - start);
+}
+
+// ---------------------------------------------------------------- compacted walk
+// Neighbour walk in two phases for sweeps whose pair body is expensive.  The
+// scan phase tests every candidate with test(j, shift) (positions only) and
+// appends the hits to this thread's list in LDS; the body phase then runs
+// body(j, shift) over the list alone, so the wavefront executes the body once
+// per neighbour instead of once per candidate.  The list is flushed after each
+// z-plane of cells (once in 2-D) and whenever it fills.  An entry is j in
+// bits 0-27 with the cell offset code (dx + 1) + 3 (dy + 1) in bits 28-31.
+// The visiting order is that of for_each_candidate, so sums over the listed
+// pairs are bit-identical to sums over a plain walk.
+constexpr int kListBits = 28;
+constexpr unsigned kListMask = (1u << kListBits) - 1u;
+
+template <int CAP>
+struct NeighbourList {
+  unsigned slot[CAP][kBlock];   // [entry][thread]: one bank per thread
+};
+
+template <int D, typename T, int CAP, typename Test, typename Body>
+__device__ __forceinline__ void for_each_neighbour_listed(const Grid& g, const Coeffs<T>& k,
+                                                          int cell, const int* __restrict__ cs,
+                                                          NeighbourList<CAP>& nl, bool valid,
+                                                          Test&& test, Body&& body) {
+  int c[3] = {0, 0, 0};
+  if (valid) decode_cell<D>(g, cell, c);
+  const bool interior = c[0] >= 1 && c[0] <= g.nc[0] - 2;
+  const int tid = threadIdx.x;
+  constexpr int zlo = (D == 3) ? -1 : 0;
+  constexpr int zhi = (D == 3) ? 1 : 0;
+  int cnt = 0;
+#pragma unroll
+  for (int dz = zlo; dz <= zhi; ++dz) {
+    const int z = (D == 3) ? wrap_index(c[2] + dz, g.nc[2]) : 0;
+    const T sz = T(dz) * k.L[2];
+    auto flush = [&]() {
+      for (int q = 0; q < cnt; ++q) {
+        const unsigned e = nl.slot[q][tid];
+        const int code = (int)(e >> kListBits);
+        const T shift[3] = {T(code % 3 - 1) * k.L[0], T(code / 3 - 1) * k.L[1], sz};
+        body((int)(e & kListMask), shift);
+      }
+      cnt = 0;
+    };
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int y = wrap_index(c[1] + dy, g.nc[1]);
+      const int row = g.nc[0] * (y + g.nc[1] * z);
+      const T sy = T(dy) * k.L[1];
+      // three segments: cell x-1 when it wraps, the contiguous run, cell x+1
+      // when it wraps
+      int b0 = 0, e0 = 0, b1 = 0, m1 = 0, m2 = 0, e1 = 0, b2 = 0, e2 = 0;
+      if (valid) {
+        if (interior) {
+          const int cc = row + c[0];
+          b1 = cs[cc - 1];
+          m1 = cs[cc];
+          m2 = cs[cc + 1];
+          e1 = cs[cc + 2];
+        } else if (c[0] == 0) {
+          b0 = cs[row + g.nc[0] - 1];
+          e0 = cs[row + g.nc[0]];
+          b1 = cs[row];
+          m1 = b1;
+          m2 = cs[row + 1];
+          e1 = cs[row + 2];
+        } else {
+          const int cc = row + c[0];
+          b1 = cs[cc - 1];
+          m1 = cs[cc];
+          m2 = cs[cc + 1];
+          e1 = m2;
+          b2 = cs[row];
+          e2 = cs[row + 1];
+        }
+      }
+      auto visit = [&](int j, int dx) {
+        const T shift[3] = {T(dx) * k.L[0], sy, sz};
+        if (test(j, shift)) {
+          nl.slot[cnt][tid] = (unsigned)j | ((unsigned)((dx + 1) + 3 * (dy + 1)) << kListBits);
+          if (++cnt == CAP) flush();
+        }
+      };
+      for (int j = b0; j < e0; ++j) visit(j, -1);
+      for (int j = b1; j < e1; ++j) visit(j, j < m1 ? -1 : (j < m2 ? 0 : 1));
+      for (int j = b2; j < e2; ++j) visit(j, 1);
+    }
+    flush();
   }
 }
 
@@ -173,6 +434,57 @@ __device__ __forceinline__ T block_reduce(T v, T* lds /* kBlock / kWave entries 
   T r = lds[0];
   for (int w = 1; w < kBlock / kWave; ++w) r = MAX ? (r > lds[w] ? r : lds[w]) : r + lds[w];
   return r;
+}
+
+// Block-wide sums / maxima of NV values per thread at once (one LDS pass);
+// results valid in thread 0.  max_mask bit v selects a maximum for value v.
+template <int NV>
+__device__ __forceinline__ void block_reduce_multi(double* v, unsigned max_mask,
+                                                   double (*lds)[kBlock / kWave]) {
+  const int lane = threadIdx.x % kWave;
+  const int wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = ((max_mask >> q) & 1u) ? wave_max(v[q]) : wave_sum(v[q]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) lds[q][wave] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double r = lds[q][0];
+      for (int w = 1; w < kBlock / kWave; ++w)
+        r = ((max_mask >> q) & 1u) ? (r > lds[q][w] ? r : lds[q][w]) : r + lds[q][w];
+      v[q] = r;
+    }
+  }
+}
+
+// Folds per-block partials [nblk][kNumPartials] into diag (sums, except
+// columns 4 and 8 which are maxima) with one block, in a fixed order:
+// deterministic.  Must run in a later launch than the kernels that wrote the
+// partials (the launch boundary makes their writes visible).
+__device__ __forceinline__ void fold_diag(const double* __restrict__ partials, int nblk,
+                                          double* __restrict__ diag) {
+  __shared__ double red[kNumPartials][kBlock / kWave];
+  constexpr unsigned kMaxCols = (1u << 4) | (1u << 8);
+  double v[kNumPartials];
+#pragma unroll
+  for (int col = 0; col < kNumPartials; ++col) v[col] = 0.0;
+  for (int r = threadIdx.x; r < nblk; r += kBlock) {
+#pragma unroll
+    for (int col = 0; col < kNumPartials; ++col) {
+      const double x = partials[r * kNumPartials + col];
+      v[col] = ((kMaxCols >> col) & 1u) ? (x > v[col] ? x : v[col]) : v[col] + x;
+    }
+  }
+  block_reduce_multi<kNumPartials>(v, kMaxCols, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int col = 0; col < kNumPartials; ++col) diag[col] = v[col];
+  }
 }
 
 }  // namespace sph

@@ -9,6 +9,7 @@ namespace sph {
 constexpr unsigned kFlagNonfinite = 1u;
 constexpr unsigned kFlagCfl = 2u;
 constexpr unsigned kFlagOutOfBox = 4u;
+constexpr unsigned kFlagInternal = 8u;
 
 struct Launch {
   int dim;
@@ -32,6 +33,20 @@ struct PArrays {
   T* h;      // null for uniform
 };
 
+// Outputs of the fused force sweep inside a multi-step run: the next step's
+// moved particles (staging, old order = this step's order), their cell slots,
+// and the per-block diagnostic partials of this step (kinetic energy,
+// momentum, max |v|) and of the next step (limiter counts, max |dr|/dt).
+template <typename T>
+struct FusedOut {
+  int apply_next;      // correction applied at the next step
+  PArrays<T> stg;
+  int* counts;         // zeroed histogram for the next cell build
+  int* slot;
+  double* part_cur;    // null: no diagnostics
+  double* part_next;
+};
+
 // ---- sweeps (sweeps.hip)
 template <typename T>
 void launch_density(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
@@ -42,17 +57,33 @@ void launch_tv(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays
 template <typename T>
 void launch_forces(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                    const int* cs, const T* vel, T* acc_out, unsigned* flags);
+template <typename T>
+void launch_forces_fused(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
+                         const int* cs, const FusedOut<T>& fo, unsigned* flags);
 
 // ---- cells (cells.hip)
 template <typename T>
 void launch_bin(const Launch& l, const Grid& g, const Coeffs<T>& k, const double* pos,
                 int* cell, T* off, unsigned* flags);
 void launch_fill(hipStream_t s, int* p, long n, int v);
-void launch_histogram(hipStream_t s, int n, const int* cell, int* counts, int* slot);
-// exclusive scan of counts[ncells] into cs[ncells + 1]; block_sums has
-// scan_blocks(ncells) + 1 entries
+// exclusive scan of counts[ncells] into cs[ncells + 1], leaving counts zeroed
+// for the next histogram.  The look-back state (scan_blocks(ncells) tile words
+// and a ticket counter) is zeroed once; scan number k (k = 0, 1, ...) after
+// that zeroing passes epoch k.  With `fold` set, block 0 also folds a
+// previous launch's diagnostic partials into a diagnostics row.
 int scan_blocks(int ncells);
-void launch_scan(hipStream_t s, int ncells, const int* counts, int* block_sums, int* cs);
+struct ScanState {
+  unsigned long long* tile_state;
+  unsigned* tickets;
+};
+struct DiagFold {
+  const double* partials;   // null: nothing to fold
+  int nblk;
+  double* diag;
+};
+void launch_scan(hipStream_t s, int ncells, int* counts, ScanState st, unsigned epoch, int* cs,
+                 unsigned* flags, DiagFold fold);
+void launch_diag_fold(hipStream_t s, DiagFold fold);
 void launch_scatter(hipStream_t s, int n, const int* cell, const int* slot, const int* cs, int* tmp);
 // Moves staged arrays (old order) into dst arrays (new order); null pointers skip.
 template <typename T>
@@ -66,10 +97,11 @@ void launch_stage_copy(const Launch& l, int n, const PArrays<T>& src, const PArr
 template <typename T>
 void launch_drift(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                   const T* dr, const PArrays<T>& stg, int* counts, int* slot, unsigned* flags);
+// v += dt/2 a (when `write`); with partials, writes this step's kinetic
+// energy, momentum and max |v| partials (columns 0-4)
 template <typename T>
 void launch_kick(const Launch& l, const Coeffs<T>& k, int n, T* vel, const T* acc,
                  const T* mass, double* partials, bool write, unsigned* flags);
-void launch_diag_final(hipStream_t s, int nblk, const double* partials, double* diag);
 void launch_zero_partials(hipStream_t s, int nblk, double* partials);
 template <typename T>
 void launch_zero(hipStream_t s, T* p, long n);

@@ -6,6 +6,14 @@
 // cells around its own through cell_start.  Consecutive threads sit in the
 // same or adjacent cells, so their neighbour reads hit the same cache lines.
 // No floating-point atomics: every particle gathers its own sum.
+//
+// The force sweep has a fused form used inside multi-step runs: it also
+// accumulates the transport-velocity sum g at the same positions and
+// densities (the correction of the next step), applies the second half kick,
+// the next step's first half kick, correction and drift, and claims the
+// particle's cell slot for the next cell build.  Pair terms come from the
+// shared helpers in sph_dev.hpp, so the fused and standalone sweeps produce
+// bit-identical results.
 #include "sph_internal.hpp"
 
 namespace sph {
@@ -34,7 +42,7 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         T rv = (oi[d] - off[d * n + j]) - sh[d];
-        r2 += rv * rv;
+        r2 = tfma(rv, rv, r2);
       }
       if constexpr (VAR) {
         const T sup = hi + hh[j];
@@ -89,51 +97,33 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         rv[d] = (oi[d] - off[d * n + j]) - sh[d];
-        r2 += rv[d] * rv[d];
+        r2 = tfma(rv[d], rv[d], r2);
       }
-      if constexpr (VAR) {
-        const T sup = hi + hh[j];
-        if (r2 < sup * sup && j != i) {
-          const T inv = frcp(T(0.5) * sup);
-          const T t = T(1) - T(0.5) * fsqrt(r2) * inv;
-          // V_j F_ij = (m_j / rho_j) (-5 alpha_ij t^3 / h_ij^2)
-          const T w = mass[j] * frcp(rho[j]) * T(-5) * wendland_alpha<D>(inv) * inv * inv *
-                      (t * t * t);
+      if (j == i) return;
+      const PairH<D, T, VAR> ph = pair_h<D, T, VAR>(k, hi, VAR ? hh[j] : T(0));
+      if (!(r2 < ph.sup2)) return;
+      const PairGeo<T> pg = pair_geo(r2);
+      const T t = kernel_t(pg.r, ph.inv_h);
+      const T t3 = t * t * t;
+      const T w = tv_weight<D, T, VAR>(ph, t3, frcp(rho[j]), VAR ? mass[j] : k.mass);
 #pragma unroll
-          for (int d = 0; d < D; ++d) acc[d].add(w * rv[d]);
-        }
-      } else {
-        if (r2 < k.sup2 && j != i) {
-          const T t = T(1) - T(0.5) * fsqrt(r2) * k.inv_h;
-          const T w = (t * t * t) * frcp(rho[j]);
-#pragma unroll
-          for (int d = 0; d < D; ++d) acc[d].add(w * rv[d]);
-        }
-      }
+      for (int d = 0; d < D; ++d) acc[d].add(w * rv[d]);
     });
-    T gi[3];
-    double g2 = 0.0;
+    T gi[3], dri[3];
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      gi[d] = VAR ? acc[d].value() : acc[d].value() * (k.fcoef * k.mass);
-      g2 += (double)gi[d] * (double)gi[d];
-    }
-    const double s = k.hmin2 * g2;
-    double b = 0.0;
-    if (s > k.lim_s0) b = fmin(k.lim_c * s, 1.0);
-    const double f = k.xi * b * k.hmin2;
+    for (int d = 0; d < D; ++d) gi[d] = tv_finish<T, VAR>(k, acc[d].value());
+    const Limited lim = limit_correction<D>(k, gi, dri);
     double d2 = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      const T v = (T)(f * (double)gi[d]);
-      dr[d * n + i] = v;
-      d2 += (double)v * (double)v;
+      dr[d * n + i] = dri[d];
+      d2 += (double)dri[d] * (double)dri[d];
       if (g_out) g_out[d * n + i] = gi[d];
     }
-    if (beta_out) beta_out[i] = (T)b;
-    if (s_out) s_out[i] = s;
-    nbeta = b > 0.0 ? 1.0 : 0.0;
-    nband = fabs(s - k.lim_s0) <= k.band_tol * k.lim_s0 ? 1.0 : 0.0;
+    if (beta_out) beta_out[i] = (T)lim.beta;
+    if (s_out) s_out[i] = lim.s;
+    nbeta = lim.beta > 0.0 ? 1.0 : 0.0;
+    nband = fabs(lim.s - k.lim_s0) <= k.band_tol * k.lim_s0 ? 1.0 : 0.0;
     drmax = sqrt(d2) * k.inv_dt;
   }
   if (partials) {
@@ -149,80 +139,161 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
 }
 
 // ------------------------------------------------------------------ forces
+// The pair body is long, so the force sweep walks its neighbours through a
+// per-thread LDS list (for_each_neighbour_listed): positions are tested for
+// every candidate, the body runs for neighbours only.
+constexpr int kForceCap = 48;
+
 // a_i = (2 / rho_i) sum_j (m_j / rho_j) F_ij (eta v_ij - P*_ij r_ij), with
 // P* = (p_i + p_j)/2 + beta^R rhobar c0 dU / 2, dU = -(v_ij . r_ij) / r,
 // beta^R = min(eta_R max(dU / c0, 0), 1), p = c0^2 (rho - rho0).
-template <int D, typename T, bool VAR>
+template <int D, typename T, bool VAR, bool FUSED>
 __global__ __launch_bounds__(kBlock) void forces_kernel(
     Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
     const T* __restrict__ off, const T* __restrict__ vel, const T* __restrict__ rho,
-    const T* __restrict__ mass, const T* __restrict__ hh, T* __restrict__ acc_out,
-    unsigned* __restrict__ flags) {
+    const T* __restrict__ mass, const T* __restrict__ hh, const int* __restrict__ id,
+    T* __restrict__ acc_out, unsigned* __restrict__ flags, FusedOut<T> fo) {
+  __shared__ NeighbourList<kForceCap> nl;
   const int n = g.n;
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  T oi[3], vi[3];
-#pragma unroll
-  for (int d = 0; d < D; ++d) {
-    oi[d] = off[d * n + i];
-    vi[d] = vel[d * n + i];
-  }
-  const T rhoi = rho[i];
-  const T pi = k.c0sq * (rhoi - k.rho0);
-  const T hi = VAR ? hh[i] : k.h;
-  Acc<T, UseKahan<T>::value> acc[3];
-#pragma unroll
-  for (int d = 0; d < D; ++d) acc[d].init(T(0));
-  for_each_candidate<D>(g, k, cell[i], cs, [&](int j, const T* sh) {
-    T rv[3];
-    T r2 = T(0);
+  const bool valid = i < n;
+  T oi[3] = {T(0), T(0), T(0)}, vi[3] = {T(0), T(0), T(0)};
+  T ai[3] = {T(0), T(0), T(0)}, gi[3] = {T(0), T(0), T(0)};
+  int celli = 0;
+  if (valid) {
+    celli = cell[i];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      rv[d] = (oi[d] - off[d * n + j]) - sh[d];
-      r2 += rv[d] * rv[d];
+      oi[d] = off[d * n + i];
+      vi[d] = vel[d * n + i];
     }
-    T sup2, inv_h;
-    if constexpr (VAR) {
-      const T sup = hi + hh[j];
-      sup2 = sup * sup;
-      inv_h = frcp(T(0.5) * sup);
-    } else {
-      sup2 = k.sup2;
-      inv_h = k.inv_h;
+    const T rhoi = rho[i];
+    const T pi = k.c0sq * (rhoi - k.rho0);
+    const T hi = VAR ? hh[i] : k.h;
+    Acc<T, UseKahan<T>::value> acc[3], tv[3];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      acc[d].init(T(0));
+      tv[d].init(T(0));
     }
-    if (r2 < sup2 && j != i) {
-      const T inv_r = r2 > T(0) ? frsq(r2) : T(0);
-      const T t = T(1) - T(0.5) * (r2 * inv_r) * inv_h;
-      T F;
-      if constexpr (VAR) F = T(-5) * wendland_alpha<D>(inv_h) * inv_h * inv_h * (t * t * t);
-      else F = k.fcoef * (t * t * t);
+    auto test = [&](int j, const T* sh) -> bool {
+      if (j == i) return false;
+      T r2 = T(0);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const T rv = (oi[d] - off[d * n + j]) - sh[d];
+        r2 = tfma(rv, rv, r2);
+      }
+      return r2 < pair_h<D, T, VAR>(k, hi, VAR ? hh[j] : T(0)).sup2;
+    };
+    auto body = [&](int j, const T* sh) {
+      T rv[3];
+      T r2 = T(0);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        rv[d] = (oi[d] - off[d * n + j]) - sh[d];
+        r2 = tfma(rv[d], rv[d], r2);
+      }
+      const PairH<D, T, VAR> ph = pair_h<D, T, VAR>(k, hi, VAR ? hh[j] : T(0));
+      const PairGeo<T> pg = pair_geo(r2);
+      const T t = kernel_t(pg.r, ph.inv_h);
+      const T t3 = t * t * t;
+      const T F = ph.fc * t3;
       T vij[3];
       T vr = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         vij[d] = vi[d] - vel[d * n + j];
-        vr += vij[d] * rv[d];
+        vr = tfma(vij[d], rv[d], vr);
       }
-      const T du = -vr * inv_r;
+      const T du = -vr * pg.inv_r;
       const T br = tmin(k.riemann_eta * tmax(du * k.inv_c0, T(0)), T(1));
       const T rhoj = rho[j];
+      const T rinv = frcp(rhoj);
       const T pj = k.c0sq * (rhoj - k.rho0);
-      const T pstar = T(0.5) * (pi + pj) + T(0.25) * br * (rhoi + rhoj) * k.c0 * du;
+      const T pstar = tfma(T(0.25) * br * (rhoi + rhoj) * k.c0, du, T(0.5) * (pi + pj));
       const T mj = VAR ? mass[j] : k.mass;
-      const T coef = mj * F * frcp(rhoj);
+      const T coef = mj * F * rinv;
 #pragma unroll
-      for (int d = 0; d < D; ++d) acc[d].add(coef * (k.eta * vij[d] - pstar * rv[d]));
+      for (int d = 0; d < D; ++d) acc[d].add(coef * tfma(-pstar, rv[d], k.eta * vij[d]));
+      if constexpr (FUSED) {
+        const T w = tv_weight<D, T, VAR>(ph, t3, rinv, mj);
+#pragma unroll
+        for (int d = 0; d < D; ++d) tv[d].add(w * rv[d]);
+      }
+    };
+    for_each_neighbour_listed<D, T, kForceCap>(g, k, celli, cs, nl, true, test, body);
+    const T s = T(2) / rhoi;
+    bool bad = false;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      ai[d] = s * acc[d].value();
+      acc_out[d * n + i] = ai[d];
+      bad |= !isfinite(ai[d]);
+      if (FUSED) gi[d] = tv_finish<T, VAR>(k, tv[d].value());
     }
-  });
-  const T s = T(2) / rhoi;
-  bool bad = false;
-#pragma unroll
-  for (int d = 0; d < D; ++d) {
-    const T a = s * acc[d].value();
-    acc_out[d * n + i] = a;
-    bad |= !isfinite(a);
+    if (bad) atomicOr(flags, kFlagNonfinite);
   }
-  if (bad) atomicOr(flags, kFlagNonfinite);
+  if constexpr (FUSED) {
+    // second half kick of this step, then the next step's half kick, correction
+    // and drift; the moved particle goes to the staging buffers
+    double ke = 0.0, mom[3] = {0.0, 0.0, 0.0}, vmax = 0.0;
+    double nbeta = 0.0, nband = 0.0, drmax = 0.0;
+    int lin = 0;
+    if (valid) {
+      const double m = VAR ? (double)mass[i] : (double)k.mass;
+      T vh[3], dr[3] = {T(0), T(0), T(0)};
+      double v2 = 0.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const T vn = tfma(k.half_dt, ai[d], vi[d]);
+        v2 += (double)vn * (double)vn;
+        mom[d] = m * (double)vn;
+        vh[d] = tfma(k.half_dt, ai[d], vn);
+      }
+      ke = 0.5 * m * v2;
+      vmax = sqrt(v2);
+      if (fo.apply_next) {
+        const Limited lim = limit_correction<D>(k, gi, dr);
+        double d2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) d2 += (double)dr[d] * (double)dr[d];
+        nbeta = lim.beta > 0.0 ? 1.0 : 0.0;
+        nband = fabs(lim.s - k.lim_s0) <= k.band_tol * k.lim_s0 ? 1.0 : 0.0;
+        drmax = sqrt(d2) * k.inv_dt;
+      }
+      unsigned f = 0;
+      T o2[3] = {oi[0], oi[1], oi[2]};
+      lin = drift_rebin<D>(g, k, celli, o2, vh, dr, f);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        fo.stg.off[d * n + i] = o2[d];
+        fo.stg.vel[d * n + i] = vh[d];
+      }
+      fo.stg.cell[i] = lin;
+      fo.stg.id[i] = id[i];
+      if constexpr (VAR) {
+        fo.stg.mass[i] = mass[i];
+        fo.stg.h[i] = hh[i];
+      }
+      if (f) atomicOr(flags, f);
+    }
+    const int slot = wave_claim_slot(valid, lin, fo.counts);
+    if (valid) fo.slot[i] = slot;
+    if (fo.part_cur) {
+      __shared__ double red8[8][kBlock / kWave];
+      double v[8] = {ke, mom[0], mom[1], mom[2], vmax, nbeta, nband, drmax};
+      block_reduce_multi<8>(v, (1u << 4) | (1u << 7), red8);
+      if (threadIdx.x == 0) {
+        double* o = fo.part_cur + blockIdx.x * kNumPartials;
+        for (int q = 0; q < 5; ++q) o[q] = v[q];
+        double* x = fo.part_next + blockIdx.x * kNumPartials;
+        x[6] = v[5];
+        x[7] = v[6];
+        x[8] = v[7];
+      }
+    }
+  }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -257,12 +328,26 @@ void launch_forces(const Launch& l, const Grid& g, const Coeffs<T>& k, const PAr
                    const int* cs, const T* vel, T* acc_out, unsigned* flags) {
   if (g.n == 0) return;
   dim3 grid(l.nblk), block(kBlock);
+  FusedOut<T> none{};
 #define SPH_FRC(D, V)                                                                       \
-  hipLaunchKernelGGL((forces_kernel<D, T, V>), grid, block, 0, l.stream, g, k, p.cell, cs,  \
-                     p.off, vel, p.rho, p.mass, p.h, acc_out, flags)
+  hipLaunchKernelGGL((forces_kernel<D, T, V, false>), grid, block, 0, l.stream, g, k, p.cell,\
+                     cs, p.off, vel, p.rho, p.mass, p.h, p.id, acc_out, flags, none)
   if (l.dim == 2) { if (l.var) SPH_FRC(2, true); else SPH_FRC(2, false); }
   else { if (l.var) SPH_FRC(3, true); else SPH_FRC(3, false); }
 #undef SPH_FRC
+}
+
+template <typename T>
+void launch_forces_fused(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
+                         const int* cs, const FusedOut<T>& fo, unsigned* flags) {
+  if (g.n == 0) return;
+  dim3 grid(l.nblk), block(kBlock);
+#define SPH_FRCF(D, V)                                                                      \
+  hipLaunchKernelGGL((forces_kernel<D, T, V, true>), grid, block, 0, l.stream, g, k, p.cell,\
+                     cs, p.off, p.vel, p.rho, p.mass, p.h, p.id, p.acc, flags, fo)
+  if (l.dim == 2) { if (l.var) SPH_FRCF(2, true); else SPH_FRCF(2, false); }
+  else { if (l.var) SPH_FRCF(3, true); else SPH_FRCF(3, false); }
+#undef SPH_FRCF
 }
 
 #define SPH_INST(T)                                                                          \
@@ -272,7 +357,10 @@ void launch_forces(const Launch& l, const Grid& g, const Coeffs<T>& k, const PAr
   template void launch_tv<T>(const Launch&, const Grid&, const Coeffs<T>&, const PArrays<T>&,\
                              const int*, T*, T*, double*, T*, double*);                      \
   template void launch_forces<T>(const Launch&, const Grid&, const Coeffs<T>&,               \
-                                 const PArrays<T>&, const int*, const T*, T*, unsigned*);
+                                 const PArrays<T>&, const int*, const T*, T*, unsigned*);    \
+  template void launch_forces_fused<T>(const Launch&, const Grid&, const Coeffs<T>&,         \
+                                       const PArrays<T>&, const int*, const FusedOut<T>&,    \
+                                       unsigned*);
 SPH_INST(float)
 SPH_INST(double)
 #undef SPH_INST

@@ -198,6 +198,31 @@ class Simulation:
                       _vp(self.diag) if diag else None, s)
             self.step_index += 1
 
+    def run(self, nsteps: int, diag=True) -> torch.Tensor | None:
+        """nsteps steps in one fused call (sph_kdk_run).  diag: True keeps every
+        step's diagnostics (returned as an (nsteps, 9) FP64 device tensor, the
+        last row also in self.diag), False skips them, or a preallocated
+        (nsteps, 9) FP64 device tensor to fill."""
+        if nsteps <= 0:
+            return None
+        if diag is True:
+            d = torch.empty((nsteps, _lib.SPH_NDIAG), dtype=torch.float64, device=self.device)
+        elif diag is False or diag is None:
+            d = None
+        else:
+            d = diag
+        _lib.call("sph_kdk_run", ctypes.byref(self.params), ctypes.byref(self.parts()),
+                  _vp(self.cs), self.step_index, nsteps, _vp(self.ws), self.ws_bytes, _vp(d),
+                  _stream())
+        if d is not None:
+            self.diag.copy_(d[-1])
+        self.step_index += nsteps
+        return d
+
+    def diag_rows(self, nsteps: int) -> torch.Tensor:
+        """Device buffer for the per-step diagnostics of a run."""
+        return torch.empty((nsteps, _lib.SPH_NDIAG), dtype=torch.float64, device=self.device)
+
     def tape_bytes(self) -> int:
         return _lib.tape_size(self.params)
 
