@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void force_vjp_kernel(
     vb[d].init(T(0));
   }
   pb.init(T(0));
-  for_each_candidate<D>(g, k, cell[i], cs, [&](int j, const T* sh) {
+  for_each_candidate<D, 1>(g, k, cell[i], cs, 0, [&](int j, const T* sh) {
     T r[3];
     T r2 = T(0);
 #pragma unroll
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kBlock) void density_vjp_kernel(
   Acc<T, UseKahan<T>::value> acc[3];
 #pragma unroll
   for (int d = 0; d < D; ++d) acc[d].init(T(0));
-  for_each_candidate<D>(g, k, cell[i], cs, [&](int j, const T* sh) {
+  for_each_candidate<D, 1>(g, k, cell[i], cs, 0, [&](int j, const T* sh) {
     T r[3];
     T r2 = T(0);
 #pragma unroll
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void tv_vjp_kernel(
 #pragma unroll
   for (int d = 0; d < D; ++d) acc[d].init(T(0));
   pb.init(T(0));
-  for_each_candidate<D>(g, k, cell[i], cs, [&](int j, const T* sh) {
+  for_each_candidate<D, 1>(g, k, cell[i], cs, 0, [&](int j, const T* sh) {
     T r[3];
     T r2 = T(0);
 #pragma unroll

@@ -60,10 +60,10 @@ void launch_bin(const Launch& l, const Grid& g, const Coeffs<T>& k, const double
                 int* cell, T* off, unsigned* flags) {
   if (g.n == 0) return;
   if (l.dim == 2)
-    hipLaunchKernelGGL((bin_kernel<2, T>), dim3(l.nblk), dim3(kBlock), 0, l.stream, g, k, pos,
+    hipLaunchKernelGGL((bin_kernel<2, T>), dim3(blocks_for(g.n)), dim3(kBlock), 0, l.stream, g, k, pos,
                        cell, off, flags);
   else
-    hipLaunchKernelGGL((bin_kernel<3, T>), dim3(l.nblk), dim3(kBlock), 0, l.stream, g, k, pos,
+    hipLaunchKernelGGL((bin_kernel<3, T>), dim3(blocks_for(g.n)), dim3(kBlock), 0, l.stream, g, k, pos,
                        cell, off, flags);
 }
 

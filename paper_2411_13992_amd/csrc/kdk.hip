@@ -92,7 +92,7 @@ void launch_drift(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArr
                   const T* dr, const PArrays<T>& stg, int* counts, int* slot, unsigned* flags) {
   if (g.n == 0) return;
 #define SPH_DRIFT(D, V)                                                                        \
-  hipLaunchKernelGGL((drift_kernel<D, T, V>), dim3(l.nblk), dim3(kBlock), 0, l.stream, g, k, p, \
+  hipLaunchKernelGGL((drift_kernel<D, T, V>), dim3(blocks_for(g.n)), dim3(kBlock), 0, l.stream, g, k, p, \
                      dr, stg, counts, slot, flags)
   if (l.dim == 2) { if (l.var) SPH_DRIFT(2, true); else SPH_DRIFT(2, false); }
   else { if (l.var) SPH_DRIFT(3, true); else SPH_DRIFT(3, false); }
@@ -108,10 +108,12 @@ __global__ __launch_bounds__(kBlock) void kick_kernel(Coeffs<T> k, int n, T* __r
                                                       const T* __restrict__ acc,
                                                       const T* __restrict__ mass,
                                                       double* __restrict__ partials, int write,
-                                                      unsigned* __restrict__ flags) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+                                                      int G, unsigned* __restrict__ flags) {
+  // same particle-to-block mapping as the sweeps (G lanes per particle, the
+  // first does the work), so per-block partials fold in the same order
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   double ke = 0.0, mom[3] = {0.0, 0.0, 0.0}, vmax = 0.0;
-  if (i < n) {
+  if (i < n && threadIdx.x % G == 0) {
     const double m = mass ? (double)mass[i] : (double)k.mass;
     double v2 = 0.0;
     bool bad = false;
@@ -147,10 +149,10 @@ void launch_kick(const Launch& l, const Coeffs<T>& k, int n, T* vel, const T* ac
   if (n == 0) return;
   if (l.dim == 2)
     hipLaunchKernelGGL((kick_kernel<2, T>), dim3(l.nblk), dim3(kBlock), 0, l.stream, k, n, vel,
-                       acc, mass, partials, write ? 1 : 0, flags);
+                       acc, mass, partials, write ? 1 : 0, l.G, flags);
   else
     hipLaunchKernelGGL((kick_kernel<3, T>), dim3(l.nblk), dim3(kBlock), 0, l.stream, k, n, vel,
-                       acc, mass, partials, write ? 1 : 0, flags);
+                       acc, mass, partials, write ? 1 : 0, l.G, flags);
 }
 
 __global__ __launch_bounds__(kBlock) void diag_fold_kernel(const double* __restrict__ partials,

@@ -118,22 +118,20 @@ __device__ __forceinline__ void decode_cell(const Grid& g, int cell, int c[3]) {
   }
 }
 
-// Calls body(j, shift) for every particle j of the 3^D cells around `cell`
-// (the particle's own cell included, so j == i is visited once).  shift[k]
+// Calls body(j, shift) for the particles j of the 3^D cells around `cell`
+// (the particle's own cell included, so j == i is visited).  A particle may be
+// served by a group of G consecutive lanes: lane `sub` of the group takes
+// every G-th particle of each cell, starting at the cell's sub-th.  shift[k]
 // is the offset of j's cell origin from i's cell origin: r_i - r_j =
-// (o_i - o_j) - shift.  Cells x-1, x, x+1 of a row are contiguous in the
-// sorted order unless the row wraps at the periodic x faces, so away from
-// those faces each row is one loop over [start(x-1), end(x+1)) with the x
-// shift read off the cell boundaries.  The visiting order (rows, then x,
-// then ascending j) is the same either way.
-template <int D, typename T, typename Body>
+// (o_i - o_j) - shift.  Order: z, then y, then x rows of cells, ascending j.
+template <int D, int G, typename T, typename Body>
 __device__ __forceinline__ void for_each_candidate(const Grid& g, const Coeffs<T>& k, int cell,
-                                                   const int* __restrict__ cs, Body&& body) {
+                                                   const int* __restrict__ cs, int sub,
+                                                   Body&& body) {
   int c[3];
   decode_cell<D>(g, cell, c);
   constexpr int zlo = (D == 3) ? -1 : 0;
   constexpr int zhi = (D == 3) ? 1 : 0;
-  const bool interior = c[0] >= 1 && c[0] <= g.nc[0] - 2;
 #pragma unroll
   for (int dz = zlo; dz <= zhi; ++dz) {
     const int z = (D == 3) ? wrap_index(c[2] + dz, g.nc[2]) : 0;
@@ -141,30 +139,45 @@ __device__ __forceinline__ void for_each_candidate(const Grid& g, const Coeffs<T
     for (int dy = -1; dy <= 1; ++dy) {
       const int y = wrap_index(c[1] + dy, g.nc[1]);
       const int row = g.nc[0] * (y + g.nc[1] * z);
-      const T sy = T(dy) * k.L[1];
-      const T sz = T(dz) * k.L[2];
-      if (interior) {
-        const int cc = row + c[0];
-        const int b = cs[cc - 1];
-        const int m1 = cs[cc];
-        const int m2 = cs[cc + 1];
-        const int e = cs[cc + 2];
-        for (int j = b; j < e; ++j) {
-          const T sx = j < m1 ? -k.L[0] : (j < m2 ? T(0) : k.L[0]);
-          const T shift[3] = {sx, sy, sz};
-          body(j, shift);
-        }
-      } else {
 #pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int cc = row + wrap_index(c[0] + dx, g.nc[0]);
-          const int b = cs[cc];
-          const int e = cs[cc + 1];
-          const T shift[3] = {T(dx) * k.L[0], sy, sz};
-          for (int j = b; j < e; ++j) body(j, shift);
-        }
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int cc = row + wrap_index(c[0] + dx, g.nc[0]);
+        const int b = cs[cc];
+        const int e = cs[cc + 1];
+        const T shift[3] = {T(dx) * k.L[0], T(dy) * k.L[1], T(dz) * k.L[2]};
+        for (int j = b + sub; j < e; j += G) body(j, shift);
       }
     }
+  }
+}
+
+// Combines the partial sums of a lane group (G consecutive lanes) in a fixed
+// order, compensated when the accumulator is: the result is the same in every
+// lane of the group and does not depend on timing.
+template <int G, typename T, bool COMP>
+__device__ __forceinline__ T group_sum(const Acc<T, COMP>& a) {
+  const T v = a.value();
+  if constexpr (G == 1) {
+    return v;
+  } else {
+    const int lane = threadIdx.x % kWave;
+    const int base = lane - lane % G;
+    Acc<T, COMP> tot;
+    tot.init(__shfl(v, base, kWave));
+#pragma unroll
+    for (int q = 1; q < G; ++q) tot.add(__shfl(v, base + q, kWave));
+    return tot.value();
+  }
+}
+
+template <int G>
+__device__ __forceinline__ int group_sum_int(int v) {
+  if constexpr (G == 1) {
+    return v;
+  } else {
+#pragma unroll
+    for (int m = G / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, kWave);
+    return v;
   }
 }
 
@@ -332,14 +345,13 @@ struct NeighbourList {
   unsigned slot[CAP][kBlock];   // [entry][thread]: one bank per thread
 };
 
-template <int D, typename T, int CAP, typename Test, typename Body>
+template <int D, int G, typename T, int CAP, typename Test, typename Body>
 __device__ __forceinline__ void for_each_neighbour_listed(const Grid& g, const Coeffs<T>& k,
                                                           int cell, const int* __restrict__ cs,
-                                                          NeighbourList<CAP>& nl, bool valid,
+                                                          int sub, NeighbourList<CAP>& nl,
                                                           Test&& test, Body&& body) {
-  int c[3] = {0, 0, 0};
-  if (valid) decode_cell<D>(g, cell, c);
-  const bool interior = c[0] >= 1 && c[0] <= g.nc[0] - 2;
+  int c[3];
+  decode_cell<D>(g, cell, c);
   const int tid = threadIdx.x;
   constexpr int zlo = (D == 3) ? -1 : 0;
   constexpr int zhi = (D == 3) ? 1 : 0;
@@ -361,44 +373,20 @@ __device__ __forceinline__ void for_each_neighbour_listed(const Grid& g, const C
     for (int dy = -1; dy <= 1; ++dy) {
       const int y = wrap_index(c[1] + dy, g.nc[1]);
       const int row = g.nc[0] * (y + g.nc[1] * z);
-      const T sy = T(dy) * k.L[1];
-      // three segments: cell x-1 when it wraps, the contiguous run, cell x+1
-      // when it wraps
-      int b0 = 0, e0 = 0, b1 = 0, m1 = 0, m2 = 0, e1 = 0, b2 = 0, e2 = 0;
-      if (valid) {
-        if (interior) {
-          const int cc = row + c[0];
-          b1 = cs[cc - 1];
-          m1 = cs[cc];
-          m2 = cs[cc + 1];
-          e1 = cs[cc + 2];
-        } else if (c[0] == 0) {
-          b0 = cs[row + g.nc[0] - 1];
-          e0 = cs[row + g.nc[0]];
-          b1 = cs[row];
-          m1 = b1;
-          m2 = cs[row + 1];
-          e1 = cs[row + 2];
-        } else {
-          const int cc = row + c[0];
-          b1 = cs[cc - 1];
-          m1 = cs[cc];
-          m2 = cs[cc + 1];
-          e1 = m2;
-          b2 = cs[row];
-          e2 = cs[row + 1];
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int cc = row + wrap_index(c[0] + dx, g.nc[0]);
+        const int b = cs[cc];
+        const int e = cs[cc + 1];
+        const T shift[3] = {T(dx) * k.L[0], T(dy) * k.L[1], sz};
+        const unsigned code = (unsigned)((dx + 1) + 3 * (dy + 1)) << kListBits;
+        for (int j = b + sub; j < e; j += G) {
+          if (test(j, shift)) {
+            nl.slot[cnt][tid] = (unsigned)j | code;
+            if (++cnt == CAP) flush();
+          }
         }
       }
-      auto visit = [&](int j, int dx) {
-        const T shift[3] = {T(dx) * k.L[0], sy, sz};
-        if (test(j, shift)) {
-          nl.slot[cnt][tid] = (unsigned)j | ((unsigned)((dx + 1) + 3 * (dy + 1)) << kListBits);
-          if (++cnt == CAP) flush();
-        }
-      };
-      for (int j = b0; j < e0; ++j) visit(j, -1);
-      for (int j = b1; j < e1; ++j) visit(j, j < m1 ? -1 : (j < m2 ? 0 : 1));
-      for (int j = b2; j < e2; ++j) visit(j, 1);
     }
     flush();
   }

@@ -15,8 +15,15 @@ struct Launch {
   int dim;
   bool var;            // per-particle mass and h present
   hipStream_t stream;
-  int nblk;            // particle blocks: ceil(n / kBlock)
+  int G;               // lanes per particle in the neighbour sweeps (1 or 4)
+  int nblk;            // blocks of the sweeps and of every kernel writing
+                       // diagnostic partials: ceil(n * G / kBlock)
 };
+
+// Lanes per particle for the neighbour sweeps: small systems leave most of the
+// GPU idle with one lane per particle, so a group of 4 lanes shares each
+// particle's candidates (more wavefronts in flight to hide memory latency).
+inline int lanes_per_particle(long n) { return n < 400000 ? 4 : 1; }
 
 inline int blocks_for(long n) { return (int)((n + kBlock - 1) / kBlock); }
 

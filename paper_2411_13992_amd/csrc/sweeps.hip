@@ -19,7 +19,7 @@
 namespace sph {
 
 // ------------------------------------------------------------------ density
-template <int D, typename T, bool VAR>
+template <int D, typename T, bool VAR, int G>
 __global__ __launch_bounds__(kBlock) void density_kernel(
     Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
     const T* __restrict__ off, const T* __restrict__ mass, const T* __restrict__ hh,
@@ -27,17 +27,22 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
     unsigned* __restrict__ flags) {
   __shared__ double red[kBlock / kWave];
   const int n = g.n;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
+  const int sub = threadIdx.x % G;
+  const bool valid = i < n;
   int cnt = 0;
-  if (i < n) {
+  Acc<T, UseKahan<T>::value> acc;
+  acc.init(T(0));
+  if (valid) {
     T oi[3];
 #pragma unroll
     for (int d = 0; d < D; ++d) oi[d] = off[d * n + i];
     const T hi = VAR ? hh[i] : k.h;
-    Acc<T, UseKahan<T>::value> acc;
-    if constexpr (VAR) acc.init(mass[i] * wendland_alpha<D>(frcp(hi)));
-    else acc.init(T(1));
-    for_each_candidate<D>(g, k, cell[i], cs, [&](int j, const T* sh) {
+    if (sub == 0) {
+      if constexpr (VAR) acc.init(mass[i] * wendland_alpha<D>(frcp(hi)));
+      else acc.init(T(1));
+    }
+    for_each_candidate<D, G>(g, k, cell[i], cs, sub, [&](int j, const T* sh) {
       T r2 = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
@@ -58,14 +63,19 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
         }
       }
     });
+  }
+  const T sum = group_sum<G>(acc);
+  cnt = group_sum_int<G>(cnt);
+  const bool lead = valid && sub == 0;
+  if (lead) {
     // uniform: rho = m alpha (1 + sum shape) / kappa
-    const T r = VAR ? acc.value() * k.inv_kappa : acc.value() * (k.mass * k.alpha * k.inv_kappa);
+    const T r = VAR ? sum * k.inv_kappa : sum * (k.mass * k.alpha * k.inv_kappa);
     rho[i] = r;
     if (counts) counts[i] = cnt;
-    if (!isfinite(r)) atomicOr(flags, kFlagNonfinite);
+    if (!isfinite(r) && flags) atomicOr(flags, kFlagNonfinite);
   }
   if (partials) {
-    double tot = block_reduce<double, false>((double)cnt, red);
+    double tot = block_reduce<double, false>(lead ? (double)cnt : 0.0, red);
     if (threadIdx.x == 0) partials[blockIdx.x * kNumPartials + 5] = tot;
   }
 }
@@ -73,25 +83,26 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
 // ------------------------------------------------------------------ transport velocity
 // g_i = sum_j V_j F_ij r_ij (V_j = m_j / rho_j); s_i = h_min^2 |g_i|^2 tested in
 // FP64; beta_i = min(C s_i, 1) if s_i > s0 else 0; dr_i = xi beta_i h_min^2 g_i.
-template <int D, typename T, bool VAR>
+template <int D, typename T, bool VAR, int G>
 __global__ __launch_bounds__(kBlock) void tv_kernel(
     Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
     const T* __restrict__ off, const T* __restrict__ rho, const T* __restrict__ mass,
     const T* __restrict__ hh, T* __restrict__ dr, T* __restrict__ beta_out,
     double* __restrict__ s_out, T* __restrict__ g_out, double* __restrict__ partials) {
-  __shared__ double red[kBlock / kWave];
+  __shared__ double red[3][kBlock / kWave];
   const int n = g.n;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  double nbeta = 0.0, nband = 0.0, drmax = 0.0;
-  if (i < n) {
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
+  const int sub = threadIdx.x % G;
+  const bool valid = i < n;
+  Acc<T, UseKahan<T>::value> acc[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) acc[d].init(T(0));
+  if (valid) {
     T oi[3];
 #pragma unroll
     for (int d = 0; d < D; ++d) oi[d] = off[d * n + i];
     const T hi = VAR ? hh[i] : k.h;
-    Acc<T, UseKahan<T>::value> acc[3];
-#pragma unroll
-    for (int d = 0; d < D; ++d) acc[d].init(T(0));
-    for_each_candidate<D>(g, k, cell[i], cs, [&](int j, const T* sh) {
+    for_each_candidate<D, G>(g, k, cell[i], cs, sub, [&](int j, const T* sh) {
       T rv[3];
       T r2 = T(0);
 #pragma unroll
@@ -109,9 +120,12 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
 #pragma unroll
       for (int d = 0; d < D; ++d) acc[d].add(w * rv[d]);
     });
-    T gi[3], dri[3];
+  }
+  T gi[3], dri[3];
 #pragma unroll
-    for (int d = 0; d < D; ++d) gi[d] = tv_finish<T, VAR>(k, acc[d].value());
+  for (int d = 0; d < D; ++d) gi[d] = tv_finish<T, VAR>(k, group_sum<G>(acc[d]));
+  double v[3] = {0.0, 0.0, 0.0};   // beta > 0, in band, |dr| / dt
+  if (valid && sub == 0) {
     const Limited lim = limit_correction<D>(k, gi, dri);
     double d2 = 0.0;
 #pragma unroll
@@ -122,44 +136,52 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
     }
     if (beta_out) beta_out[i] = (T)lim.beta;
     if (s_out) s_out[i] = lim.s;
-    nbeta = lim.beta > 0.0 ? 1.0 : 0.0;
-    nband = fabs(lim.s - k.lim_s0) <= k.band_tol * k.lim_s0 ? 1.0 : 0.0;
-    drmax = sqrt(d2) * k.inv_dt;
+    v[0] = lim.beta > 0.0 ? 1.0 : 0.0;
+    v[1] = fabs(lim.s - k.lim_s0) <= k.band_tol * k.lim_s0 ? 1.0 : 0.0;
+    v[2] = sqrt(d2) * k.inv_dt;
   }
   if (partials) {
-    double a = block_reduce<double, false>(nbeta, red);
-    double b = block_reduce<double, false>(nband, red);
-    double c = block_reduce<double, true>(drmax, red);
+    block_reduce_multi<3>(v, 1u << 2, red);
     if (threadIdx.x == 0) {
-      partials[blockIdx.x * kNumPartials + 6] = a;
-      partials[blockIdx.x * kNumPartials + 7] = b;
-      partials[blockIdx.x * kNumPartials + 8] = c;
+      partials[blockIdx.x * kNumPartials + 6] = v[0];
+      partials[blockIdx.x * kNumPartials + 7] = v[1];
+      partials[blockIdx.x * kNumPartials + 8] = v[2];
     }
   }
 }
 
 // ------------------------------------------------------------------ forces
-// The pair body is long, so the force sweep walks its neighbours through a
-// per-thread LDS list (for_each_neighbour_listed): positions are tested for
-// every candidate, the body runs for neighbours only.
-constexpr int kForceCap = 48;
-
 // a_i = (2 / rho_i) sum_j (m_j / rho_j) F_ij (eta v_ij - P*_ij r_ij), with
 // P* = (p_i + p_j)/2 + beta^R rhobar c0 dU / 2, dU = -(v_ij . r_ij) / r,
 // beta^R = min(eta_R max(dU / c0, 0), 1), p = c0^2 (rho - rho0).
-template <int D, typename T, bool VAR, bool FUSED>
-__global__ __launch_bounds__(kBlock) void forces_kernel(
-    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+// The pair body is long, so the sweep walks its neighbours through a
+// per-thread LDS list (for_each_neighbour_listed): positions are tested for
+// every candidate, the body runs for neighbours only.
+template <int G>
+struct ForceCap { static constexpr int value = G == 1 ? 48 : 16; };
+
+template <int D, typename T, bool VAR, bool FUSED, int G>
+__device__ __forceinline__ void forces_impl(
+    const Grid& g, const Coeffs<T>& k, const int* __restrict__ cell, const int* __restrict__ cs,
     const T* __restrict__ off, const T* __restrict__ vel, const T* __restrict__ rho,
     const T* __restrict__ mass, const T* __restrict__ hh, const int* __restrict__ id,
-    T* __restrict__ acc_out, unsigned* __restrict__ flags, FusedOut<T> fo) {
-  __shared__ NeighbourList<kForceCap> nl;
+    T* __restrict__ acc_out, unsigned* __restrict__ flags, const FusedOut<T>& fo) {
+  __shared__ NeighbourList<ForceCap<G>::value> nl;
   const int n = g.n;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
+  const int sub = threadIdx.x % G;
   const bool valid = i < n;
+  const bool lead = valid && sub == 0;
   T oi[3] = {T(0), T(0), T(0)}, vi[3] = {T(0), T(0), T(0)};
   T ai[3] = {T(0), T(0), T(0)}, gi[3] = {T(0), T(0), T(0)};
   int celli = 0;
+  T rhoi = T(1);
+  Acc<T, UseKahan<T>::value> acc[3], tv[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    acc[d].init(T(0));
+    tv[d].init(T(0));
+  }
   if (valid) {
     celli = cell[i];
 #pragma unroll
@@ -167,15 +189,9 @@ __global__ __launch_bounds__(kBlock) void forces_kernel(
       oi[d] = off[d * n + i];
       vi[d] = vel[d * n + i];
     }
-    const T rhoi = rho[i];
+    rhoi = rho[i];
     const T pi = k.c0sq * (rhoi - k.rho0);
     const T hi = VAR ? hh[i] : k.h;
-    Acc<T, UseKahan<T>::value> acc[3], tv[3];
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      acc[d].init(T(0));
-      tv[d].init(T(0));
-    }
     auto test = [&](int j, const T* sh) -> bool {
       if (j == i) return false;
       T r2 = T(0);
@@ -222,25 +238,27 @@ __global__ __launch_bounds__(kBlock) void forces_kernel(
         for (int d = 0; d < D; ++d) tv[d].add(w * rv[d]);
       }
     };
-    for_each_neighbour_listed<D, T, kForceCap>(g, k, celli, cs, nl, true, test, body);
-    const T s = T(2) / rhoi;
-    bool bad = false;
+    for_each_neighbour_listed<D, G, T, ForceCap<G>::value>(g, k, celli, cs, sub, nl, test, body);
+  }
+  const T s = T(2) / rhoi;
+  bool bad = false;
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      ai[d] = s * acc[d].value();
-      acc_out[d * n + i] = ai[d];
-      bad |= !isfinite(ai[d]);
-      if (FUSED) gi[d] = tv_finish<T, VAR>(k, tv[d].value());
-    }
+  for (int d = 0; d < D; ++d) {
+    ai[d] = s * group_sum<G>(acc[d]);
+    bad |= !isfinite(ai[d]);
+    if (FUSED) gi[d] = tv_finish<T, VAR>(k, group_sum<G>(tv[d]));
+  }
+  if (lead) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) acc_out[d * n + i] = ai[d];
     if (bad) atomicOr(flags, kFlagNonfinite);
   }
   if constexpr (FUSED) {
     // second half kick of this step, then the next step's half kick, correction
     // and drift; the moved particle goes to the staging buffers
-    double ke = 0.0, mom[3] = {0.0, 0.0, 0.0}, vmax = 0.0;
-    double nbeta = 0.0, nband = 0.0, drmax = 0.0;
+    double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // ke, mom x3, vmax, nbeta, nband, drmax
     int lin = 0;
-    if (valid) {
+    if (lead) {
       const double m = VAR ? (double)mass[i] : (double)k.mass;
       T vh[3], dr[3] = {T(0), T(0), T(0)};
       double v2 = 0.0;
@@ -248,19 +266,19 @@ __global__ __launch_bounds__(kBlock) void forces_kernel(
       for (int d = 0; d < D; ++d) {
         const T vn = tfma(k.half_dt, ai[d], vi[d]);
         v2 += (double)vn * (double)vn;
-        mom[d] = m * (double)vn;
+        v[1 + d] = m * (double)vn;
         vh[d] = tfma(k.half_dt, ai[d], vn);
       }
-      ke = 0.5 * m * v2;
-      vmax = sqrt(v2);
+      v[0] = 0.5 * m * v2;
+      v[4] = sqrt(v2);
       if (fo.apply_next) {
         const Limited lim = limit_correction<D>(k, gi, dr);
         double d2 = 0.0;
 #pragma unroll
         for (int d = 0; d < D; ++d) d2 += (double)dr[d] * (double)dr[d];
-        nbeta = lim.beta > 0.0 ? 1.0 : 0.0;
-        nband = fabs(lim.s - k.lim_s0) <= k.band_tol * k.lim_s0 ? 1.0 : 0.0;
-        drmax = sqrt(d2) * k.inv_dt;
+        v[5] = lim.beta > 0.0 ? 1.0 : 0.0;
+        v[6] = fabs(lim.s - k.lim_s0) <= k.band_tol * k.lim_s0 ? 1.0 : 0.0;
+        v[7] = sqrt(d2) * k.inv_dt;
       }
       unsigned f = 0;
       T o2[3] = {oi[0], oi[1], oi[2]};
@@ -278,11 +296,10 @@ __global__ __launch_bounds__(kBlock) void forces_kernel(
       }
       if (f) atomicOr(flags, f);
     }
-    const int slot = wave_claim_slot(valid, lin, fo.counts);
-    if (valid) fo.slot[i] = slot;
+    const int slot = wave_claim_slot(lead, lin, fo.counts);
+    if (lead) fo.slot[i] = slot;
     if (fo.part_cur) {
       __shared__ double red8[8][kBlock / kWave];
-      double v[8] = {ke, mom[0], mom[1], mom[2], vmax, nbeta, nband, drmax};
       block_reduce_multi<8>(v, (1u << 4) | (1u << 7), red8);
       if (threadIdx.x == 0) {
         double* o = fo.part_cur + blockIdx.x * kNumPartials;
@@ -296,58 +313,82 @@ __global__ __launch_bounds__(kBlock) void forces_kernel(
   }
 }
 
+template <int D, typename T, bool VAR, int G>
+__global__ __launch_bounds__(kBlock) void forces_kernel(
+    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+    const T* __restrict__ off, const T* __restrict__ vel, const T* __restrict__ rho,
+    const T* __restrict__ mass, const T* __restrict__ hh, const int* __restrict__ id,
+    T* __restrict__ acc_out, unsigned* __restrict__ flags, FusedOut<T> fo) {
+  forces_impl<D, T, VAR, false, G>(g, k, cell, cs, off, vel, rho, mass, hh, id, acc_out, flags,
+                                   fo);
+}
+
+template <int D, typename T, bool VAR, int G>
+__global__ __launch_bounds__(kBlock) void forces_fused_kernel(
+    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+    const T* __restrict__ off, const T* __restrict__ vel, const T* __restrict__ rho,
+    const T* __restrict__ mass, const T* __restrict__ hh, const int* __restrict__ id,
+    T* __restrict__ acc_out, unsigned* __restrict__ flags, FusedOut<T> fo) {
+  forces_impl<D, T, VAR, true, G>(g, k, cell, cs, off, vel, rho, mass, hh, id, acc_out, flags,
+                                  fo);
+}
+
 // ------------------------------------------------------------------ launchers
+// Sweeps run on a grid of n * G threads (G lanes per particle).
+#define SPH_SWEEP(KERNEL, ARGS)                                                               \
+  do {                                                                                        \
+    const dim3 grid_(l.nblk), block_(kBlock);                                                 \
+    if (l.dim == 2) {                                                                         \
+      if (l.var) {                                                                            \
+        if (l.G == 4) hipLaunchKernelGGL((KERNEL<2, T, true, 4>), grid_, block_, 0, l.stream, ARGS); \
+        else hipLaunchKernelGGL((KERNEL<2, T, true, 1>), grid_, block_, 0, l.stream, ARGS);         \
+      } else {                                                                                \
+        if (l.G == 4) hipLaunchKernelGGL((KERNEL<2, T, false, 4>), grid_, block_, 0, l.stream, ARGS); \
+        else hipLaunchKernelGGL((KERNEL<2, T, false, 1>), grid_, block_, 0, l.stream, ARGS);         \
+      }                                                                                       \
+    } else {                                                                                  \
+      if (l.var) {                                                                            \
+        if (l.G == 4) hipLaunchKernelGGL((KERNEL<3, T, true, 4>), grid_, block_, 0, l.stream, ARGS); \
+        else hipLaunchKernelGGL((KERNEL<3, T, true, 1>), grid_, block_, 0, l.stream, ARGS);         \
+      } else {                                                                                \
+        if (l.G == 4) hipLaunchKernelGGL((KERNEL<3, T, false, 4>), grid_, block_, 0, l.stream, ARGS); \
+        else hipLaunchKernelGGL((KERNEL<3, T, false, 1>), grid_, block_, 0, l.stream, ARGS);         \
+      }                                                                                       \
+    }                                                                                         \
+  } while (0)
+#define SPH_ARGS(...) __VA_ARGS__
+
 template <typename T>
 void launch_density(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                     const int* cs, T* rho_out, double* partials, int* counts, unsigned* flags) {
   if (g.n == 0) return;
-  dim3 grid(l.nblk), block(kBlock);
-#define SPH_DENS(D, V)                                                                      \
-  hipLaunchKernelGGL((density_kernel<D, T, V>), grid, block, 0, l.stream, g, k, p.cell, cs, \
-                     p.off, p.mass, p.h, rho_out, partials, counts, flags)
-  if (l.dim == 2) { if (l.var) SPH_DENS(2, true); else SPH_DENS(2, false); }
-  else { if (l.var) SPH_DENS(3, true); else SPH_DENS(3, false); }
-#undef SPH_DENS
+  SPH_SWEEP(density_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.mass, p.h, rho_out, partials,
+                                     counts, flags));
 }
 
 template <typename T>
 void launch_tv(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                const int* cs, T* dr, T* beta, double* s_out, T* g_out, double* partials) {
   if (g.n == 0) return;
-  dim3 grid(l.nblk), block(kBlock);
-#define SPH_TV(D, V)                                                                        \
-  hipLaunchKernelGGL((tv_kernel<D, T, V>), grid, block, 0, l.stream, g, k, p.cell, cs,      \
-                     p.off, p.rho, p.mass, p.h, dr, beta, s_out, g_out, partials)
-  if (l.dim == 2) { if (l.var) SPH_TV(2, true); else SPH_TV(2, false); }
-  else { if (l.var) SPH_TV(3, true); else SPH_TV(3, false); }
-#undef SPH_TV
+  SPH_SWEEP(tv_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.rho, p.mass, p.h, dr, beta, s_out,
+                                g_out, partials));
 }
 
 template <typename T>
 void launch_forces(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                    const int* cs, const T* vel, T* acc_out, unsigned* flags) {
   if (g.n == 0) return;
-  dim3 grid(l.nblk), block(kBlock);
   FusedOut<T> none{};
-#define SPH_FRC(D, V)                                                                       \
-  hipLaunchKernelGGL((forces_kernel<D, T, V, false>), grid, block, 0, l.stream, g, k, p.cell,\
-                     cs, p.off, vel, p.rho, p.mass, p.h, p.id, acc_out, flags, none)
-  if (l.dim == 2) { if (l.var) SPH_FRC(2, true); else SPH_FRC(2, false); }
-  else { if (l.var) SPH_FRC(3, true); else SPH_FRC(3, false); }
-#undef SPH_FRC
+  SPH_SWEEP(forces_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, vel, p.rho, p.mass, p.h, p.id,
+                                          acc_out, flags, none));
 }
 
 template <typename T>
 void launch_forces_fused(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                          const int* cs, const FusedOut<T>& fo, unsigned* flags) {
   if (g.n == 0) return;
-  dim3 grid(l.nblk), block(kBlock);
-#define SPH_FRCF(D, V)                                                                      \
-  hipLaunchKernelGGL((forces_kernel<D, T, V, true>), grid, block, 0, l.stream, g, k, p.cell,\
-                     cs, p.off, p.vel, p.rho, p.mass, p.h, p.id, p.acc, flags, fo)
-  if (l.dim == 2) { if (l.var) SPH_FRCF(2, true); else SPH_FRCF(2, false); }
-  else { if (l.var) SPH_FRCF(3, true); else SPH_FRCF(3, false); }
-#undef SPH_FRCF
+  SPH_SWEEP(forces_fused_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.vel, p.rho, p.mass, p.h, p.id,
+                                          p.acc, flags, fo));
 }
 
 #define SPH_INST(T)                                                                          \
