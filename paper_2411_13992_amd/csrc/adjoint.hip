@@ -40,135 +40,170 @@ __device__ __forceinline__ bool pair_kernel(const Coeffs<T>& k, T r2, T hi, T hj
 //   rhobar_i += -(f.w) / rho_i - Cc (c0^2/2 + beta c0 dU / 4) (r.w)
 // with Cc = 2 m_j F / (rho_i rho_j), Cp = 2 m_j (F'/|r|) / (rho_i rho_j),
 // B = eta v_ij - P* r, f = Cc B, dP = dP*/dU = rhobar c0 (beta + dU beta') / 2,
-// v_perp = v_ij - (v_ij . r) r / |r|^2.
-template <int D, typename T, bool VAR>
+// v_perp = v_ij - (v_ij . r) r / |r|^2.  The long pair body runs over a
+// per-thread neighbour list (positions are tested first).
+template <int G>
+struct VjpCap { static constexpr int value = G == 1 ? 48 : (G == 2 ? 24 : 16); };
+
+template <int D, typename T, bool VAR, int G>
 __global__ __launch_bounds__(kBlock) void force_vjp_kernel(
     Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
     const T* __restrict__ off, const T* __restrict__ vel, const T* __restrict__ rho,
     const T* __restrict__ mass, const T* __restrict__ hh, const T* __restrict__ a_bar,
     T* __restrict__ r_bar, T* __restrict__ v_bar, T* __restrict__ rho_bar) {
+  __shared__ NeighbourList<VjpCap<G>::value> nl;
   const int n = g.n;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  T oi[3], vi[3], ai[3];
-#pragma unroll
-  for (int d = 0; d < D; ++d) {
-    oi[d] = off[d * n + i];
-    vi[d] = vel[d * n + i];
-    ai[d] = a_bar[d * n + i];
-  }
-  const T rhoi = rho[i];
-  const T inv_rhoi = T(1) / rhoi;
-  const T pi = k.c0sq * (rhoi - k.rho0);
-  const T hi = VAR ? hh[i] : k.h;
-  const T mi = VAR ? mass[i] : k.mass;
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
+  const int sub = threadIdx.x % G;
+  const bool valid = i < n;
   Acc<T, UseKahan<T>::value> rb[3], vb[3], pb;
 #pragma unroll
-  for (int d = 0; d < D; ++d) {
+  for (int d = 0; d < 3; ++d) {
     rb[d].init(T(0));
     vb[d].init(T(0));
   }
   pb.init(T(0));
-  for_each_candidate<D, 1>(g, k, cell[i], cs, 0, [&](int j, const T* sh) {
-    T r[3];
-    T r2 = T(0);
+  if (valid) {
+    T oi[3], vi[3], ai[3];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      r[d] = (oi[d] - off[d * n + j]) - sh[d];
-      r2 = tfma(r[d], r[d], r2);
+      oi[d] = off[d * n + i];
+      vi[d] = vel[d * n + i];
+      ai[d] = a_bar[d * n + i];
     }
-    if (j == i) return;
-    PairKernel<D, T> pk;
-    T inv_r;
-    if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? hh[j] : k.h, pk, inv_r)) return;
-    const T mj = VAR ? mass[j] : k.mass;
-    const T rhoj = rho[j];
-    const T pj = k.c0sq * (rhoj - k.rho0);
-    T vij[3], w[3];
-    T vr = T(0);
-    const T mratio = VAR ? mi / mj : T(1);
+    const T rhoi = rho[i];
+    const T inv_rhoi = T(1) / rhoi;
+    const T pi = k.c0sq * (rhoi - k.rho0);
+    const T hi = VAR ? hh[i] : k.h;
+    const T mi = VAR ? mass[i] : k.mass;
+    auto test = [&](int j, const T* sh) -> bool {
+      if (j == i) return false;
+      T r2 = T(0);
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      vij[d] = vi[d] - vel[d * n + j];
-      vr = tfma(vij[d], r[d], vr);
-      w[d] = tfma(-mratio, a_bar[d * n + j], ai[d]);
-    }
-    const T du = -vr * inv_r;
-    const T x = k.riemann_eta * du * k.inv_c0;
-    const T br = tmin(tmax(x, T(0)), T(1));
-    const T bprime = (x > T(0) && x < T(1)) ? k.riemann_eta * k.inv_c0 : T(0);
-    const T rhobar = T(0.5) * (rhoi + rhoj);
-    const T pstar = T(0.5) * (pi + pj) + T(0.5) * br * rhobar * k.c0 * du;
-    const T dP = T(0.5) * rhobar * k.c0 * (br + du * bprime);
-    const T base = T(2) * mj * inv_rhoi / rhoj;
-    const T Cc = base * pk.F;
-    const T Cp = base * pk.Fpr;
-    T Bw = T(0), rw = T(0);
+      for (int d = 0; d < D; ++d) {
+        const T rv = (oi[d] - off[d * n + j]) - sh[d];
+        r2 = tfma(rv, rv, r2);
+      }
+      return r2 < pair_h<D, T, VAR>(k, hi, VAR ? hh[j] : T(0)).sup2;
+    };
+    auto body = [&](int j, const T* sh) {
+      T r[3];
+      T r2 = T(0);
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const T B = tfma(-pstar, r[d], k.eta * vij[d]);
-      Bw = tfma(B, w[d], Bw);
-      rw = tfma(r[d], w[d], rw);
-    }
-    const T vperp_coef = vr * inv_r * inv_r;   // (v_ij . r) / |r|^2
+      for (int d = 0; d < D; ++d) {
+        r[d] = (oi[d] - off[d * n + j]) - sh[d];
+        r2 = tfma(r[d], r[d], r2);
+      }
+      PairKernel<D, T> pk;
+      T inv_r;
+      pair_kernel<D, T, VAR>(k, r2, hi, VAR ? hh[j] : k.h, pk, inv_r);
+      const T mj = VAR ? mass[j] : k.mass;
+      const T rhoj = rho[j];
+      const T pj = k.c0sq * (rhoj - k.rho0);
+      T vij[3], w[3];
+      T vr = T(0);
+      const T mratio = VAR ? mi / mj : T(1);
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const T vperp = vij[d] - vperp_coef * r[d];
-      rb[d].add(Bw * Cp * r[d] + Cc * (-pstar * w[d] + dP * rw * vperp * inv_r));
-      vb[d].add(Cc * (k.eta * w[d] + dP * inv_r * rw * r[d]));
-    }
-    pb.add(-Cc * Bw * inv_rhoi - Cc * (T(0.5) * k.c0sq + T(0.25) * br * k.c0 * du) * rw);
-  });
+      for (int d = 0; d < D; ++d) {
+        vij[d] = vi[d] - vel[d * n + j];
+        vr = tfma(vij[d], r[d], vr);
+        w[d] = tfma(-mratio, a_bar[d * n + j], ai[d]);
+      }
+      const T du = -vr * inv_r;
+      const T x = k.riemann_eta * du * k.inv_c0;
+      const T br = tmin(tmax(x, T(0)), T(1));
+      const T bprime = (x > T(0) && x < T(1)) ? k.riemann_eta * k.inv_c0 : T(0);
+      const T rhobar = T(0.5) * (rhoi + rhoj);
+      const T pstar = T(0.5) * (pi + pj) + T(0.5) * br * rhobar * k.c0 * du;
+      const T dP = T(0.5) * rhobar * k.c0 * (br + du * bprime);
+      const T base = T(2) * mj * inv_rhoi / rhoj;
+      const T Cc = base * pk.F;
+      const T Cp = base * pk.Fpr;
+      T Bw = T(0), rw = T(0);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const T B = tfma(-pstar, r[d], k.eta * vij[d]);
+        Bw = tfma(B, w[d], Bw);
+        rw = tfma(r[d], w[d], rw);
+      }
+      const T vperp_coef = vr * inv_r * inv_r;   // (v_ij . r) / |r|^2
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const T vperp = vij[d] - vperp_coef * r[d];
+        rb[d].add(Bw * Cp * r[d] + Cc * (-pstar * w[d] + dP * rw * vperp * inv_r));
+        vb[d].add(Cc * (k.eta * w[d] + dP * inv_r * rw * r[d]));
+      }
+      pb.add(-Cc * Bw * inv_rhoi - Cc * (T(0.5) * k.c0sq + T(0.25) * br * k.c0 * du) * rw);
+    };
+    for_each_neighbour_listed<D, G, T, VjpCap<G>::value>(g, k, cell[i], cs, sub, nl, test, body);
+  }
+  T rbs[3], vbs[3];
 #pragma unroll
   for (int d = 0; d < D; ++d) {
-    r_bar[d * n + i] += rb[d].value();
-    v_bar[d * n + i] += vb[d].value();
+    rbs[d] = group_sum<G>(rb[d]);
+    vbs[d] = group_sum<G>(vb[d]);
   }
-  rho_bar[i] += pb.value();
+  const T pbs = group_sum<G>(pb);
+  if (valid && sub == 0) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      r_bar[d * n + i] += rbs[d];
+      v_bar[d * n + i] += vbs[d];
+    }
+    rho_bar[i] += pbs;
+  }
 }
 
 // ------------------------------------------------------------------ density^T
 // rbar_i += sum_j (rhobar_i m_j + rhobar_j m_i) F_ij r_ij / kappa, then
 // vbar_i += vcoef * rbar_i (the drift r' = r + dt v' of the same step).
-template <int D, typename T, bool VAR>
+template <int D, typename T, bool VAR, int G>
 __global__ __launch_bounds__(kBlock) void density_vjp_kernel(
     Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
     const T* __restrict__ off, const T* __restrict__ mass, const T* __restrict__ hh,
     const T* __restrict__ rho_bar, T* __restrict__ r_bar, T* __restrict__ v_bar, T vcoef) {
   const int n = g.n;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  T oi[3];
-#pragma unroll
-  for (int d = 0; d < D; ++d) oi[d] = off[d * n + i];
-  const T hi = VAR ? hh[i] : k.h;
-  const T mi = VAR ? mass[i] : k.mass;
-  const T pbi = rho_bar[i];
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
+  const int sub = threadIdx.x % G;
+  const bool valid = i < n;
   Acc<T, UseKahan<T>::value> acc[3];
 #pragma unroll
-  for (int d = 0; d < D; ++d) acc[d].init(T(0));
-  for_each_candidate<D, 1>(g, k, cell[i], cs, 0, [&](int j, const T* sh) {
-    T r[3];
-    T r2 = T(0);
+  for (int d = 0; d < 3; ++d) acc[d].init(T(0));
+  if (valid) {
+    T oi[3];
+#pragma unroll
+    for (int d = 0; d < D; ++d) oi[d] = off[d * n + i];
+    const T hi = VAR ? hh[i] : k.h;
+    const T mi = VAR ? mass[i] : k.mass;
+    const T pbi = rho_bar[i];
+    for_each_candidate<D, G>(g, k, cell[i], cs, sub, [&](int j, const T* sh) {
+      T r[3];
+      T r2 = T(0);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        r[d] = (oi[d] - off[d * n + j]) - sh[d];
+        r2 = tfma(r[d], r[d], r2);
+      }
+      if (j == i) return;
+      PairKernel<D, T> pk;
+      T inv_r;
+      if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? hh[j] : k.h, pk, inv_r)) return;
+      const T mj = VAR ? mass[j] : k.mass;
+      const T c = (pbi * mj + rho_bar[j] * mi) * pk.F;
+#pragma unroll
+      for (int d = 0; d < D; ++d) acc[d].add(c * r[d]);
+    });
+  }
+  T sums[3];
+#pragma unroll
+  for (int d = 0; d < D; ++d) sums[d] = group_sum<G>(acc[d]);
+  if (valid && sub == 0) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      r[d] = (oi[d] - off[d * n + j]) - sh[d];
-      r2 = tfma(r[d], r[d], r2);
+      const T rb = r_bar[d * n + i] + sums[d] * k.inv_kappa;
+      r_bar[d * n + i] = rb;
+      if (v_bar) v_bar[d * n + i] += vcoef * rb;
     }
-    if (j == i) return;
-    PairKernel<D, T> pk;
-    T inv_r;
-    if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? hh[j] : k.h, pk, inv_r)) return;
-    const T mj = VAR ? mass[j] : k.mass;
-    const T c = (pbi * mj + rho_bar[j] * mi) * pk.F;
-#pragma unroll
-    for (int d = 0; d < D; ++d) acc[d].add(c * r[d]);
-  });
-#pragma unroll
-  for (int d = 0; d < D; ++d) {
-    const T rb = r_bar[d * n + i] + acc[d].value() * k.inv_kappa;
-    r_bar[d * n + i] = rb;
-    if (v_bar) v_bar[d * n + i] += vcoef * rb;
   }
 }
 
@@ -204,66 +239,77 @@ __global__ __launch_bounds__(kBlock) void tv_ghat_kernel(Coeffs<T> k, int n,
     for (int d = 0; d < D; ++d) ghat[d * n + i] = (T)(f * (b * ri[d] + two_c_h2 * gr * gi[d]));
     xi_part = k.hmin2 * b * gr;
   }
-  const double tot = block_reduce<double, false>(xi_part, red);
-  if (threadIdx.x == 0) partials[blockIdx.x * kNumPartials] = tot;
+  const int cols[1] = {0};
+  double v[1] = {xi_part};
+  wave_partials<1>(partials, cols, v, 0u);
 }
 
 // ------------------------------------------------------------------ correction^T, pass 2
 // r_out_i = r_in_i + sum_j H_ij (V_j ghat_i - V_i ghat_j),  H = F I + (F'/r) r r^T
 // rho_out_i = (m_i / rho_i^2) sum_j F_ij (ghat_j . r_ij)
-template <int D, typename T, bool VAR>
+template <int D, typename T, bool VAR, int G>
 __global__ __launch_bounds__(kBlock) void tv_vjp_kernel(
     Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
     const T* __restrict__ off, const T* __restrict__ rho, const T* __restrict__ mass,
     const T* __restrict__ hh, const T* __restrict__ ghat, const T* __restrict__ r_in,
     T* __restrict__ r_out, T* __restrict__ rho_out) {
   const int n = g.n;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  T oi[3], gi[3];
-#pragma unroll
-  for (int d = 0; d < D; ++d) {
-    oi[d] = off[d * n + i];
-    gi[d] = ghat[d * n + i];
-  }
-  const T hi = VAR ? hh[i] : k.h;
-  const T mi = VAR ? mass[i] : k.mass;
-  const T rhoi = rho[i];
-  const T Vi = mi / rhoi;
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
+  const int sub = threadIdx.x % G;
+  const bool valid = i < n;
   Acc<T, UseKahan<T>::value> acc[3], pb;
 #pragma unroll
-  for (int d = 0; d < D; ++d) acc[d].init(T(0));
+  for (int d = 0; d < 3; ++d) acc[d].init(T(0));
   pb.init(T(0));
-  for_each_candidate<D, 1>(g, k, cell[i], cs, 0, [&](int j, const T* sh) {
-    T r[3];
-    T r2 = T(0);
+  T mi = T(1), rhoi = T(1);
+  if (valid) {
+    T oi[3], gi[3];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      r[d] = (oi[d] - off[d * n + j]) - sh[d];
-      r2 = tfma(r[d], r[d], r2);
+      oi[d] = off[d * n + i];
+      gi[d] = ghat[d * n + i];
     }
-    if (j == i) return;
-    PairKernel<D, T> pk;
-    T inv_r;
-    if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? hh[j] : k.h, pk, inv_r)) return;
-    const T mj = VAR ? mass[j] : k.mass;
-    const T Vj = mj / rho[j];
-    T u[3], gj[3];
-    T ur = T(0), gjr = T(0);
+    const T hi = VAR ? hh[i] : k.h;
+    mi = VAR ? mass[i] : k.mass;
+    rhoi = rho[i];
+    const T Vi = mi / rhoi;
+    for_each_candidate<D, G>(g, k, cell[i], cs, sub, [&](int j, const T* sh) {
+      T r[3];
+      T r2 = T(0);
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      gj[d] = ghat[d * n + j];
-      u[d] = Vj * gi[d] - Vi * gj[d];
-      ur += u[d] * r[d];
-      gjr += gj[d] * r[d];
-    }
+      for (int d = 0; d < D; ++d) {
+        r[d] = (oi[d] - off[d * n + j]) - sh[d];
+        r2 = tfma(r[d], r[d], r2);
+      }
+      if (j == i) return;
+      PairKernel<D, T> pk;
+      T inv_r;
+      if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? hh[j] : k.h, pk, inv_r)) return;
+      const T mj = VAR ? mass[j] : k.mass;
+      const T Vj = mj / rho[j];
+      T u[3], gj[3];
+      T ur = T(0), gjr = T(0);
 #pragma unroll
-    for (int d = 0; d < D; ++d) acc[d].add(pk.F * u[d] + pk.Fpr * ur * r[d]);
-    pb.add(pk.F * gjr);
-  });
+      for (int d = 0; d < D; ++d) {
+        gj[d] = ghat[d * n + j];
+        u[d] = Vj * gi[d] - Vi * gj[d];
+        ur = tfma(u[d], r[d], ur);
+        gjr = tfma(gj[d], r[d], gjr);
+      }
 #pragma unroll
-  for (int d = 0; d < D; ++d) r_out[d * n + i] = r_in[d * n + i] + acc[d].value();
-  rho_out[i] = pb.value() * mi / (rhoi * rhoi);
+      for (int d = 0; d < D; ++d) acc[d].add(pk.F * u[d] + pk.Fpr * ur * r[d]);
+      pb.add(pk.F * gjr);
+    });
+  }
+  T sums[3];
+#pragma unroll
+  for (int d = 0; d < D; ++d) sums[d] = group_sum<G>(acc[d]);
+  const T pbs = group_sum<G>(pb);
+  if (valid && sub == 0) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) r_out[d * n + i] = r_in[d * n + i] + sums[d];
+    rho_out[i] = pbs * mi / (rhoi * rhoi);
+  }
 }
 
 // ------------------------------------------------------------------ elementwise
@@ -301,39 +347,27 @@ __global__ __launch_bounds__(kBlock) void xi_final_kernel(int nblk, const double
                                                           double* __restrict__ xi_bar) {
   __shared__ double red[kBlock / kWave];
   double v = 0.0;
-  for (int r = threadIdx.x; r < nblk; r += kBlock) v += partials[r * kNumPartials];
+  for (int r = threadIdx.x; r < nblk * kWavesPerBlock; r += kBlock) v += partials[r];
   const double t = block_reduce<double, false>(v, red);
   if (threadIdx.x == 0) xi_bar[0] += t;
 }
 
 // ------------------------------------------------------------------ launchers
-#define SPH_DISPATCH(KERNEL, ...)                                                            \
-  do {                                                                                       \
-    dim3 grid_(l.nblk), block_(kBlock);                                                      \
-    if (l.dim == 2) {                                                                        \
-      if (l.var) hipLaunchKernelGGL((KERNEL<2, T, true>), grid_, block_, 0, l.stream, __VA_ARGS__); \
-      else hipLaunchKernelGGL((KERNEL<2, T, false>), grid_, block_, 0, l.stream, __VA_ARGS__);     \
-    } else {                                                                                 \
-      if (l.var) hipLaunchKernelGGL((KERNEL<3, T, true>), grid_, block_, 0, l.stream, __VA_ARGS__); \
-      else hipLaunchKernelGGL((KERNEL<3, T, false>), grid_, block_, 0, l.stream, __VA_ARGS__);     \
-    }                                                                                        \
-  } while (0)
-
 template <typename T>
 void launch_force_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                       const int* cs, const T* vel, const T* a_bar, T* r_bar, T* v_bar,
                       T* rho_bar) {
   if (g.n == 0) return;
-  SPH_DISPATCH(force_vjp_kernel, g, k, p.cell, cs, p.off, vel, p.rho, p.mass, p.h, a_bar, r_bar,
-               v_bar, rho_bar);
+  SPH_SWEEP(force_vjp_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, vel, p.rho, p.mass, p.h, a_bar,
+                                       r_bar, v_bar, rho_bar));
 }
 
 template <typename T>
 void launch_density_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                         const int* cs, const T* rho_bar, T* r_bar, T* v_bar, T vcoef) {
   if (g.n == 0) return;
-  SPH_DISPATCH(density_vjp_kernel, g, k, p.cell, cs, p.off, p.mass, p.h, rho_bar, r_bar, v_bar,
-               vcoef);
+  SPH_SWEEP(density_vjp_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.mass, p.h, rho_bar, r_bar,
+                                         v_bar, vcoef));
 }
 
 template <typename T>
@@ -352,8 +386,8 @@ template <typename T>
 void launch_tv_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                    const int* cs, const T* ghat, const T* r_in, T* r_out, T* rho_out) {
   if (g.n == 0) return;
-  SPH_DISPATCH(tv_vjp_kernel, g, k, p.cell, cs, p.off, p.rho, p.mass, p.h, ghat, r_in, r_out,
-               rho_out);
+  SPH_SWEEP(tv_vjp_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.rho, p.mass, p.h, ghat, r_in,
+                                    r_out, rho_out));
 }
 
 template <typename T>

@@ -21,7 +21,7 @@ struct Sizes {
 
 // Workspace regions (byte offsets from the workspace base).
 struct WsLayout {
-  size_t flags, cellbuf, slot, tmp, perm;
+  size_t flags, cellbuf, slot, tmp, tmp_id, tmp_range, perm;
   size_t stg_cell, stg_id, stg_off, stg_vel, stg_acc, stg_rho, stg_mass, stg_h;
   size_t dr, partials, partials2;
   size_t adj_r, adj_v, adj_rho, adj_g, adj_r2;
@@ -91,6 +91,8 @@ WsLayout ws_layout(const Sizes& s) {
   w.cellbuf = c.take(cellbuf_bytes(s.ncells));
   w.slot = c.take(sizeof(int) * n);
   w.tmp = c.take(sizeof(int) * n);
+  w.tmp_id = c.take(sizeof(int) * n);
+  w.tmp_range = c.take(2 * sizeof(int) * n);
   w.perm = c.take(sizeof(int) * n);
   w.stg_cell = c.take(sizeof(int) * n);
   w.stg_id = c.take(sizeof(int) * n);
@@ -101,8 +103,9 @@ WsLayout ws_layout(const Sizes& s) {
   w.stg_mass = c.take(t * n);
   w.stg_h = c.take(t * n);
   w.dr = c.take(t * dn);
-  w.partials = c.take(sizeof(double) * kNumPartials * (size_t)(s.nblk > 0 ? s.nblk : 1));
-  w.partials2 = c.take(sizeof(double) * kNumPartials * (size_t)(s.nblk > 0 ? s.nblk : 1));
+  const size_t prow = (size_t)(s.nblk > 0 ? s.nblk : 1) * kWavesPerBlock;
+  w.partials = c.take(sizeof(double) * kNumPartials * prow);
+  w.partials2 = c.take(sizeof(double) * kNumPartials * prow);
   w.adj_r = c.take(t * dn);
   w.adj_v = c.take(t * dn);
   w.adj_rho = c.take(t * n);
@@ -303,8 +306,9 @@ int32_t build_cells_t(const sph_params* p, sph_particles* parts, int32_t* cs, in
   if (!src.rho) stg.rho = nullptr;
   launch_stage_copy<T>(l, sz.n, src, stg, counts, (int*)(ws + w.slot));
   launch_scan(stream, sz.ncells, counts, cb.scan, 0u, cs, (unsigned*)(ws + w.flags), DiagFold{});
-  launch_scatter(stream, sz.n, stg.cell, (int*)(ws + w.slot), cs, (int*)(ws + w.tmp));
-  launch_rank_gather<T>(l, sz.n, (int*)(ws + w.tmp), cs, stg, src, perm);
+  const SortTmp st{(int*)(ws + w.tmp), (int*)(ws + w.tmp_id), (int2*)(ws + w.tmp_range)};
+  launch_scatter(stream, sz.n, stg.cell, stg.id, (int*)(ws + w.slot), cs, st);
+  launch_rank_gather<T>(l, sz.n, st, stg, src, perm);
   return hip_status();
 }
 
@@ -330,7 +334,7 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
   const CellBuf cb = cellbuf_of(ws, w.cellbuf, sz.ncells);
   int* counts = cb.counts;
   int* slot = (int*)(ws + w.slot);
-  int* tmp = (int*)(ws + w.tmp);
+  const SortTmp st{(int*)(ws + w.tmp), (int*)(ws + w.tmp_id), (int2*)(ws + w.tmp_range)};
   int* perm = (int*)(ws + w.perm);
   const size_t n = (size_t)sz.n, dn = (size_t)sz.dim * n, t = sz.tsz;
   const size_t csb = sizeof(int) * ((size_t)sz.ncells + 1);
@@ -376,11 +380,11 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
     double* nxt = diag ? part[(s + 1) & 1] : nullptr;
     // the previous step's diagnostics are folded by the scan of this step
     DiagFold fold{};
-    if (diag && s > 0) fold = DiagFold{part[(s - 1) & 1], sz.nblk, diag + (size_t)SPH_NDIAG * (s - 1)};
+    if (diag && s > 0) fold = DiagFold{part[(s - 1) & 1], sz.nblk * kWavesPerBlock, diag + (size_t)SPH_NDIAG * (s - 1)};
     // 3. cell build
     launch_scan(stream, sz.ncells, counts, cb.scan, (unsigned)s, cs, flags, fold);
-    launch_scatter(stream, sz.n, stg.cell, slot, cs, tmp);
-    launch_rank_gather<T>(l, sz.n, tmp, cs, src, dst, perm);
+    launch_scatter(stream, sz.n, stg.cell, stg.id, slot, cs, st);
+    launch_rank_gather<T>(l, sz.n, st, src, dst, perm);
     // 4. density summation (Eq. 8)
     launch_density<T>(l, g, k, a, cs, a.rho, cur, nullptr, flags);
     if (s + 1 < nsteps) {
@@ -411,7 +415,7 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
         if (e != hipSuccess) return SPH_E_HIP;
       }
       launch_kick<T>(l, k, sz.n, a.vel, a.acc, a.mass, cur, true, flags);
-      if (diag) launch_diag_fold(stream, DiagFold{cur, sz.nblk, diag + (size_t)SPH_NDIAG * s});
+      if (diag) launch_diag_fold(stream, DiagFold{cur, sz.nblk * kWavesPerBlock, diag + (size_t)SPH_NDIAG * s});
     }
   }
   return hip_status();
@@ -721,7 +725,7 @@ int32_t sph_diagnostics(const sph_params* p, const sph_particles* parts, const i
     launch_density<T>(l, g, k, a, cell_start, (T*)((char*)ws + w.stg_rho), partials, nullptr,
                       nullptr);
     launch_kick<T>(l, k, sz.n, a.vel, a.acc, a.mass, partials, false, nullptr);
-    launch_diag_fold(s, DiagFold{partials, sz.nblk, diag});
+    launch_diag_fold(s, DiagFold{partials, sz.nblk * kWavesPerBlock, diag});
     return SPH_OK;
   });
   if (st != SPH_OK) return st;

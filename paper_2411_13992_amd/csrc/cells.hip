@@ -133,6 +133,12 @@ __global__ __launch_bounds__(kBlock) void scan_lookback_kernel(
     unsigned* __restrict__ flags, DiagFold fold) {
   __shared__ int lds[kBlock / kWave];
   __shared__ int tile_s, prefix_s;
+  if (fold.partials && (int)blockIdx.x >= ntiles) {
+    // the extra blocks fold the previous step's diagnostics, one column each;
+    // they take no ticket
+    fold_diag_column(fold.partials, fold.nrows, blockIdx.x - ntiles, fold.diag);
+    return;
+  }
   if (threadIdx.x == 0)
     tile_s = (int)(atomicAdd(&tickets[0], 1u) - epoch * (unsigned)ntiles);
   __syncthreads();
@@ -189,50 +195,59 @@ __global__ __launch_bounds__(kBlock) void scan_lookback_kernel(
     run += v[t];
   }
   if (tile == ntiles - 1 && threadIdx.x == 0) cs[ncells] = prefix_s + total;
-  if (fold.partials && blockIdx.x == 0) fold_diag(fold.partials, fold.nblk, fold.diag);
 }
 
 void launch_scan(hipStream_t s, int ncells, int* counts, ScanState st, unsigned epoch, int* cs,
                  unsigned* flags, DiagFold fold) {
   const int nt = scan_blocks(ncells);
-  hipLaunchKernelGGL(scan_lookback_kernel, dim3(nt), dim3(kBlock), 0, s, ncells, nt, counts, cs,
+  const int nb = nt + (fold.partials ? kNumPartials : 0);
+  hipLaunchKernelGGL(scan_lookback_kernel, dim3(nb), dim3(kBlock), 0, s, ncells, nt, counts, cs,
                      st.tile_state, st.tickets, epoch, flags, fold);
 }
 
 // ------------------------------------------------------------------ scatter
+// Each particle lands in slot `slot` of its new cell, together with its id
+// and that cell's [start, end) so the ranking pass needs no further lookups.
 __global__ __launch_bounds__(kBlock) void scatter_kernel(int n, const int* __restrict__ cell,
+                                                         const int* __restrict__ id,
                                                          const int* __restrict__ slot,
                                                          const int* __restrict__ cs,
-                                                         int* __restrict__ tmp) {
+                                                         SortTmp tmp) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) tmp[cs[cell[i]] + slot[i]] = i;
+  if (i >= n) return;
+  const int c = cell[i];
+  const int b = cs[c];
+  const int e = cs[c + 1];
+  const int pos = b + slot[i];
+  tmp.src[pos] = i;
+  tmp.id[pos] = id[i];
+  tmp.range[pos] = make_int2(b, e);
 }
 
-void launch_scatter(hipStream_t s, int n, const int* cell, const int* slot, const int* cs, int* tmp) {
+void launch_scatter(hipStream_t s, int n, const int* cell, const int* id, const int* slot,
+                    const int* cs, SortTmp tmp) {
   if (n == 0) return;
-  hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, cell, slot, cs,
-                     tmp);
+  hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, cell, id, slot,
+                     cs, tmp);
 }
 
 // ------------------------------------------------------------------ rank + gather
-// tmp[p] holds the old index of the particle in slot p of its cell; its final
-// position is cell_start + (number of cell members with a smaller id).
+// Slot p holds a particle of some cell; its final position is the cell start
+// plus the number of cell members with a smaller id.
 template <int D, typename T>
-__global__ __launch_bounds__(kBlock) void rank_gather_kernel(int n, const int* __restrict__ tmp,
-                                                             const int* __restrict__ cs,
+__global__ __launch_bounds__(kBlock) void rank_gather_kernel(int n, SortTmp tmp,
                                                              PArrays<T> stg, PArrays<T> dst,
                                                              int* __restrict__ perm) {
   const int p = blockIdx.x * kBlock + threadIdx.x;
   if (p >= n) return;
-  const int src = tmp[p];
-  const int c = stg.cell[src];
-  const int idk = stg.id[src];
-  const int b = cs[c], e = cs[c + 1];
+  const int src = tmp.src[p];
+  const int idk = tmp.id[p];
+  const int2 be = tmp.range[p];
   int rank = 0;
-  for (int q = b; q < e; ++q) rank += stg.id[tmp[q]] < idk ? 1 : 0;
-  const int to = b + rank;
+  for (int q = be.x; q < be.y; ++q) rank += tmp.id[q] < idk ? 1 : 0;
+  const int to = be.x + rank;
   if (perm) perm[to] = src;
-  dst.cell[to] = c;
+  dst.cell[to] = stg.cell[src];
   dst.id[to] = idk;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
@@ -246,22 +261,22 @@ __global__ __launch_bounds__(kBlock) void rank_gather_kernel(int n, const int* _
 }
 
 template <typename T>
-void launch_rank_gather(const Launch& l, int n, const int* tmp, const int* cs,
-                        const PArrays<T>& stg, const PArrays<T>& dst, int* perm) {
+void launch_rank_gather(const Launch& l, int n, SortTmp tmp, const PArrays<T>& stg,
+                        const PArrays<T>& dst, int* perm) {
   if (n == 0) return;
   if (l.dim == 2)
     hipLaunchKernelGGL((rank_gather_kernel<2, T>), dim3(blocks_for(n)), dim3(kBlock), 0, l.stream,
-                       n, tmp, cs, stg, dst, perm);
+                       n, tmp, stg, dst, perm);
   else
     hipLaunchKernelGGL((rank_gather_kernel<3, T>), dim3(blocks_for(n)), dim3(kBlock), 0, l.stream,
-                       n, tmp, cs, stg, dst, perm);
+                       n, tmp, stg, dst, perm);
 }
 
 #define SPH_INST(T)                                                                          \
   template void launch_bin<T>(const Launch&, const Grid&, const Coeffs<T>&, const double*,   \
                               int*, T*, unsigned*);                                          \
-  template void launch_rank_gather<T>(const Launch&, int, const int*, const int*,            \
-                                      const PArrays<T>&, const PArrays<T>&, int*);
+  template void launch_rank_gather<T>(const Launch&, int, SortTmp, const PArrays<T>&,        \
+                                      const PArrays<T>&, int*);
 SPH_INST(float)
 SPH_INST(double)
 #undef SPH_INST

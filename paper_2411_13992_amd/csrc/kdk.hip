@@ -133,13 +133,9 @@ __global__ __launch_bounds__(kBlock) void kick_kernel(Coeffs<T> k, int n, T* __r
     if (bad && flags) atomicOr(flags, kFlagNonfinite);
   }
   if (partials) {
-    __shared__ double red5[5][kBlock / kWave];
+    const int cols[5] = {0, 1, 2, 3, 4};
     double v[5] = {ke, mom[0], mom[1], mom[2], vmax};
-    block_reduce_multi<5>(v, 1u << 4, red5);
-    if (threadIdx.x == 0) {
-      double* o = partials + blockIdx.x * kNumPartials;
-      for (int q = 0; q < 5; ++q) o[q] = v[q];
-    }
+    wave_partials<5>(partials, cols, v, 1u << 4);
   }
 }
 
@@ -156,14 +152,14 @@ void launch_kick(const Launch& l, const Coeffs<T>& k, int n, T* vel, const T* ac
 }
 
 __global__ __launch_bounds__(kBlock) void diag_fold_kernel(const double* __restrict__ partials,
-                                                           int nblk, double* __restrict__ diag) {
-  fold_diag(partials, nblk, diag);
+                                                           int nrows, double* __restrict__ diag) {
+  fold_diag_column(partials, nrows, blockIdx.x, diag);
 }
 
 void launch_diag_fold(hipStream_t s, DiagFold fold) {
   if (!fold.partials) return;
-  hipLaunchKernelGGL(diag_fold_kernel, dim3(1), dim3(kBlock), 0, s, fold.partials, fold.nblk,
-                     fold.diag);
+  hipLaunchKernelGGL(diag_fold_kernel, dim3(kNumPartials), dim3(kBlock), 0, s, fold.partials,
+                     fold.nrows, fold.diag);
 }
 
 __global__ __launch_bounds__(kBlock) void zero_double_kernel(double* __restrict__ p, long n) {
@@ -172,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void zero_double_kernel(double* __restrict_
 }
 
 void launch_zero_partials(hipStream_t s, int nblk, double* partials) {
-  long n = (long)(nblk > 0 ? nblk : 1) * kNumPartials;
+  long n = (long)(nblk > 0 ? nblk : 1) * kWavesPerBlock * kNumPartials;
   hipLaunchKernelGGL(zero_double_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, partials, n);
 }
 

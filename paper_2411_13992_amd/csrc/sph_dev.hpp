@@ -450,29 +450,46 @@ __device__ __forceinline__ void block_reduce_multi(double* v, unsigned max_mask,
   }
 }
 
-// Folds per-block partials [nblk][kNumPartials] into diag (sums, except
-// columns 4 and 8 which are maxima) with one block, in a fixed order:
-// deterministic.  Must run in a later launch than the kernels that wrote the
-// partials (the launch boundary makes their writes visible).
-__device__ __forceinline__ void fold_diag(const double* __restrict__ partials, int nblk,
-                                          double* __restrict__ diag) {
-  __shared__ double red[kNumPartials][kBlock / kWave];
-  constexpr unsigned kMaxCols = (1u << 4) | (1u << 8);
-  double v[kNumPartials];
+// Diagnostic partials: one row per wavefront, stored column-major
+// [kNumPartials][nrows] with nrows = (grid blocks) * (waves per block); every
+// kernel that writes partials in a step runs on the same grid, so rows line
+// up.  Each wavefront reduces its lanes with shuffles only (no block
+// barrier) and its first lane writes the row.
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+template <int NV>
+__device__ __forceinline__ void wave_partials(double* __restrict__ p, const int* cols,
+                                              double* v, unsigned max_mask) {
 #pragma unroll
-  for (int col = 0; col < kNumPartials; ++col) v[col] = 0.0;
-  for (int r = threadIdx.x; r < nblk; r += kBlock) {
+  for (int q = 0; q < NV; ++q) v[q] = ((max_mask >> q) & 1u) ? wave_max(v[q]) : wave_sum(v[q]);
+  if (threadIdx.x % kWave == 0) {
+    const size_t nrows = (size_t)gridDim.x * kWavesPerBlock;
+    const size_t row = (size_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
 #pragma unroll
-    for (int col = 0; col < kNumPartials; ++col) {
-      const double x = partials[r * kNumPartials + col];
-      v[col] = ((kMaxCols >> col) & 1u) ? (x > v[col] ? x : v[col]) : v[col] + x;
+    for (int q = 0; q < NV; ++q) p[cols[q] * nrows + row] = v[q];
+  }
+}
+
+// Folds column `col` of the partials (nrows rows) into diag[col], in a fixed
+// order (sum, or maximum for columns 4 and 8): deterministic.  One block per
+// column; must run in a later launch than the writers.
+__device__ __forceinline__ void fold_diag_column(const double* __restrict__ partials, int nrows,
+                                                 int col, double* __restrict__ diag) {
+  __shared__ double red[kBlock / kWave];
+  const bool is_max = (col == 4 || col == 8);
+  const double* c = partials + (size_t)col * nrows;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int r = threadIdx.x; r < nrows; r += 4 * kBlock) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int rr = r + u * kBlock;
+      const double x = rr < nrows ? c[rr] : 0.0;
+      a[u] = is_max ? (x > a[u] ? x : a[u]) : a[u] + x;
     }
   }
-  block_reduce_multi<kNumPartials>(v, kMaxCols, red);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int col = 0; col < kNumPartials; ++col) diag[col] = v[col];
-  }
+  double v = is_max ? fmax(fmax(a[0], a[1]), fmax(a[2], a[3])) : (a[0] + a[1]) + (a[2] + a[3]);
+  v = is_max ? block_reduce<double, true>(v, red) : block_reduce<double, false>(v, red);
+  if (threadIdx.x == 0) diag[col] = v;
 }
 
 }  // namespace sph

@@ -85,17 +85,25 @@ struct ScanState {
 };
 struct DiagFold {
   const double* partials;   // null: nothing to fold
-  int nblk;
+  int nrows;                // partial rows: blocks * waves per block
   double* diag;
 };
 void launch_scan(hipStream_t s, int ncells, int* counts, ScanState st, unsigned epoch, int* cs,
                  unsigned* flags, DiagFold fold);
 void launch_diag_fold(hipStream_t s, DiagFold fold);
-void launch_scatter(hipStream_t s, int n, const int* cell, const int* slot, const int* cs, int* tmp);
+// Sorting scratch: per destination slot, the source index, the particle id
+// and the cell's [start, end).
+struct SortTmp {
+  int* src;
+  int* id;
+  int2* range;
+};
+void launch_scatter(hipStream_t s, int n, const int* cell, const int* id, const int* slot,
+                    const int* cs, SortTmp tmp);
 // Moves staged arrays (old order) into dst arrays (new order); null pointers skip.
 template <typename T>
-void launch_rank_gather(const Launch& l, int n, const int* tmp, const int* cs,
-                        const PArrays<T>& stg, const PArrays<T>& dst, int* perm);
+void launch_rank_gather(const Launch& l, int n, SortTmp tmp, const PArrays<T>& stg,
+                        const PArrays<T>& dst, int* perm);
 
 // ---- integration (kdk.hip)
 template <typename T>
@@ -134,5 +142,30 @@ void launch_adj_finish(const Launch& l, const Coeffs<T>& k, int n, const T* vhal
 template <typename T>
 void launch_adj_kick(const Launch& l, const Coeffs<T>& k, int n, const T* v_bar, T* a_bar);
 void launch_xi_final(hipStream_t s, int nblk, const double* partials, double* xi_bar);
+
+// Launches a sweep kernel template KERNEL<D, T, VAR, G> on a grid of
+// n * G threads (G lanes per particle), dispatching on dimension, per-particle
+// mass/h and G; needs `l` (Launch) and the type T in scope.
+#define SPH_SWEEP_G(KERNEL, DD, VV, ...)                                                     \
+  do {                                                                                        \
+    if (l.G == 4)                                                                             \
+      hipLaunchKernelGGL((KERNEL<DD, T, VV, 4>), grid_, block_, 0, l.stream, __VA_ARGS__);    \
+    else if (l.G == 2)                                                                        \
+      hipLaunchKernelGGL((KERNEL<DD, T, VV, 2>), grid_, block_, 0, l.stream, __VA_ARGS__);    \
+    else                                                                                      \
+      hipLaunchKernelGGL((KERNEL<DD, T, VV, 1>), grid_, block_, 0, l.stream, __VA_ARGS__);    \
+  } while (0)
+#define SPH_SWEEP(KERNEL, ARGS)                                                               \
+  do {                                                                                        \
+    const dim3 grid_(l.nblk), block_(kBlock);                                                 \
+    if (l.dim == 2) {                                                                         \
+      if (l.var) SPH_SWEEP_G(KERNEL, 2, true, ARGS);                                          \
+      else SPH_SWEEP_G(KERNEL, 2, false, ARGS);                                               \
+    } else {                                                                                  \
+      if (l.var) SPH_SWEEP_G(KERNEL, 3, true, ARGS);                                          \
+      else SPH_SWEEP_G(KERNEL, 3, false, ARGS);                                               \
+    }                                                                                         \
+  } while (0)
+#define SPH_ARGS(...) __VA_ARGS__
 
 }  // namespace sph

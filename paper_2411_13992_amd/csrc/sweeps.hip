@@ -25,7 +25,6 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
     const T* __restrict__ off, const T* __restrict__ mass, const T* __restrict__ hh,
     T* __restrict__ rho, double* __restrict__ partials, int* __restrict__ counts,
     unsigned* __restrict__ flags) {
-  __shared__ double red[kBlock / kWave];
   const int n = g.n;
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
@@ -75,8 +74,9 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
     if (!isfinite(r) && flags) atomicOr(flags, kFlagNonfinite);
   }
   if (partials) {
-    double tot = block_reduce<double, false>(lead ? (double)cnt : 0.0, red);
-    if (threadIdx.x == 0) partials[blockIdx.x * kNumPartials + 5] = tot;
+    const int cols[1] = {5};
+    double v[1] = {lead ? (double)cnt : 0.0};
+    wave_partials<1>(partials, cols, v, 0u);
   }
 }
 
@@ -89,7 +89,6 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
     const T* __restrict__ off, const T* __restrict__ rho, const T* __restrict__ mass,
     const T* __restrict__ hh, T* __restrict__ dr, T* __restrict__ beta_out,
     double* __restrict__ s_out, T* __restrict__ g_out, double* __restrict__ partials) {
-  __shared__ double red[3][kBlock / kWave];
   const int n = g.n;
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
@@ -141,12 +140,8 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
     v[2] = sqrt(d2) * k.inv_dt;
   }
   if (partials) {
-    block_reduce_multi<3>(v, 1u << 2, red);
-    if (threadIdx.x == 0) {
-      partials[blockIdx.x * kNumPartials + 6] = v[0];
-      partials[blockIdx.x * kNumPartials + 7] = v[1];
-      partials[blockIdx.x * kNumPartials + 8] = v[2];
-    }
+    const int cols[3] = {6, 7, 8};
+    wave_partials<3>(partials, cols, v, 1u << 2);
   }
 }
 
@@ -158,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
 // per-thread LDS list (for_each_neighbour_listed): positions are tested for
 // every candidate, the body runs for neighbours only.
 template <int G>
-struct ForceCap { static constexpr int value = G == 1 ? 48 : 16; };
+struct ForceCap { static constexpr int value = G == 1 ? 48 : (G == 2 ? 24 : 16); };
 
 template <int D, typename T, bool VAR, bool FUSED, int G>
 __device__ __forceinline__ void forces_impl(
@@ -299,16 +294,10 @@ __device__ __forceinline__ void forces_impl(
     const int slot = wave_claim_slot(lead, lin, fo.counts);
     if (lead) fo.slot[i] = slot;
     if (fo.part_cur) {
-      __shared__ double red8[8][kBlock / kWave];
-      block_reduce_multi<8>(v, (1u << 4) | (1u << 7), red8);
-      if (threadIdx.x == 0) {
-        double* o = fo.part_cur + blockIdx.x * kNumPartials;
-        for (int q = 0; q < 5; ++q) o[q] = v[q];
-        double* x = fo.part_next + blockIdx.x * kNumPartials;
-        x[6] = v[5];
-        x[7] = v[6];
-        x[8] = v[7];
-      }
+      const int cur_cols[5] = {0, 1, 2, 3, 4};
+      wave_partials<5>(fo.part_cur, cur_cols, v, 1u << 4);
+      const int next_cols[3] = {6, 7, 8};
+      wave_partials<3>(fo.part_next, next_cols, v + 5, 1u << 2);
     }
   }
 }
@@ -334,29 +323,7 @@ __global__ __launch_bounds__(kBlock) void forces_fused_kernel(
 }
 
 // ------------------------------------------------------------------ launchers
-// Sweeps run on a grid of n * G threads (G lanes per particle).
-#define SPH_SWEEP(KERNEL, ARGS)                                                               \
-  do {                                                                                        \
-    const dim3 grid_(l.nblk), block_(kBlock);                                                 \
-    if (l.dim == 2) {                                                                         \
-      if (l.var) {                                                                            \
-        if (l.G == 4) hipLaunchKernelGGL((KERNEL<2, T, true, 4>), grid_, block_, 0, l.stream, ARGS); \
-        else hipLaunchKernelGGL((KERNEL<2, T, true, 1>), grid_, block_, 0, l.stream, ARGS);         \
-      } else {                                                                                \
-        if (l.G == 4) hipLaunchKernelGGL((KERNEL<2, T, false, 4>), grid_, block_, 0, l.stream, ARGS); \
-        else hipLaunchKernelGGL((KERNEL<2, T, false, 1>), grid_, block_, 0, l.stream, ARGS);         \
-      }                                                                                       \
-    } else {                                                                                  \
-      if (l.var) {                                                                            \
-        if (l.G == 4) hipLaunchKernelGGL((KERNEL<3, T, true, 4>), grid_, block_, 0, l.stream, ARGS); \
-        else hipLaunchKernelGGL((KERNEL<3, T, true, 1>), grid_, block_, 0, l.stream, ARGS);         \
-      } else {                                                                                \
-        if (l.G == 4) hipLaunchKernelGGL((KERNEL<3, T, false, 4>), grid_, block_, 0, l.stream, ARGS); \
-        else hipLaunchKernelGGL((KERNEL<3, T, false, 1>), grid_, block_, 0, l.stream, ARGS);         \
-      }                                                                                       \
-    }                                                                                         \
-  } while (0)
-#define SPH_ARGS(...) __VA_ARGS__
+
 
 template <typename T>
 void launch_density(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
