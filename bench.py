@@ -40,7 +40,8 @@ FORCE_BYTES_PER_PARTICLE = {"f32": 28, "f64": 56}
 # x 2 flops per FMA (packed FP32 math is not used).
 VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "forces_kernel_tg2d_400_f32_pmc.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2411_13992_amd", "csrc", "sweeps.hip")
+PMC_COPY_BYTES = 64 << 20
+KERNEL_SOURCES = os.path.join(ROOT, "paper_2411_13992_amd", "csrc")
 
 
 def _events_time(fn, reps):
@@ -121,8 +122,10 @@ def kernel_roofline(sim, pairs, dtype, reps=200):
 
 
 def _pmc_traffic():
-    """HBM bytes per launch of the force sweep from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+    """Bytes per launch of the force sweep between L2 and the memory fabric,
+    from the committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE,
+    each scaled by what it reads for a device copy of known size), if it was
+    taken on the current kernel sources."""
     if not os.path.exists(PMC_SUMMARY):
         return None
     text = open(PMC_SUMMARY).read()
@@ -130,8 +133,18 @@ def _pmc_traffic():
     b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not m or not b:
         return None
-    cur = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    return float(b.group(1)) if cur == m.group(1) else None
+    return float(b.group(1)) if source_digest() == m.group(1) else None
+
+
+def source_digest():
+    """SHA-256 over the HIP sources (sorted by name): a counter summary taken on
+    other kernel code is not used."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(KERNEL_SOURCES)):
+        if name.endswith((".hip", ".hpp")):
+            h.update(name.encode())
+            h.update(open(os.path.join(KERNEL_SOURCES, name), "rb").read())
+    return h.hexdigest()
 
 
 def cpu_baseline(case, budget_s=12.0):
@@ -161,6 +174,9 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--pmc", action="store_true",
+                    help="counter run: 20 force-sweep launches on the benchmark state and one "
+                         "64 MiB device copy of known size (for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -172,6 +188,18 @@ def main():
 
     case = cases.make(WORKLOAD)
     sim = Simulation.from_case(case, dtype="f32")
+    if args.pmc:
+        sim.run(args.warmup)
+        out = torch.empty_like(sim.acc)
+        for _ in range(20):
+            sim.forces(out=out)
+        src = torch.ones(PMC_COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_run": True, "force_launches": 20, "copy_bytes": PMC_COPY_BYTES}))
+        return
     t32, pairs = time_steps(sim, args.steps, args.warmup)
     roof = kernel_roofline(sim, pairs, "f32")
     flags32 = sim.flags()

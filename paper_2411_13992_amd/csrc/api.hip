@@ -76,7 +76,7 @@ Sizes sizes_of(const sph_params* p, bool var) {
   s.dim = p->dim;
   s.n = (int)p->n;
   s.ncells = p->ncell[0] * p->ncell[1] * (p->dim == 3 ? p->ncell[2] : 1);
-  s.nblk = blocks_for((long)s.n * lanes_per_particle(s.n));
+  s.nblk = blocks_for((long)s.n * lanes_per_particle(s.dim));
   s.tsz = p->dtype == SPH_F64 ? 8 : 4;
   s.var = var;
   return s;
@@ -278,7 +278,7 @@ Launch launch_of(const sph_params* p, bool var, void* stream) {
   l.dim = p->dim;
   l.var = var;
   l.stream = (hipStream_t)stream;
-  l.G = lanes_per_particle(p->n);
+  l.G = lanes_per_particle(p->dim);
   l.nblk = blocks_for(p->n * l.G);
   return l;
 }

@@ -15,15 +15,18 @@ struct Launch {
   int dim;
   bool var;            // per-particle mass and h present
   hipStream_t stream;
-  int G;               // lanes per particle in the neighbour sweeps (1 or 4)
+  int G;               // lanes per particle in the neighbour sweeps (1, 2 or 4)
   int nblk;            // blocks of the sweeps and of every kernel writing
                        // diagnostic partials: ceil(n * G / kBlock)
 };
 
-// Lanes per particle for the neighbour sweeps: small systems leave most of the
-// GPU idle with one lane per particle, so a group of 4 lanes shares each
-// particle's candidates (more wavefronts in flight to hide memory latency).
-inline int lanes_per_particle(long n) { return n < 400000 ? 4 : 1; }
+// Lanes per particle for the neighbour sweeps.  A group of lanes shares one
+// particle's candidate cells, which puts more wavefronts in flight and splits
+// the serial candidate walk; the price is the group reduction and an epilogue
+// run by one lane in G.  Measured on gfx950: in 2-D (9 cells, about 60
+// candidates per particle) two lanes beat one and four; in 3-D (27 cells,
+// about 470 candidates) four lanes cut the force sweep by 2x over two.
+inline int lanes_per_particle(int dim) { return dim == 3 ? 4 : 2; }
 
 inline int blocks_for(long n) { return (int)((n + kBlock - 1) / kBlock); }
 
