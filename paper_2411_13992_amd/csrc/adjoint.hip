@@ -53,6 +53,8 @@ __global__ __launch_bounds__(kBlock) void force_vjp_kernel(
     T* __restrict__ r_bar, T* __restrict__ v_bar, T* __restrict__ rho_bar) {
   __shared__ NeighbourList<VjpCap<G>::value> nl;
   const int n = g.n;
+  const Cols<T, D> offc(off, n), velc(vel, n), abarc(a_bar, n);
+  const Cols<T, 1> rhoc(rho, n), hc(hh, n), mc(mass, n);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   const bool valid = i < n;
@@ -81,33 +83,33 @@ __global__ __launch_bounds__(kBlock) void force_vjp_kernel(
       T r2 = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        const T rv = (oi[d] - off[d * n + j]) - sh[d];
+        const T rv = (oi[d] - offc(d, j)) - sh[d];
         r2 = tfma(rv, rv, r2);
       }
-      return r2 < pair_h<D, T, VAR>(k, hi, VAR ? hh[j] : T(0)).sup2;
+      return r2 < pair_h<D, T, VAR>(k, hi, VAR ? hc(0, j) : T(0)).sup2;
     };
     auto body = [&](int j, const T* sh) {
       T r[3];
       T r2 = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        r[d] = (oi[d] - off[d * n + j]) - sh[d];
+        r[d] = (oi[d] - offc(d, j)) - sh[d];
         r2 = tfma(r[d], r[d], r2);
       }
       PairKernel<D, T> pk;
       T inv_r;
-      pair_kernel<D, T, VAR>(k, r2, hi, VAR ? hh[j] : k.h, pk, inv_r);
-      const T mj = VAR ? mass[j] : k.mass;
-      const T rhoj = rho[j];
+      pair_kernel<D, T, VAR>(k, r2, hi, VAR ? hc(0, j) : k.h, pk, inv_r);
+      const T mj = VAR ? mc(0, j) : k.mass;
+      const T rhoj = rhoc(0, j);
       const T pj = k.c0sq * (rhoj - k.rho0);
       T vij[3], w[3];
       T vr = T(0);
       const T mratio = VAR ? mi / mj : T(1);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        vij[d] = vi[d] - vel[d * n + j];
+        vij[d] = vi[d] - velc(d, j);
         vr = tfma(vij[d], r[d], vr);
-        w[d] = tfma(-mratio, a_bar[d * n + j], ai[d]);
+        w[d] = tfma(-mratio, abarc(d, j), ai[d]);
       }
       const T du = -vr * inv_r;
       const T x = k.riemann_eta * du * k.inv_c0;
@@ -163,6 +165,8 @@ __global__ __launch_bounds__(kBlock) void density_vjp_kernel(
     const T* __restrict__ off, const T* __restrict__ mass, const T* __restrict__ hh,
     const T* __restrict__ rho_bar, T* __restrict__ r_bar, T* __restrict__ v_bar, T vcoef) {
   const int n = g.n;
+  const Cols<T, D> offc(off, n);
+  const Cols<T, 1> rbarc(rho_bar, n), hc(hh, n), mc(mass, n);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   const bool valid = i < n;
@@ -181,15 +185,15 @@ __global__ __launch_bounds__(kBlock) void density_vjp_kernel(
       T r2 = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        r[d] = (oi[d] - off[d * n + j]) - sh[d];
+        r[d] = (oi[d] - offc(d, j)) - sh[d];
         r2 = tfma(r[d], r[d], r2);
       }
       if (j == i) return;
       PairKernel<D, T> pk;
       T inv_r;
-      if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? hh[j] : k.h, pk, inv_r)) return;
-      const T mj = VAR ? mass[j] : k.mass;
-      const T c = (pbi * mj + rho_bar[j] * mi) * pk.F;
+      if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? hc(0, j) : k.h, pk, inv_r)) return;
+      const T mj = VAR ? mc(0, j) : k.mass;
+      const T c = (pbi * mj + rbarc(0, j) * mi) * pk.F;
 #pragma unroll
       for (int d = 0; d < D; ++d) acc[d].add(c * r[d]);
     });
@@ -254,6 +258,8 @@ __global__ __launch_bounds__(kBlock) void tv_vjp_kernel(
     const T* __restrict__ hh, const T* __restrict__ ghat, const T* __restrict__ r_in,
     T* __restrict__ r_out, T* __restrict__ rho_out) {
   const int n = g.n;
+  const Cols<T, D> offc(off, n), ghatc(ghat, n);
+  const Cols<T, 1> rhoc(rho, n), hc(hh, n), mc(mass, n);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   const bool valid = i < n;
@@ -278,20 +284,20 @@ __global__ __launch_bounds__(kBlock) void tv_vjp_kernel(
       T r2 = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        r[d] = (oi[d] - off[d * n + j]) - sh[d];
+        r[d] = (oi[d] - offc(d, j)) - sh[d];
         r2 = tfma(r[d], r[d], r2);
       }
       if (j == i) return;
       PairKernel<D, T> pk;
       T inv_r;
-      if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? hh[j] : k.h, pk, inv_r)) return;
-      const T mj = VAR ? mass[j] : k.mass;
-      const T Vj = mj / rho[j];
+      if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? hc(0, j) : k.h, pk, inv_r)) return;
+      const T mj = VAR ? mc(0, j) : k.mass;
+      const T Vj = mj / rhoc(0, j);
       T u[3], gj[3];
       T ur = T(0), gjr = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        gj[d] = ghat[d * n + j];
+        gj[d] = ghatc(d, j);
         u[d] = Vj * gi[d] - Vi * gj[d];
         ur = tfma(u[d], r[d], ur);
         gjr = tfma(gj[d], r[d], gjr);

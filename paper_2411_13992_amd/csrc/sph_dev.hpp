@@ -98,6 +98,32 @@ struct UseKahan { static constexpr bool value = false; };
 template <>
 struct UseKahan<float> { static constexpr bool value = true; };
 
+// Neighbour reads through raw buffer resources.  Cols<T, NC> views NC
+// consecutive components of n elements each (component c starts at p + c n),
+// one 128-bit resource per component in scalar registers; a read takes the
+// element index in one VGPR (byte offset j * sizeof(T) < 2^31 since
+// n < 2^28), so every array a pair touches is read with the same offset and
+// no 64-bit address arithmetic.  A read past a component's n elements
+// returns 0 instead of touching memory.
+constexpr int kBufferWord3 = 0x00020000;   // raw untyped dword access (gfx9 family)
+
+template <typename T, int NC>
+struct Cols {
+  __amdgpu_buffer_rsrc_t r[NC];
+  __device__ __forceinline__ Cols(const T* p, int n) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      r[c] = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p) + (long)c * n, 0,
+                                               n * (int)sizeof(T), kBufferWord3);
+  }
+  __device__ __forceinline__ T operator()(int c, int j) const {
+    if constexpr (sizeof(T) == 4)
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r[c], j * 4, 0, 0));
+    else
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r[c], j * 8, 0, 0));
+  }
+};
+
 // ---------------------------------------------------------------- cells
 __device__ __forceinline__ int wrap_index(int x, int n) {
   x += (x < 0) ? n : 0;
@@ -334,7 +360,7 @@ __device__ __forceinline__ int wave_claim_slot(bool valid, int c, int* __restric
 // body(j, shift) over the list alone, so the wavefront executes the body once
 // per neighbour instead of once per candidate.  The list is flushed after each
 // z-plane of cells (once in 2-D) and whenever it fills.  An entry is j in
-// bits 0-27 with the cell offset code (dx + 1) + 3 (dy + 1) in bits 28-31.
+// bits 0-27, dx + 1 in bits 28-29 and dy + 1 in bits 30-31.
 // The visiting order is that of for_each_candidate, so sums over the listed
 // pairs are bit-identical to sums over a plain walk.
 constexpr int kListBits = 28;
@@ -363,8 +389,9 @@ __device__ __forceinline__ void for_each_neighbour_listed(const Grid& g, const C
     auto flush = [&]() {
       for (int q = 0; q < cnt; ++q) {
         const unsigned e = nl.slot[q][tid];
-        const int code = (int)(e >> kListBits);
-        const T shift[3] = {T(code % 3 - 1) * k.L[0], T(code / 3 - 1) * k.L[1], sz};
+        // (c - 1) L as c L - L: exact for c in {0, 1, 2}
+        const T cx = T((e >> kListBits) & 3u), cy = T(e >> (kListBits + 2));
+        const T shift[3] = {tfma(cx, k.L[0], -k.L[0]), tfma(cy, k.L[1], -k.L[1]), sz};
         body((int)(e & kListMask), shift);
       }
       cnt = 0;
@@ -379,7 +406,7 @@ __device__ __forceinline__ void for_each_neighbour_listed(const Grid& g, const C
         const int b = cs[cc];
         const int e = cs[cc + 1];
         const T shift[3] = {T(dx) * k.L[0], T(dy) * k.L[1], sz};
-        const unsigned code = (unsigned)((dx + 1) + 3 * (dy + 1)) << kListBits;
+        const unsigned code = (unsigned)((dx + 1) | ((dy + 1) << 2)) << kListBits;
         for (int j = b + sub; j < e; j += G) {
           if (test(j, shift)) {
             nl.slot[cnt][tid] = (unsigned)j | code;

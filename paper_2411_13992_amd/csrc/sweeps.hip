@@ -26,6 +26,8 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
     T* __restrict__ rho, double* __restrict__ partials, int* __restrict__ counts,
     unsigned* __restrict__ flags) {
   const int n = g.n;
+  const Cols<T, D> offc(off, n);
+  const Cols<T, 1> hc(hh, n), mc(mass, n);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   const bool valid = i < n;
@@ -45,14 +47,14 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
       T r2 = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        T rv = (oi[d] - off[d * n + j]) - sh[d];
+        T rv = (oi[d] - offc(d, j)) - sh[d];
         r2 = tfma(rv, rv, r2);
       }
       if constexpr (VAR) {
-        const T sup = hi + hh[j];
+        const T sup = hi + hc(0, j);
         if (r2 < sup * sup && j != i) {
           const T inv = frcp(T(0.5) * sup);
-          acc.add(mass[j] * wendland_alpha<D>(inv) * wendland_shape(fsqrt(r2) * inv));
+          acc.add(mc(0, j) * wendland_alpha<D>(inv) * wendland_shape(fsqrt(r2) * inv));
           ++cnt;
         }
       } else {
@@ -90,6 +92,8 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
     const T* __restrict__ hh, T* __restrict__ dr, T* __restrict__ beta_out,
     double* __restrict__ s_out, T* __restrict__ g_out, double* __restrict__ partials) {
   const int n = g.n;
+  const Cols<T, D> offc(off, n);
+  const Cols<T, 1> rhoc(rho, n), hc(hh, n), mc(mass, n);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   const bool valid = i < n;
@@ -106,16 +110,16 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
       T r2 = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        rv[d] = (oi[d] - off[d * n + j]) - sh[d];
+        rv[d] = (oi[d] - offc(d, j)) - sh[d];
         r2 = tfma(rv[d], rv[d], r2);
       }
       if (j == i) return;
-      const PairH<D, T, VAR> ph = pair_h<D, T, VAR>(k, hi, VAR ? hh[j] : T(0));
+      const PairH<D, T, VAR> ph = pair_h<D, T, VAR>(k, hi, VAR ? hc(0, j) : T(0));
       if (!(r2 < ph.sup2)) return;
       const PairGeo<T> pg = pair_geo(r2);
       const T t = kernel_t(pg.r, ph.inv_h);
       const T t3 = t * t * t;
-      const T w = tv_weight<D, T, VAR>(ph, t3, frcp(rho[j]), VAR ? mass[j] : k.mass);
+      const T w = tv_weight<D, T, VAR>(ph, t3, frcp(rhoc(0, j)), VAR ? mc(0, j) : k.mass);
 #pragma unroll
       for (int d = 0; d < D; ++d) acc[d].add(w * rv[d]);
     });
@@ -163,6 +167,8 @@ __device__ __forceinline__ void forces_impl(
     T* __restrict__ acc_out, unsigned* __restrict__ flags, const FusedOut<T>& fo) {
   __shared__ NeighbourList<ForceCap<G>::value> nl;
   const int n = g.n;
+  const Cols<T, D> offc(off, n), velc(vel, n);
+  const Cols<T, 1> rhoc(rho, n), hc(hh, n), mc(mass, n);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   const bool valid = i < n;
@@ -192,20 +198,20 @@ __device__ __forceinline__ void forces_impl(
       T r2 = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        const T rv = (oi[d] - off[d * n + j]) - sh[d];
+        const T rv = (oi[d] - offc(d, j)) - sh[d];
         r2 = tfma(rv, rv, r2);
       }
-      return r2 < pair_h<D, T, VAR>(k, hi, VAR ? hh[j] : T(0)).sup2;
+      return r2 < pair_h<D, T, VAR>(k, hi, VAR ? hc(0, j) : T(0)).sup2;
     };
     auto body = [&](int j, const T* sh) {
       T rv[3];
       T r2 = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        rv[d] = (oi[d] - off[d * n + j]) - sh[d];
+        rv[d] = (oi[d] - offc(d, j)) - sh[d];
         r2 = tfma(rv[d], rv[d], r2);
       }
-      const PairH<D, T, VAR> ph = pair_h<D, T, VAR>(k, hi, VAR ? hh[j] : T(0));
+      const PairH<D, T, VAR> ph = pair_h<D, T, VAR>(k, hi, VAR ? hc(0, j) : T(0));
       const PairGeo<T> pg = pair_geo(r2);
       const T t = kernel_t(pg.r, ph.inv_h);
       const T t3 = t * t * t;
@@ -214,16 +220,16 @@ __device__ __forceinline__ void forces_impl(
       T vr = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        vij[d] = vi[d] - vel[d * n + j];
+        vij[d] = vi[d] - velc(d, j);
         vr = tfma(vij[d], rv[d], vr);
       }
       const T du = -vr * pg.inv_r;
       const T br = tmin(k.riemann_eta * tmax(du * k.inv_c0, T(0)), T(1));
-      const T rhoj = rho[j];
+      const T rhoj = rhoc(0, j);
       const T rinv = frcp(rhoj);
       const T pj = k.c0sq * (rhoj - k.rho0);
       const T pstar = tfma(T(0.25) * br * (rhoi + rhoj) * k.c0, du, T(0.5) * (pi + pj));
-      const T mj = VAR ? mass[j] : k.mass;
+      const T mj = VAR ? mc(0, j) : k.mass;
       const T coef = mj * F * rinv;
 #pragma unroll
       for (int d = 0; d < D; ++d) acc[d].add(coef * tfma(-pstar, rv[d], k.eta * vij[d]));
