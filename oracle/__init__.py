@@ -46,7 +46,15 @@ class Params(ctypes.Structure):
         ("lim_s0", ctypes.c_double), ("riemann_eta", ctypes.c_double),
         ("h_min", ctypes.c_double), ("kappa", ctypes.c_double), ("band_tol", ctypes.c_double),
         ("tv_every", ctypes.c_int32), ("use_grid", ctypes.c_int32),
+        ("tv_mode", ctypes.c_int32),
     ]
+
+
+# Transport-velocity formulations
+TV_LIMITED = 0      # h-scaled correction with the limiter, Eq. (16)
+TV_SCALED = 1       # h-scaled correction without limiter, Eq. (14)
+TV_BACKGROUND = 2   # background pressure rho0 c0^2 in kick-drift-kick, Eq. (12)
+TV_MODES = {"limited": TV_LIMITED, "scaled": TV_SCALED, "background": TV_BACKGROUND}
 
 
 _lib = None
@@ -77,7 +85,8 @@ def lib():
                                      ctypes.c_double, _D]
         L.oracle_tv.argtypes = [ctypes.c_int, ctypes.c_int64, _D, _D, _D, _D, _D, _I64, _I32,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                ctypes.c_double, _D, _D, _D, _D, _D]
+                                ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                _D, _D, _D, _D, _D]
         L.oracle_forces.argtypes = [ctypes.c_int, ctypes.c_int64, _D, _D, _D, _D, _D, _D,
                                     _I64, _I32, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, _D, _D]
@@ -129,12 +138,16 @@ def lattice_kappa(dim: int, h_over_dx: float = 1.3) -> float:
 
 
 def params(case, band_tol: float = 1e-5, tv_every: int = 1, use_grid: bool = True,
-           xi: float | None = None, kappa: float | None = None) -> Params:
+           xi: float | None = None, kappa: float | None = None,
+           tv_mode: int | str = TV_LIMITED) -> Params:
+    if isinstance(tv_mode, str):
+        tv_mode = TV_MODES[tv_mode]
     return Params(rho0=case.rho0, c0=case.c0, eta=case.eta, dt=case.dt,
                   xi=case.xi if xi is None else xi, lim_c=case.lim_c, lim_s0=case.lim_s0,
                   riemann_eta=case.riemann_eta, h_min=case.h_min,
                   kappa=lattice_kappa(case.dim) if kappa is None else kappa,
-                  band_tol=band_tol, tv_every=tv_every, use_grid=1 if use_grid else 0)
+                  band_tol=band_tol, tv_every=tv_every, use_grid=1 if use_grid else 0,
+                  tv_mode=int(tv_mode))
 
 
 def neighbors(pos, h, box, method: str = "grid"):
@@ -161,15 +174,20 @@ def density(pos, mass, h, box, nbr, kappa):
     return rho
 
 
-def tv(pos, mass, rho, h, box, nbr, h_min, xi=-0.2, lim_c=1e3, lim_s0=5e-4):
-    """Returns dict g, s, beta, dr, gscale."""
+def tv(pos, mass, rho, h, box, nbr, h_min, xi=-0.2, lim_c=1e3, lim_s0=5e-4,
+       tv_mode: int | str = TV_LIMITED, bg: float = 0.0):
+    """Returns dict g, s, beta, dr, gscale.  bg = rho0 c0^2 dt^2 is used by the
+    background-pressure formulation only."""
+    if isinstance(tv_mode, str):
+        tv_mode = TV_MODES[tv_mode]
     pos, mass, rho, h, box = map(_f64, (pos, mass, rho, h, box))
     dim, n = pos.shape
     start, lst = nbr
     out = {k: np.zeros((dim, n)) for k in ("g", "dr")}
     out.update({k: np.zeros(n) for k in ("s", "beta", "gscale")})
     lib().oracle_tv(dim, n, _p(pos), _p(mass), _p(rho), _p(h), _p(box), _p(start), _p(lst),
-                    float(h_min), float(xi), float(lim_c), float(lim_s0), _p(out["g"]),
+                    float(h_min), float(xi), float(lim_c), float(lim_s0), int(tv_mode),
+                    float(bg), _p(out["g"]),
                     _p(out["s"]), _p(out["beta"]), _p(out["dr"]), _p(out["gscale"]))
     return out
 

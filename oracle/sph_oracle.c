@@ -25,6 +25,11 @@
  *    the perfect-lattice kernel sum times dx^D at h = 1.3 dx, so a perfect
  *    lattice has rho = rho0 exactly;
  *  - transport correction (Eq. 14-16): V_j = m_j / rho_j, h = h_min;
+ *  - original correction in kick-drift-kick (Eq. 12 with p0 = rho0 c0^2): the
+ *    extra transport acceleration a_t = -2 sum_j m_j p0/(rho_i rho_j) grad_i W_ij
+ *    acts over the drift as dr = a_t dt^2 / 2 (the same half-acceleration-
+ *    times-step-squared step that turns Eq. 12 into Eq. 14), so
+ *    dr_i = -(p0 dt^2 / rho_i) g_i with g_i = sum_j V_j grad_i W_ij;
  *  - time integration: kick-drift-kick with fixed dt; the correction is added to
  *    the drift; forces use the half-step velocity.
  */
@@ -52,7 +57,13 @@ typedef struct {
     double band_tol;    /* relative half-width of the limiter band    */
     int32_t tv_every;   /* apply the correction every k-th step       */
     int32_t use_grid;   /* 1: bucket neighbour search, 0: brute force */
+    int32_t tv_mode;    /* ORACLE_TV_* below                          */
 } oracle_params;
+
+/* Transport-velocity formulations */
+#define ORACLE_TV_LIMITED 0    /* h-scaled with the limiter, Eq. (16)          */
+#define ORACLE_TV_SCALED 1     /* h-scaled without limiter, Eq. (14)           */
+#define ORACLE_TV_BACKGROUND 2 /* background pressure rho0 c0^2 in KDK, Eq. (12) */
 
 /* ------------------------------------------------------------------ */
 /* threads                                                             */
@@ -310,18 +321,22 @@ void oracle_density(int dim, int64_t n, const double *pos, const double *mass,
 }
 
 /* ------------------------------------------------------------------ */
-/* Transport-velocity correction, Eq. (14)-(16)                        */
+/* Transport-velocity correction, Eq. (12), (14)-(16)                  */
 /*   g_i    = sum_j V_j grad_i W_ij,  V_j = m_j / rho_j                 */
 /*   s_i    = h_min^2 |g_i|^2                                          */
+/* limited (Eq. 15-16):                                                */
 /*   beta_i = min(C s_i, 1) if s_i > s0 else 0                         */
 /*   dr_i   = xi beta_i h_min^2 g_i                                    */
+/* scaled, no limiter (Eq. 14): beta_i = 1, dr_i = xi h_min^2 g_i       */
+/* background pressure in KDK (Eq. 12): beta_i = 1,                     */
+/*   dr_i   = -(bg / rho_i) g_i,  bg = p0 dt^2 = rho0 c0^2 dt^2         */
 /* gscale_i = sum_j |V_j grad_i W_ij| (the summation-error scale)      */
 /* ------------------------------------------------------------------ */
 void oracle_tv(int dim, int64_t n, const double *pos, const double *mass,
                const double *rho, const double *h, const double *box,
                const int64_t *start, const int32_t *list, double h_min, double xi,
-               double lim_c, double lim_s0, double *g, double *s, double *beta,
-               double *dr, double *gscale)
+               double lim_c, double lim_s0, int tv_mode, double bg, double *g, double *s,
+               double *beta, double *dr, double *gscale)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
@@ -344,11 +359,21 @@ void oracle_tv(int dim, int64_t n, const double *pos, const double *mass,
         double g2 = 0.0;
         for (int k = 0; k < dim; ++k) g2 += gi[k] * gi[k];
         double si = h_min * h_min * g2;
-        double bi = 0.0;
-        if (si > lim_s0) bi = fmin(lim_c * si, 1.0);
+        double bi, coef;
+        if (tv_mode == ORACLE_TV_LIMITED) {
+            bi = 0.0;
+            if (si > lim_s0) bi = fmin(lim_c * si, 1.0);
+            coef = xi * bi * h_min * h_min;
+        } else if (tv_mode == ORACLE_TV_SCALED) {
+            bi = 1.0;
+            coef = xi * h_min * h_min;
+        } else {
+            bi = 1.0;
+            coef = -bg / rho[i];
+        }
         for (int k = 0; k < dim; ++k) {
             if (g) g[k * n + i] = gi[k];
-            if (dr) dr[k * n + i] = xi * bi * h_min * h_min * gi[k];
+            if (dr) dr[k * n + i] = coef * gi[k];
         }
         if (s) s[i] = si;
         if (beta) beta[i] = bi;
@@ -511,7 +536,8 @@ void oracle_kdk_step(int dim, int64_t n, double *pos, double *vel, double *acc,
     make_lists(dim, n, pos, h, box, p->use_grid, &nl);
     if (p->tv_every > 0 && step_index % p->tv_every == 0)
         oracle_tv(dim, n, pos, mass, rho, h, box, nl.start, nl.list, p->h_min, p->xi,
-                  p->lim_c, p->lim_s0, g, s, beta, dr, NULL);
+                  p->lim_c, p->lim_s0, p->tv_mode, p->rho0 * p->c0 * p->c0 * p->dt * p->dt,
+                  g, s, beta, dr, NULL);
     free_lists(&nl);
 
     /* 2. half kick, 3. drift with the correction, wrapped into the box */

@@ -223,6 +223,82 @@ def test_tv_is_restoring_and_limited():
     assert seen == {"off", "ramp", "full"}
 
 
+def _density_gradient_fd(c, rho, i):
+    """kappa * d/dr_i of the kernel sum sum_j V_j W_ij (V_j = m_j / rho_j), by
+    central differences of the density routine (Eq. 8 with V_j as masses)."""
+    kappa = oracle.lattice_kappa(c.dim)
+    vol = c.mass / rho
+    out = np.zeros(c.dim)
+    for k in range(c.dim):
+        e = 1e-6 * c.dx
+        vals = []
+        for sgn in (1, -1):
+            p = c.pos.copy()
+            p[k, i] += sgn * e
+            nbp = oracle.neighbors(p, c.h, c.box)
+            vals.append(oracle.density(p, vol, c.h, c.box, nbp, kappa)[i])
+        out[k] = (vals[0] - vals[1]) / (2 * e) * kappa
+    return out
+
+
+def test_tv_unlimited_formulations():
+    """The two original corrections, each pinned to its own equation through
+    the density gradient G_i = grad_i sum_j V_j W_ij (central differences of
+    Eq. 8's sum, not the correction's own pair loop):
+      Eq. (14), no limiter:  dr_i = xi h^2 G_i, beta = 1 everywhere;
+      Eq. (12) in KDK:       the transport acceleration
+                             a_t = -2 sum_j m_j p0 / (rho_i rho_j) grad_i W_ij
+                                 = -(2 p0 / rho_i) G_i  with p0 = rho0 c0^2,
+                             acting over the drift as dr = a_t dt^2 / 2.
+    Also: the limited form equals the unlimited one wherever beta = 1, and all
+    three vanish on a lattice."""
+    c = cases.taylor_green_2d(16, jitter=0.2, seed=21)
+    rho = 1.0 + 0.1 * np.random.default_rng(22).uniform(-1.0, 1.0, size=c.n)
+    nb = oracle.neighbors(c.pos, c.h, c.box)
+    dt, p0 = c.dt, c.rho0 * c.c0 ** 2
+    bg = p0 * dt * dt
+    lim = oracle.tv(c.pos, c.mass, rho, c.h, c.box, nb, c.h_min, tv_mode="limited", bg=bg)
+    sca = oracle.tv(c.pos, c.mass, rho, c.h, c.box, nb, c.h_min, tv_mode="scaled", bg=bg)
+    bgr = oracle.tv(c.pos, c.mass, rho, c.h, c.box, nb, c.h_min, tv_mode="background", bg=bg)
+    assert np.all(sca["beta"] == 1.0) and np.all(bgr["beta"] == 1.0)
+    below = np.nonzero(lim["s"] <= c.lim_s0)[0]     # limiter off: beta = 0 there
+    assert below.size > 0
+    for i in (3, 50, 129, 200, int(below[0])):
+        G = _density_gradient_fd(c, rho, i)
+        tol = 1e-6 * sca["gscale"][i]
+        assert np.all(np.abs(sca["dr"][:, i] - (-0.2) * c.h_min ** 2 * G) < tol * c.h_min ** 2)
+        a_t = -(2.0 * p0 / rho[i]) * G
+        assert np.all(np.abs(bgr["dr"][:, i] - 0.5 * a_t * dt * dt) < tol * bg / rho[i])
+    full = lim["beta"] == 1.0
+    assert full.sum() > 10 and (~full).sum() > 0
+    assert np.array_equal(lim["dr"][:, full], sca["dr"][:, full])
+    # on a lattice every formulation gives no correction
+    c0 = cases.taylor_green_2d(12)
+    nb0 = oracle.neighbors(c0.pos, c0.h, c0.box)
+    rho0 = oracle.density(c0.pos, c0.mass, c0.h, c0.box, nb0, oracle.lattice_kappa(2))
+    for mode in ("scaled", "background"):
+        out = oracle.tv(c0.pos, c0.mass, rho0, c0.h, c0.box, nb0, c0.h_min, tv_mode=mode,
+                        bg=c0.rho0 * c0.c0 ** 2 * c0.dt ** 2)
+        assert np.max(np.abs(out["dr"])) < 1e-13 * c0.dx
+
+
+def test_background_correction_scale():
+    """With p0 = rho0 c0^2 and dt = 0.6 h / (U + c0), the background-pressure
+    correction is dt^2 c0^2 / (xi h^2) = -(0.6 c0 / (U + c0))^2 / 0.2 times the
+    h-scaled one at rho = rho0 (about 1.49x for c0 = 10 U): the size of the
+    original correction relative to Eq. (14)."""
+    c = cases.taylor_green_2d(16, jitter=0.2, seed=23)
+    nb = oracle.neighbors(c.pos, c.h, c.box)
+    rho = np.full(c.n, c.rho0)
+    bg = c.rho0 * c.c0 ** 2 * c.dt ** 2
+    sca = oracle.tv(c.pos, c.mass, rho, c.h, c.box, nb, c.h_min, tv_mode="scaled", bg=bg)
+    bgr = oracle.tv(c.pos, c.mass, rho, c.h, c.box, nb, c.h_min, tv_mode="background", bg=bg)
+    ratio = (0.6 * c.c0 / (c.u_ref + c.c0)) ** 2 / 0.2
+    m = np.abs(sca["dr"]) > 1e-6 * c.dx
+    assert np.allclose(bgr["dr"][m] / sca["dr"][m], ratio, rtol=1e-12)
+    assert 1.4 < ratio < 1.6
+
+
 # ---------------------------------------------------------------- forces
 def test_pressure_linear_field():
     """A linear pressure p = G x (rho = rho0 + G x / c0^2) at rest: the Riemann
