@@ -71,6 +71,15 @@ extern "C" {
 #define SPH_F32 0
 #define SPH_F64 1
 
+/* transport-velocity formulation (params.tv_mode); g_i = sum_j V_j grad_i W_ij,
+ * V_j = m_j / rho_j, s_i = h_min^2 |g_i|^2 */
+#define SPH_TV_LIMITED    0  /* Eq. 15-16: dr = xi beta h_min^2 g, beta the limiter   */
+#define SPH_TV_SCALED     1  /* Eq. 14 without limiter: dr = xi h_min^2 g (beta = 1)   */
+#define SPH_TV_BACKGROUND 2  /* Eq. 12 with background pressure p0 = rho0 c0^2 in the
+                                kick-drift-kick drift: the transport acceleration
+                                a_t = -2 (p0 / rho_i) g_i acts as dr = a_t dt^2 / 2,
+                                i.e. dr = -(rho0 c0^2 dt^2 / rho_i) g (beta = 1)       */
+
 /* Run parameters.  Symbols follow the paper: rho0 reference density, c0
  * artificial sound speed (Eq. 2), eta dynamic viscosity (Eq. 7), xi the
  * correction coefficient (-0.2, Eq. 14/16), lim_c and lim_s0 the limiter slope
@@ -85,6 +94,8 @@ typedef struct {
                              0 disables it                                       */
     int32_t per_particle; /* 1: particles carry their own mass and h arrays
                              (variable resolution); 0: uniform mass and h_min    */
+    int32_t tv_mode;      /* SPH_TV_LIMITED (default), SPH_TV_SCALED or
+                             SPH_TV_BACKGROUND; other values: SPH_E_ARG          */
     double box[3];        /* periodic box edges                                  */
     double rho0, c0, eta;
     double h_min, h_max;  /* smallest / largest smoothing length                 */
@@ -171,10 +182,11 @@ int32_t sph_density(const sph_params *p, const sph_particles *parts,
 int32_t sph_forces(const sph_params *p, const sph_particles *parts,
                    const int32_t *cell_start, const void *vel, void *acc_out, void *stream);
 
-/* Transport-velocity correction, Eq. 14-16, from positions and parts->rho:
- * dr_out[D][N]; beta_out [N] (optional) the limiter value; s_out [N] FP64
- * (optional) h_min^2 |g|^2 (the limiter test is made in FP64); g_out [D][N]
- * (optional) the raw sum g.  */
+/* Transport-velocity correction in the formulation params.tv_mode (Eq. 14-16,
+ * or Eq. 12 for SPH_TV_BACKGROUND), from positions and parts->rho:
+ * dr_out[D][N]; beta_out [N] (optional) the limiter value (1 for the unlimited
+ * formulations); s_out [N] FP64 (optional) h_min^2 |g|^2 (the limiter test is
+ * made in FP64); g_out [D][N] (optional) the raw sum g.  */
 int32_t sph_tv_correction(const sph_params *p, const sph_particles *parts,
                           const int32_t *cell_start, void *dr_out, void *beta_out,
                           double *s_out, void *g_out, void *stream);
@@ -210,7 +222,8 @@ int32_t sph_diagnostics(const sph_params *p, const sph_particles *parts,
 /* Reverse of one sph_kdk_step recorded in `tape`.  On entry adj holds the
  * cotangents of step n+1 in step n+1's order; on return those of step n in
  * step n's order.  xi_bar (device, one double) is incremented by the
- * derivative with respect to xi.  The neighbour sets are taken as fixed (the
+ * derivative with respect to xi (which SPH_TV_BACKGROUND does not use: no
+ * contribution there).  The neighbour sets are taken as fixed (the
  * C2 kernel's value and first two derivatives vanish at the support edge);
  * the limiter jump at s0 has zero derivative. */
 int32_t sph_adjoint_step(const sph_params *p, const void *tape, sph_adjoint *adj,

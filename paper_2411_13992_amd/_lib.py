@@ -17,6 +17,12 @@ SPH_OK = 0
 SPH_F32 = 0
 SPH_F64 = 1
 SPH_NDIAG = 9
+# transport-velocity formulations (params.tv_mode)
+TV_LIMITED = 0      # Eq. 15-16
+TV_SCALED = 1       # Eq. 14 without limiter
+TV_BACKGROUND = 2   # Eq. 12, background pressure rho0 c0^2 in the kick-drift-kick drift
+TV_MODES = {"limited": TV_LIMITED, "scaled": TV_SCALED, "background": TV_BACKGROUND}
+
 FLAG_NONFINITE = 1
 FLAG_CFL = 2
 FLAG_OUT_OF_BOX = 4
@@ -36,7 +42,8 @@ class SphParams(ctypes.Structure):
     _fields_ = [
         ("dim", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n", ctypes.c_int64),
         ("ncell", ctypes.c_int32 * 3), ("tv_every", ctypes.c_int32),
-        ("per_particle", ctypes.c_int32), ("box", ctypes.c_double * 3),
+        ("per_particle", ctypes.c_int32), ("tv_mode", ctypes.c_int32),
+        ("box", ctypes.c_double * 3),
         ("rho0", ctypes.c_double), ("c0", ctypes.c_double), ("eta", ctypes.c_double),
         ("h_min", ctypes.c_double), ("h_max", ctypes.c_double), ("mass", ctypes.c_double),
         ("kappa", ctypes.c_double), ("dt", ctypes.c_double), ("xi", ctypes.c_double),

@@ -212,16 +212,21 @@ __global__ __launch_bounds__(kBlock) void density_vjp_kernel(
 }
 
 // ------------------------------------------------------------------ correction^T, pass 1
-// ghat_i = xi h^2 (beta_i rbar_i + 2 C h^2 (g_i . rbar_i) g_i [ramp branch only]);
-// per-block partials of sum_i h^2 beta_i g_i . rbar_i (the xi derivative).
+// ghat_i = d(dr_i)/dg_i ^T rbar_i for the chosen formulation (beta_i from the
+// tape is 0 on steps without correction, which zeroes every term):
+//   limited:    xi h^2 (beta_i rbar_i + 2 C h^2 (g_i . rbar_i) g_i [ramp branch only])
+//   scaled:     xi h^2 beta_i rbar_i
+//   background: -(rho0 c0^2 dt^2 / rho_i) beta_i rbar_i
+// and per-wavefront partials of the xi derivative sum_i h^2 beta_i g_i . rbar_i
+// (none for the background formulation, which has no xi).
 template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void tv_ghat_kernel(Coeffs<T> k, int n,
                                                          const T* __restrict__ gsum,
                                                          const T* __restrict__ beta,
+                                                         const T* __restrict__ rho,
                                                          const T* __restrict__ r_bar,
                                                          T* __restrict__ ghat,
                                                          double* __restrict__ partials) {
-  __shared__ double red[kBlock / kWave];
   const int i = blockIdx.x * kBlock + threadIdx.x;
   double xi_part = 0.0;
   if (i < n) {
@@ -235,13 +240,20 @@ __global__ __launch_bounds__(kBlock) void tv_ghat_kernel(Coeffs<T> k, int n,
       gr += gi[d] * ri[d];
     }
     const double b = (double)beta[i];
-    const double s = k.hmin2 * gg;
-    const bool ramp = (s > k.lim_s0) && (k.lim_c * s < 1.0);
-    const double two_c_h2 = ramp ? 2.0 * k.lim_c * k.hmin2 : 0.0;
-    const double f = k.xi * k.hmin2;
+    double f, two_c_h2 = 0.0;
+    if (k.tv_mode == kTvBackground) {
+      f = -k.bg / (double)rho[i] * b;
+    } else {
+      f = k.xi * k.hmin2 * b;
+      xi_part = k.hmin2 * b * gr;
+      if (k.tv_mode == kTvLimited) {
+        const double s = k.hmin2 * gg;
+        const bool ramp = (s > k.lim_s0) && (k.lim_c * s < 1.0);
+        if (ramp) two_c_h2 = 2.0 * k.lim_c * k.hmin2 * k.xi * k.hmin2;
+      }
+    }
 #pragma unroll
-    for (int d = 0; d < D; ++d) ghat[d * n + i] = (T)(f * (b * ri[d] + two_c_h2 * gr * gi[d]));
-    xi_part = k.hmin2 * b * gr;
+    for (int d = 0; d < D; ++d) ghat[d * n + i] = (T)(f * ri[d] + two_c_h2 * gr * gi[d]);
   }
   const int cols[1] = {0};
   double v[1] = {xi_part};
@@ -250,13 +262,16 @@ __global__ __launch_bounds__(kBlock) void tv_ghat_kernel(Coeffs<T> k, int n,
 
 // ------------------------------------------------------------------ correction^T, pass 2
 // r_out_i = r_in_i + sum_j H_ij (V_j ghat_i - V_i ghat_j),  H = F I + (F'/r) r r^T
-// rho_out_i = (m_i / rho_i^2) sum_j F_ij (ghat_j . r_ij)
+// rho_out_i = (m_i / rho_i^2) sum_j F_ij (ghat_j . r_ij), plus for the
+// background formulation the derivative of its 1/rho_i factor,
+// (rho0 c0^2 dt^2 / rho_i^2) beta_i (g_i . r_in_i) (FP64).
 template <int D, typename T, bool VAR, int G>
 __global__ __launch_bounds__(kBlock) void tv_vjp_kernel(
     Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
     const T* __restrict__ off, const T* __restrict__ rho, const T* __restrict__ mass,
-    const T* __restrict__ hh, const T* __restrict__ ghat, const T* __restrict__ r_in,
-    T* __restrict__ r_out, T* __restrict__ rho_out) {
+    const T* __restrict__ hh, const T* __restrict__ ghat, const T* __restrict__ gsum,
+    const T* __restrict__ beta, const T* __restrict__ r_in, T* __restrict__ r_out,
+    T* __restrict__ rho_out) {
   const int n = g.n;
   const Cols<T, D> offc(off, n), ghatc(ghat, n);
   const Cols<T, 1> rhoc(rho, n), hc(hh, n), mc(mass, n);
@@ -312,9 +327,17 @@ __global__ __launch_bounds__(kBlock) void tv_vjp_kernel(
   for (int d = 0; d < D; ++d) sums[d] = group_sum<G>(acc[d]);
   const T pbs = group_sum<G>(pb);
   if (valid && sub == 0) {
+    double direct = 0.0;
 #pragma unroll
-    for (int d = 0; d < D; ++d) r_out[d * n + i] = r_in[d * n + i] + sums[d];
-    rho_out[i] = pbs * mi / (rhoi * rhoi);
+    for (int d = 0; d < D; ++d) {
+      if (k.tv_mode == kTvBackground)
+        direct += (double)gsum[d * n + i] * (double)r_in[d * n + i];
+      r_out[d * n + i] = r_in[d * n + i] + sums[d];
+    }
+    T rb = pbs * mi / (rhoi * rhoi);
+    if (k.tv_mode == kTvBackground)
+      rb = (T)((double)rb + k.bg * (double)beta[i] / ((double)rhoi * (double)rhoi) * direct);
+    rho_out[i] = rb;
   }
 }
 
@@ -378,22 +401,23 @@ void launch_density_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, cons
 
 template <typename T>
 void launch_tv_ghat(const Launch& l, const Coeffs<T>& k, int n, const T* gsum, const T* beta,
-                    const T* r_bar, T* ghat, double* partials) {
+                    const T* rho, const T* r_bar, T* ghat, double* partials) {
   if (n == 0) return;
   if (l.dim == 2)
     hipLaunchKernelGGL((tv_ghat_kernel<2, T>), dim3(l.nblk), dim3(kBlock), 0, l.stream, k, n,
-                       gsum, beta, r_bar, ghat, partials);
+                       gsum, beta, rho, r_bar, ghat, partials);
   else
     hipLaunchKernelGGL((tv_ghat_kernel<3, T>), dim3(l.nblk), dim3(kBlock), 0, l.stream, k, n,
-                       gsum, beta, r_bar, ghat, partials);
+                       gsum, beta, rho, r_bar, ghat, partials);
 }
 
 template <typename T>
 void launch_tv_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
-                   const int* cs, const T* ghat, const T* r_in, T* r_out, T* rho_out) {
+                   const int* cs, const T* ghat, const T* gsum, const T* beta, const T* r_in,
+                   T* r_out, T* rho_out) {
   if (g.n == 0) return;
-  SPH_SWEEP(tv_vjp_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.rho, p.mass, p.h, ghat, r_in,
-                                    r_out, rho_out));
+  SPH_SWEEP(tv_vjp_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.rho, p.mass, p.h, ghat, gsum,
+                                    beta, r_in, r_out, rho_out));
 }
 
 template <typename T>
@@ -431,9 +455,10 @@ void launch_xi_final(hipStream_t s, int nblk, const double* partials, double* xi
   template void launch_density_vjp<T>(const Launch&, const Grid&, const Coeffs<T>&,          \
                                       const PArrays<T>&, const int*, const T*, T*, T*, T);   \
   template void launch_tv_ghat<T>(const Launch&, const Coeffs<T>&, int, const T*, const T*,  \
-                                  const T*, T*, double*);                                    \
+                                  const T*, const T*, T*, double*);                          \
   template void launch_tv_vjp<T>(const Launch&, const Grid&, const Coeffs<T>&,               \
-                                 const PArrays<T>&, const int*, const T*, const T*, T*, T*); \
+                                 const PArrays<T>&, const int*, const T*, const T*,          \
+                                 const T*, const T*, T*, T*);                                \
   template void launch_unpermute<T>(const Launch&, int, const int*, const T*, T*, int);      \
   template void launch_adj_kick<T>(const Launch&, const Coeffs<T>&, int, const T*, T*);      \
   template void launch_adj_finish<T>(const Launch&, const Coeffs<T>&, int, const T*, T*, T*);

@@ -151,6 +151,9 @@ int32_t check_params(const sph_params* p) {
   if (p->n >= (int64_t(1) << 28)) return SPH_E_UNSUPPORTED;
   if (p->tv_every < 0) return SPH_E_ARG;
   if (p->per_particle != 0 && p->per_particle != 1) return SPH_E_ARG;
+  if (p->tv_mode != SPH_TV_LIMITED && p->tv_mode != SPH_TV_SCALED &&
+      p->tv_mode != SPH_TV_BACKGROUND)
+    return SPH_E_ARG;
   const double vals[] = {p->rho0, p->c0, p->h_min, p->h_max, p->kappa, p->mass};
   for (double v : vals)
     if (!std::isfinite(v)) return SPH_E_NONFINITE;
@@ -222,6 +225,8 @@ Coeffs<T> coeffs_of(const sph_params* p, const Grid& g) {
   k.hmin2 = h * h;
   k.band_tol = p->band_tol;
   k.inv_dt = p->dt > 0.0 ? 1.0 / p->dt : 0.0;
+  k.tv_mode = p->tv_mode;
+  k.bg = p->rho0 * p->c0 * p->c0 * p->dt * p->dt;
   return k;
 }
 
@@ -468,10 +473,11 @@ int32_t adjoint_step_t(const sph_params* p, const char* tape, sph_adjoint* adj, 
   launch_unpermute<T>(l, sz.n, perm, r_bar, r_n, sz.dim);
   launch_unpermute<T>(l, sz.n, perm, v_bar, vh_n, sz.dim);
   // 1^T: the correction dr = T(r^n, rho^n; xi)
-  launch_tv_ghat<T>(l, k, sz.n, (const T*)(tape + tl.g), (const T*)(tape + tl.beta), r_n, ghat,
-                    partials);
+  launch_tv_ghat<T>(l, k, sz.n, (const T*)(tape + tl.g), (const T*)(tape + tl.beta), pre.rho, r_n,
+                    ghat, partials);
   if (xi_bar) launch_xi_final(stream, sz.nblk, partials, xi_bar);
-  launch_tv_vjp<T>(l, g, k, pre, cs_pre, ghat, r_n, r_bar, rho_bar);
+  launch_tv_vjp<T>(l, g, k, pre, cs_pre, ghat, (const T*)(tape + tl.g),
+                   (const T*)(tape + tl.beta), r_n, r_bar, rho_bar);
   // 2^T: v' = v^n + dt/2 a^n
   launch_adj_finish<T>(l, k, sz.n, vh_n, v_bar, a_bar);
   return hip_status();

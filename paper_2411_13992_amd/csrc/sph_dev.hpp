@@ -11,6 +11,7 @@
 namespace sph {
 
 constexpr int kBlock = 256;          // threads per block for every particle kernel
+constexpr int kTvLimited = 0, kTvScaled = 1, kTvBackground = 2;   // SPH_TV_*
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kNumPartials = 9;      // per-block diagnostic partials
 constexpr double kPi = 3.14159265358979323846;
@@ -37,6 +38,8 @@ struct Coeffs {
   T inv_kappa;
   T dt, half_dt;
   double xi, lim_c, lim_s0, hmin2, band_tol, inv_dt;
+  int tv_mode;      // SPH_TV_LIMITED / SPH_TV_SCALED / SPH_TV_BACKGROUND
+  double bg;        // rho0 c0^2 dt^2, the background-pressure coefficient
 };
 
 // ---------------------------------------------------------------- math
@@ -310,22 +313,35 @@ __device__ __forceinline__ int drift_rebin(const Grid& g, const Coeffs<T>& k, in
   return c[0] + g.nc[0] * (c[1] + g.nc[1] * c[2]);
 }
 
-// ---------------------------------------------------------------- limiter
-// Eq. 15-16 from the raw sum g (FP64 test): s = h_min^2 |g|^2,
-// beta = min(C s, 1) if s > s0 else 0, dr = xi beta h_min^2 g.
+// ---------------------------------------------------------------- correction
 struct Limited {
   double s, beta;
 };
 
+// The correction of one particle from its sum g (FP64 arithmetic):
+//   limited (Eq. 15-16): beta = min(C s, 1) if s > s0 else 0, dr = xi beta h^2 g
+//   scaled (Eq. 14):     beta = 1, dr = xi h^2 g
+//   background (Eq. 12 in the drift): beta = 1, dr = -(rho0 c0^2 dt^2 / rho_i) g
+// with s = h_min^2 |g|^2.
 template <int D, typename T>
-__device__ __forceinline__ Limited limit_correction(const Coeffs<T>& k, const T* gi, T* dr) {
+__device__ __forceinline__ Limited limit_correction(const Coeffs<T>& k, const T* gi, T rhoi,
+                                                    T* dr) {
   double g2 = 0.0;
 #pragma unroll
   for (int d = 0; d < D; ++d) g2 += (double)gi[d] * (double)gi[d];
   Limited out;
   out.s = k.hmin2 * g2;
-  out.beta = out.s > k.lim_s0 ? fmin(k.lim_c * out.s, 1.0) : 0.0;
-  const double f = k.xi * out.beta * k.hmin2;
+  double f;
+  if (k.tv_mode == kTvLimited) {
+    out.beta = out.s > k.lim_s0 ? fmin(k.lim_c * out.s, 1.0) : 0.0;
+    f = k.xi * out.beta * k.hmin2;
+  } else if (k.tv_mode == kTvScaled) {
+    out.beta = 1.0;
+    f = k.xi * k.hmin2;
+  } else {
+    out.beta = 1.0;
+    f = -k.bg / (double)rhoi;
+  }
 #pragma unroll
   for (int d = 0; d < D; ++d) dr[d] = (T)(f * (double)gi[d]);
   return out;

@@ -133,10 +133,11 @@ void launch_density_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, cons
                         const int* cs, const T* rho_bar, T* r_bar, T* v_bar, T vcoef);
 template <typename T>
 void launch_tv_ghat(const Launch& l, const Coeffs<T>& k, int n, const T* gsum, const T* beta,
-                    const T* r_bar, T* ghat, double* partials);
+                    const T* rho, const T* r_bar, T* ghat, double* partials);
 template <typename T>
 void launch_tv_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
-                   const int* cs, const T* ghat, const T* r_in, T* r_out, T* rho_out);
+                   const int* cs, const T* ghat, const T* gsum, const T* beta, const T* r_in,
+                   T* r_out, T* rho_out);
 template <typename T>
 void launch_unpermute(const Launch& l, int n, const int* perm, const T* src, T* dst, int ncomp);
 template <typename T>

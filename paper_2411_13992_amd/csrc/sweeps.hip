@@ -83,8 +83,8 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
 }
 
 // ------------------------------------------------------------------ transport velocity
-// g_i = sum_j V_j F_ij r_ij (V_j = m_j / rho_j); s_i = h_min^2 |g_i|^2 tested in
-// FP64; beta_i = min(C s_i, 1) if s_i > s0 else 0; dr_i = xi beta_i h_min^2 g_i.
+// g_i = sum_j V_j F_ij r_ij (V_j = m_j / rho_j), then the correction of the
+// chosen formulation from g_i (limit_correction, FP64).
 template <int D, typename T, bool VAR, int G>
 __global__ __launch_bounds__(kBlock) void tv_kernel(
     Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
   for (int d = 0; d < D; ++d) gi[d] = tv_finish<T, VAR>(k, group_sum<G>(acc[d]));
   double v[3] = {0.0, 0.0, 0.0};   // beta > 0, in band, |dr| / dt
   if (valid && sub == 0) {
-    const Limited lim = limit_correction<D>(k, gi, dri);
+    const Limited lim = limit_correction<D>(k, gi, rho[i], dri);
     double d2 = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -273,7 +273,7 @@ __device__ __forceinline__ void forces_impl(
       v[0] = 0.5 * m * v2;
       v[4] = sqrt(v2);
       if (fo.apply_next) {
-        const Limited lim = limit_correction<D>(k, gi, dr);
+        const Limited lim = limit_correction<D>(k, gi, rhoi, dr);
         double d2 = 0.0;
 #pragma unroll
         for (int d = 0; d < D; ++d) d2 += (double)dr[d] * (double)dr[d];

@@ -42,6 +42,7 @@ class Config:
     lim_s0: float = 5.0e-4    # Eq. 15
     riemann_eta: float = 3.0  # Eq. 6
     tv_every: int = 1
+    tv_mode: str = "limited"  # "limited" (Eq. 16), "scaled" (Eq. 14), "background" (Eq. 12)
     band_tol: float = 1.0e-5
     h_over_dx: float = 1.3    # Sec. 4: h = 1.3 dp, fixes the reference kernel sum
     ncell: tuple | None = None
@@ -73,6 +74,7 @@ def make_params(cfg: Config, n: int, dtype: str, per_particle: bool = False) -> 
         p.ncell[k] = nc[k] if k < cfg.dim else 1
         p.box[k] = cfg.box[k] if k < cfg.dim else 1.0
     p.tv_every = cfg.tv_every
+    p.tv_mode = _lib.TV_MODES[cfg.tv_mode]
     p.rho0, p.c0, p.eta = cfg.rho0, cfg.c0, cfg.eta
     p.h_min, p.h_max, p.mass = cfg.h_min, cfg.h_max, cfg.mass
     p.kappa = _lib.lattice_kappa(cfg.dim, cfg.h_over_dx)

@@ -19,6 +19,14 @@ def _declared():
     return re.findall(r"^(?:int32_t|const char \*)\s*(sph_\w+)\s*\(", text, flags=re.M)
 
 
+def test_params_layout_matches_header():
+    """The ctypes mirror of sph_params has the header's field order: the
+    doubles start at byte 40 (after eight 32-bit and one 64-bit fields)."""
+    assert _lib.SphParams.box.offset == 40
+    assert _lib.SphParams.tv_mode.offset == 36
+    assert ctypes.sizeof(_lib.SphParams) == 40 + 8 * 16
+
+
 def test_library_exports_every_declared_symbol():
     L = _lib.load()
     names = _declared()
@@ -66,6 +74,10 @@ def test_argument_validation():
     assert _status(_params(dt=-1.0))[0] == -1
     assert _status(_params(h_min=0.05, h_max=0.04))[0] == -1
     assert _status(_params(per_particle=2))[0] == -1
+    for mode in (_lib.TV_LIMITED, _lib.TV_SCALED, _lib.TV_BACKGROUND):
+        assert _status(_params(tv_mode=mode))[0] == 0
+    assert _status(_params(tv_mode=3))[0] == -1
+    assert _status(_params(tv_mode=-1))[0] == -1
     L = _lib.load()
     assert L.sph_workspace_size(None, None) == -1
     assert b"cell grid" in L.sph_status_string(-4)

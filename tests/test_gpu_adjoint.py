@@ -92,15 +92,19 @@ def _step_loss(sim, c, base_snap):
                  + np.sum(c["rho"] * ex["rho"]))
 
 
-@pytest.mark.parametrize("name", list(INIT))
-def test_step_vjp_matches_fd(name):
+@pytest.mark.parametrize("name,mode", [(name, "limited") for name in INIT] +
+                         [("tg2d_jit", "scaled"), ("tg2d_jit", "background"),
+                          ("tg3d_jit", "background"), ("varres", "scaled")])
+def test_step_vjp_matches_fd(name, mode):
     """One kick-drift-kick step as a map of (r^n, v^n, a^n, rho^n, xi): the
     reverse step agrees with a central difference of the FP64 forward, with
-    the correction active (jittered input, limiter in all three branches)."""
+    the correction active (jittered input; the limited formulation with its
+    limiter in all three branches, the unlimited ones of Eq. 14 and Eq. 12,
+    where the latter has no xi and a 1/rho_i factor)."""
     import torch
     from paper_2411_13992_amd.adjoint import Adjoint, adjoint_step
     case = INIT[name]
-    sim = _sim(case, "f64")
+    sim = _sim(case, "f64", tv_mode=mode)
     d, n = sim.dim, sim.n
     rng = np.random.default_rng(5)
     start = sim.snapshot()
@@ -146,24 +150,31 @@ def test_step_vjp_matches_fd(name):
     assert np.array_equal(pattern[0], pattern[1]), "a limiter branch changed inside the difference"
     fd = (vals[0] - vals[1]) / (2 * eps)
     assert abs(pred - fd) <= 1e-6 * abs(fd), (pred, fd)
-    assert xi_bar.item() != 0.0
+    if mode == "background":
+        assert xi_bar.item() == 0.0
+    else:
+        assert xi_bar.item() != 0.0
 
 
-def _oracle_ke(case, pos, v0, xi, nsteps, tv_every=1):
-    st = oracle.State(case, pos=pos, vel=v0, xi=xi, tv_every=tv_every)
+def _oracle_ke(case, pos, v0, xi, nsteps, tv_every=1, tv_mode="limited"):
+    st = oracle.State(case, pos=pos, vel=v0, xi=xi, tv_every=tv_every, tv_mode=tv_mode)
     d = st.run(nsteps)
     return st.kinetic_energy(), d[:, 6]
 
 
-@pytest.mark.parametrize("dtype,tol", [("f64", 1e-6), ("f32", 1e-4)])
-def test_rollout_gradient_matches_oracle_fd(dtype, tol):
+@pytest.mark.parametrize("dtype,tol,mode", [("f64", 1e-6, "limited"), ("f32", 1e-4, "limited"),
+                                            ("f64", 1e-6, "scaled"),
+                                            ("f64", 1e-6, "background"),
+                                            ("f32", 1e-4, "background")])
+def test_rollout_gradient_matches_oracle_fd(dtype, tol, mode):
     """Gradient of KE(v^N) after 12 steps (checkpoints every 5: segments 5, 5, 2)
     with respect to v^0 (three random directions) and xi, against central
-    differences of the FP64 oracle started from the same particles."""
+    differences of the FP64 oracle started from the same particles, in each
+    transport-velocity formulation (the background one has no xi)."""
     import torch
     from paper_2411_13992_amd.adjoint import rollout, kinetic_energy
     case = cases.taylor_green_2d(16, jitter=0.15, seed=21, vel_perturb=0.01)
-    sim = _sim(case, dtype)
+    sim = _sim(case, dtype, tv_mode=mode)
     pos0 = sim.positions_fp64(sim.initial["cell"], sim.initial["off"])
     ids0 = sim.initial["id"].cpu().numpy()
     pos_by_id = np.empty_like(pos0)
@@ -180,9 +191,13 @@ def test_rollout_gradient_matches_oracle_fd(dtype, tol):
     for k in range(3):
         u = rng.normal(size=case.vel.shape)
         fd = central_fd(lambda e: _oracle_ke(case, pos_by_id, case.vel + e * u, case.xi,
-                                             nsteps), 1e-6)
+                                             nsteps, tv_mode=mode), 1e-6)
         assert abs(np.sum(gv * u) - fd) <= tol * abs(fd), (k, np.sum(gv * u), fd)
-    fd = central_fd(lambda e: _oracle_ke(case, pos_by_id, case.vel, case.xi + e, nsteps), 1e-6)
+    fd = central_fd(lambda e: _oracle_ke(case, pos_by_id, case.vel, case.xi + e, nsteps,
+                                         tv_mode=mode), 1e-6)
+    if mode == "background":
+        assert fd == 0.0 and gxi == 0.0
+        return
     assert fd != 0.0
     assert abs(gxi - fd) <= tol * abs(fd), (gxi, fd)
 
