@@ -30,12 +30,32 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pair interactions/s per TV-WCSPH step, FP32 vs FP64; adjoint/forward time"
 WORKLOAD = "tg2d_400"
+WORKLOADS = {
+    "tg2d_400": "2-D periodic Taylor-Green vortex, 400x400 lattice jittered +-0.05 dx "
+                "(160,000 particles), h = 1.3 dx, Wendland C2, Re = 100, c0 = 10 U, "
+                "transport-velocity correction with limiter every step, FP32 sweeps with "
+                "FP64 reductions",
+    "tg3d_128": "3-D periodic Taylor-Green vortex, 128^3 lattice jittered +-0.05 dx "
+                "(2,097,152 particles), h = 1.3 dx, Wendland C2, nu = 0.01, c0 = 10 U, "
+                "correction with limiter every step, FP32 sweeps with FP64 reductions",
+    "varres2d_1m": "2-D periodic variable-resolution box, smooth 2:1 smoothing-length "
+                   "profile, dp_min = 1/1306 (1,000,632 particles), jitter +-0.1 dp, "
+                   "low-speed random divergence-free flow, correction with limiter every "
+                   "step, FP32 sweeps with FP64 reductions",
+}
 
-# Algorithmic work per interacting pair and bytes per particle of the force
-# sweep (2-D): flops counted on the pair formula (FMA = 2), bytes = compulsory
-# per-particle reads (offsets 2, velocity 2, density 1) and writes (acceleration 2).
-FORCE_FLOPS_PER_PAIR_2D = 46
-FORCE_BYTES_PER_PARTICLE = {"f32": 28, "f64": 56}
+# Algorithmic work per interacting pair of the force sweep: the operations of
+# the pair formula (Eq. 2, 3b, 5-7) counted one per add, multiply, min/max,
+# reciprocal or reciprocal square root and two per FMA, without the summation
+# compensation: 50 in 2-D, 62 in 3-D.  Algorithmic bytes per particle: the
+# compulsory reads (offsets D, velocity D, density 1, plus mass and h with
+# per-particle resolution) and writes (acceleration D), once each.
+FORCE_FLOPS_PER_PAIR = {2: 50, 3: 62}
+
+
+def force_bytes_per_particle(dim: int, dtype: str, per_particle: bool) -> int:
+    words = 3 * dim + 1 + (2 if per_particle else 0)
+    return words * (8 if dtype == "f64" else 4)
 # Non-packed vector FP32 peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 # x 2 flops per FMA (packed FP32 math is not used).
 VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
@@ -94,7 +114,7 @@ def time_adjoint(sim, steps, every):
     return t_fwd, t_bwd
 
 
-def kernel_roofline(sim, pairs, dtype, reps=200):
+def kernel_roofline(sim, pairs, dtype, reps=200, use_pmc=True):
     """Average duration of the force sweep launch (sph_forces on the benchmark
     state, same kernel and launch shape as inside the step), by HIP events on
     the stream it runs on."""
@@ -102,10 +122,10 @@ def kernel_roofline(sim, pairs, dtype, reps=200):
     out = torch.empty_like(sim.acc)
     sim.forces(out=out)
     t = _events_time(lambda: sim.forces(out=out), reps)
-    flops = FORCE_FLOPS_PER_PAIR_2D * pairs
-    bytes_ = FORCE_BYTES_PER_PARTICLE[dtype] * sim.n
+    flops = FORCE_FLOPS_PER_PAIR[sim.dim] * pairs
+    bytes_ = force_bytes_per_particle(sim.dim, dtype, sim.var) * sim.n
     achieved = flops / t / 1e12
-    traffic = _pmc_traffic()
+    traffic = _pmc_traffic() if use_pmc else None
     return {
         "kernel": "forces_kernel",
         "bound": "alu",
@@ -174,6 +194,9 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--workload", default=WORKLOAD, choices=sorted(WORKLOADS),
+                    help="the 2-D benchmark workload (default) or one of the larger "
+                         "parity workloads, reported on the same line format")
     ap.add_argument("--pmc", action="store_true",
                     help="counter run: 20 force-sweep launches on the benchmark state and one "
                          "64 MiB device copy of known size (for rocprofv3 --pmc)")
@@ -186,7 +209,8 @@ def main():
     import cases
     from paper_2411_13992_amd import Simulation
 
-    case = cases.make(WORKLOAD)
+    case = cases.make(args.workload)
+    default = args.workload == WORKLOAD
     sim = Simulation.from_case(case, dtype="f32")
     if args.pmc:
         sim.run(args.warmup)
@@ -200,11 +224,15 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"pmc_run": True, "force_launches": 20, "copy_bytes": PMC_COPY_BYTES}))
         return
-    t32, pairs = time_steps(sim, args.steps, args.warmup)
-    roof = kernel_roofline(sim, pairs, "f32")
+    steps, warmup = args.steps, args.warmup
+    if not default:     # 10-30x the work per step: keep the timed region short
+        steps, warmup = max(steps // 10, 5), max(warmup // 10, 2)
+    t32, pairs = time_steps(sim, steps, warmup)
+    roof = kernel_roofline(sim, pairs, "f32", reps=200 if default else 20, use_pmc=default)
     flags32 = sim.flags()
+    del sim
     sim64 = Simulation.from_case(case, dtype="f64")
-    t64, pairs64 = time_steps(sim64, max(args.steps // 2, 1), max(args.warmup // 2, 1))
+    t64, pairs64 = time_steps(sim64, max(steps // 2, 1), max(warmup // 2, 1))
     del sim64
     simadj = Simulation.from_case(case, dtype="f32")
     t_fwd, t_bwd = time_adjoint(simadj, 40, 20)
@@ -214,18 +242,15 @@ def main():
         "value": pairs / t32,
         "unit": "pair-interactions/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": t32 * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "2-D periodic Taylor-Green vortex, 400x400 lattice jittered "
-                               "+-0.05 dx (160,000 particles), h = 1.3 dx, Wendland C2, "
-                               "Re = 100, c0 = 10 U, transport-velocity correction with "
-                               "limiter every step, FP32 sweeps with FP64 reductions",
+        "config": {"workload": WORKLOADS[args.workload], "name": args.workload,
                    "particles": case.n, "pairs_per_step": pairs, "dt": case.dt},
         "fp64": {"value": pairs64 / t64, "ms_per_step": t64 * 1e3,
                  "fp32_speedup": t64 / t32},
@@ -238,6 +263,8 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
+    else:
+        out["cpu_baseline"] = None
     print(json.dumps(out))
 
 

@@ -16,8 +16,12 @@ Conventions (shared by every case):
 * reference density rho0 = 1; particle mass m = rho0 * dp^D (the particle
   volume of the variable-resolution discussion in Sec. 2.4), smoothing length
   h = 1.3 dp (Sec. 4, first paragraph);
-* the fixed time step is the acoustic criterion of Eq. (11) with the maximum
-  speed replaced by the reference speed: dt = 0.6 h_min / (U_ref + c0);
+* the fixed time step is the smaller of the two criteria of Eq. (9)-(11) with
+  the maximum speed replaced by the reference speed: the acoustic
+  0.6 h_min / (U_ref + c0) and the advection 0.25 h_min / max(U_ref, nu / h_min),
+  whose nu / h term bounds the explicit viscous step (it decides only in the
+  low-speed variable-resolution box; every Taylor-Green case takes the
+  acoustic step);
 * c0 = 10 U_ref (Sec. 2.1, the artificial sound speed);
 * the transport-velocity constants are those of Sec. 3: xi = -0.2 (Eq. 14/16),
   limiter C = 1e3 and threshold 5e-4 (Eq. 15); the Riemann dissipation limiter
@@ -37,6 +41,7 @@ __all__ = [
 
 H_OVER_DP = 1.3          # Sec. 4: h = 1.3 dp
 CFL_AC = 0.6             # Eq. (11) constant
+CFL_AD = 0.25            # Eq. (9) constant
 XI = -0.2                # Eq. (14) and (16)
 LIMITER_C = 1.0e3        # Eq. (15)
 LIMITER_S0 = 5.0e-4      # Eq. (15) threshold
@@ -111,8 +116,10 @@ def _jitter(pos: np.ndarray, amp: np.ndarray | float, seed: int, box) -> np.ndar
     return out
 
 
-def _dt(h_min: float, u_ref: float, c0: float) -> float:
-    return CFL_AC * h_min / (u_ref + c0)
+def _dt(h_min: float, u_ref: float, c0: float, nu: float) -> float:
+    acoustic = CFL_AC * h_min / (u_ref + c0)
+    advection = CFL_AD * h_min / max(u_ref, nu / h_min)
+    return min(acoustic, advection)
 
 
 def taylor_green_2d(n: int, jitter: float = 0.0, seed: int = 1, re: float = 100.0,
@@ -144,7 +151,7 @@ def taylor_green_2d(n: int, jitter: float = 0.0, seed: int = 1, re: float = 100.
     mass = np.full(n * n, rho0 * dx * dx)
     return Case(name=name or f"tg2d_{n}", dim=2, pos=pos, vel=vel, mass=mass, h=h,
                 box=box, dx=dx, rho0=rho0, c0=c0, eta=eta, u_ref=u,
-                dt=_dt(H_OVER_DP * dx, u, c0), steps=steps, uniform=True,
+                dt=_dt(H_OVER_DP * dx, u, c0, eta / rho0), steps=steps, uniform=True,
                 extra={"re": re, "jitter": jitter, "seed": seed})
 
 
@@ -169,7 +176,7 @@ def taylor_green_3d(n: int, jitter: float = 0.05, seed: int = 1, nu: float = 0.0
     mass = np.full(n ** 3, rho0 * dx ** 3)
     return Case(name=name or f"tg3d_{n}", dim=3, pos=pos, vel=vel, mass=mass, h=h,
                 box=box, dx=dx, rho0=rho0, c0=c0, eta=rho0 * nu, u_ref=u,
-                dt=_dt(H_OVER_DP * dx, u, c0), steps=steps, uniform=True,
+                dt=_dt(H_OVER_DP * dx, u, c0, nu), steps=steps, uniform=True,
                 extra={"jitter": jitter, "seed": seed})
 
 
@@ -238,7 +245,7 @@ def variable_resolution_2d(dp_min: float = 1.0 / 1306, jitter: float = 0.1, seed
     mass = rho0 * vol
     return Case(name=name or "varres2d", dim=2, pos=pos, vel=vel, mass=mass, h=h,
                 box=box, dx=float(dp.min()), rho0=rho0, c0=c0, eta=rho0 * nu, u_ref=u,
-                dt=_dt(float(h.min()), u, c0), steps=steps, uniform=False,
+                dt=_dt(float(h.min()), u, c0, nu), steps=steps, uniform=False,
                 extra={"jitter": jitter, "seed": seed, "columns": len(widths)})
 
 
