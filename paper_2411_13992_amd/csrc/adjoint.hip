@@ -55,6 +55,15 @@ __global__ __launch_bounds__(kBlock) void force_vjp_kernel(
   const int n = g.n;
   const Cols<T, D> offc(off, n), velc(vel, n), abarc(a_bar, n);
   const Cols<T, 1> rhoc(rho, n), hc(hh, n), mc(mass, n);
+  // candidate-test values: offsets, then h (variable resolution)
+  constexpr int NS = D + (VAR ? 1 : 0);
+  auto srct = [&](int j, T* v) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) v[d] = offc(d, j);
+    if constexpr (VAR) v[D] = hc(0, j);
+  };
+  __shared__ Stage<D, T, NS, StageCap<D, T>::value> st;
+  stage_positions<D, G>(g, cell, cs, st, srct);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   const bool valid = i < n;
@@ -78,15 +87,15 @@ __global__ __launch_bounds__(kBlock) void force_vjp_kernel(
     const T pi = k.c0sq * (rhoi - k.rho0);
     const T hi = VAR ? hh[i] : k.h;
     const T mi = VAR ? mass[i] : k.mass;
-    auto test = [&](int j, const T* sh) -> bool {
+    auto test = [&](int j, const T* v, const T* sh) -> bool {
       if (j == i) return false;
       T r2 = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        const T rv = (oi[d] - offc(d, j)) - sh[d];
+        const T rv = (oi[d] - v[d]) - sh[d];
         r2 = tfma(rv, rv, r2);
       }
-      return r2 < pair_h<D, T, VAR>(k, hi, VAR ? hc(0, j) : T(0)).sup2;
+      return r2 < pair_h<D, T, VAR>(k, hi, VAR ? v[D] : T(0)).sup2;
     };
     auto body = [&](int j, const T* sh) {
       T r[3];
@@ -137,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void force_vjp_kernel(
       }
       pb.add(-Cc * Bw * inv_rhoi - Cc * (T(0.5) * k.c0sq + T(0.25) * br * k.c0 * du) * rw);
     };
-    for_each_neighbour_listed<D, G, T, VjpCap<G>::value>(g, k, cell[i], cs, sub, nl, test, body);
+    for_each_neighbour_listed<D, G, T, NS>(g, k, cell[i], cs, sub, st, nl, srct, test, body);
   }
   T rbs[3], vbs[3];
 #pragma unroll

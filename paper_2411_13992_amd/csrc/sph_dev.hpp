@@ -369,16 +369,124 @@ __device__ __forceinline__ int wave_claim_slot(bool valid, int c, int* __restric
   return base + (lane - start);
 }
 
+// ---------------------------------------------------------------- position staging
+// A block serves kBlock / G consecutive particles of the (cell, id) order, so
+// their cells form one range [cf, cl] of linear cell indices.  For each
+// stencil offset (dy, dz) the cells they reach lie in the circular range
+// [cf + o - 1, cl + o + 1], o = dy nx + dz nx ny (except cells reached across
+// the periodic x seam), and the particles of a circular cell range are one
+// circular run of particle indices.  stage_positions copies each run that
+// fits in CAP slots into LDS once, with coalesced reads, as records of the NS
+// values the candidate test needs; the compacted walk's test phase then reads
+// LDS when every lane's cell of the wavefront is staged, global memory
+// otherwise.  The values are the same either way.
+template <int D>
+struct Ranges { static constexpr int value = D == 3 ? 9 : 3; };
+
+// Slots per staged range, 0 to stage nothing.  Staging pays for the 2-D FP32
+// force sweeps (a block of 128 particles reaches ~21 cells of ~7 particles per
+// range, ~150 particles, up to ~220); larger FP64 and 3-D stages would cut
+// occupancy.
+template <int D, typename T>
+struct StageCap { static constexpr int value = (D == 2 && sizeof(T) == 4) ? 256 : 0; };
+
+template <int D, typename T, int NS, int CAP_>
+struct Stage {
+  static constexpr int R = Ranges<D>::value;
+  static constexpr int CAP = CAP_;
+  static constexpr int W = NS == 3 ? 4 : NS;          // record width (power of 2)
+  struct alignas(W * sizeof(T)) Rec { T w[W]; };
+  Rec rec[CAP > 0 ? R * CAP : 1];
+  int pstart[R];   // first particle of range r's run
+  int plen[R];     // particles staged for range r (0: not staged)
+  int clo[R];      // first cell of range r
+  int cspan[R];    // (last cell - first cell) mod ncells
+};
+
+// Fills st for this block; every thread of the block calls it (it
+// synchronises the block when CAP > 0).  src(j, v) reads particle j's NS values.
+template <int D, int G, typename T, int NS, int CAP, typename Src>
+__device__ __forceinline__ void stage_positions(const Grid& g, const int* __restrict__ cell,
+                                                const int* __restrict__ cs,
+                                                Stage<D, T, NS, CAP>& st, Src&& src) {
+  if constexpr (CAP > 0) {
+    constexpr int R = Stage<D, T, NS, CAP>::R;
+    const int n = g.n, nc = g.ncells;
+    const int p0 = blockIdx.x * (kBlock / G);
+    const int p1 = min(p0 + kBlock / G, n);
+    if (threadIdx.x < R) {
+      const int r = threadIdx.x;
+      int ps = 0, len = 0, lo = 0, span = 0;
+      if (p0 < n) {
+        const int dy = r % 3 - 1, dz = (D == 3) ? r / 3 - 1 : 0;
+        const int o = dy * g.nc[0] + dz * g.nc[0] * g.nc[1];
+        const int cf = cell[p0], cl = cell[p1 - 1];
+        lo = ((cf + o - 1) % nc + nc) % nc;
+        const int hi = ((cl + o + 1) % nc + nc) % nc;
+        span = hi - lo + (hi < lo ? nc : 0);
+        if (span + 1 < nc) {
+          ps = cs[lo];
+          const int cnt = cs[hi + 1] - ps + (hi < lo ? n : 0);
+          if (cnt <= CAP) len = cnt;
+        }
+      }
+      st.pstart[r] = ps;
+      st.plen[r] = len;
+      st.clo[r] = lo;
+      st.cspan[r] = span;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int len = st.plen[r], ps = st.pstart[r];
+      for (int t = threadIdx.x; t < len; t += kBlock) {
+        int j = ps + t;
+        j -= (j >= n) ? n : 0;
+        T v[NS];
+        src(j, v);
+        typename Stage<D, T, NS, CAP>::Rec rc;
+#pragma unroll
+        for (int q = 0; q < Stage<D, T, NS, CAP>::W; ++q) rc.w[q] = q < NS ? v[q] : T(0);
+        st.rec[r * CAP + t] = rc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// kNotStaged if cell cc (reached with stencil range r, first particle b) is
+// not staged, else delta such that particle j of cc sits in slot j + delta
+// (delta = r CAP - first particle of the run, plus n past the end of the
+// order: either sign).
+constexpr int kNotStaged = -2147483647 - 1;
+
+template <int D, typename T, int NS, int CAP>
+__device__ __forceinline__ int staged_delta(const Grid& g, const Stage<D, T, NS, CAP>& st, int r,
+                                            int cc, int b) {
+  if constexpr (CAP == 0) {
+    return kNotStaged;
+  } else {
+    int rel = cc - st.clo[r];
+    rel += rel < 0 ? g.ncells : 0;
+    if (st.plen[r] == 0 || rel > st.cspan[r]) return kNotStaged;
+    int off = b - st.pstart[r];
+    off += off < 0 ? g.n : 0;
+    return r * CAP + off - b;
+  }
+}
+
 // ---------------------------------------------------------------- compacted walk
 // Neighbour walk in two phases for sweeps whose pair body is expensive.  The
-// scan phase tests every candidate with test(j, shift) (positions only) and
-// appends the hits to this thread's list in LDS; the body phase then runs
-// body(j, shift) over the list alone, so the wavefront executes the body once
-// per neighbour instead of once per candidate.  The list is flushed after each
-// z-plane of cells (once in 2-D) and whenever it fills.  An entry is j in
-// bits 0-27, dx + 1 in bits 28-29 and dy + 1 in bits 30-31.
-// The visiting order is that of for_each_candidate, so sums over the listed
-// pairs are bit-identical to sums over a plain walk.
+// scan phase tests every candidate with test(j, v, shift), v the NS staged
+// values of j (positions, and h with per-particle resolution; from the
+// position stage or from src), and appends the hits to this thread's list in
+// LDS; the body phase then runs body(j, shift) over the list alone, so the
+// wavefront executes the body once per neighbour instead of once per
+// candidate.  The list is flushed after each z-plane of cells (once in 2-D)
+// and whenever it fills.  An entry is j in bits 0-27, dx + 1 in bits 28-29
+// and dy + 1 in bits 30-31.  The visiting order is that of
+// for_each_candidate, so sums over the listed pairs are bit-identical to sums
+// over a plain walk.
 constexpr int kListBits = 28;
 constexpr unsigned kListMask = (1u << kListBits) - 1u;
 
@@ -387,10 +495,13 @@ struct NeighbourList {
   unsigned slot[CAP][kBlock];   // [entry][thread]: one bank per thread
 };
 
-template <int D, int G, typename T, int CAP, typename Test, typename Body>
+template <int D, int G, typename T, int NS, int SCAP, int CAP, typename Src, typename Test,
+          typename Body>
 __device__ __forceinline__ void for_each_neighbour_listed(const Grid& g, const Coeffs<T>& k,
                                                           int cell, const int* __restrict__ cs,
-                                                          int sub, NeighbourList<CAP>& nl,
+                                                          int sub,
+                                                          const Stage<D, T, NS, SCAP>& st,
+                                                          NeighbourList<CAP>& nl, Src&& src,
                                                           Test&& test, Body&& body) {
   int c[3];
   decode_cell<D>(g, cell, c);
@@ -416,17 +527,33 @@ __device__ __forceinline__ void for_each_neighbour_listed(const Grid& g, const C
     for (int dy = -1; dy <= 1; ++dy) {
       const int y = wrap_index(c[1] + dy, g.nc[1]);
       const int row = g.nc[0] * (y + g.nc[1] * z);
+      const int r = (dy + 1) + 3 * (dz - zlo);
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
         const int cc = row + wrap_index(c[0] + dx, g.nc[0]);
         const int b = cs[cc];
         const int e = cs[cc + 1];
+        const int delta = staged_delta<D>(g, st, r, cc, b);
         const T shift[3] = {T(dx) * k.L[0], T(dy) * k.L[1], sz};
         const unsigned code = (unsigned)((dx + 1) | ((dy + 1) << 2)) << kListBits;
-        for (int j = b + sub; j < e; j += G) {
-          if (test(j, shift)) {
-            nl.slot[cnt][tid] = (unsigned)j | code;
-            if (++cnt == CAP) flush();
+        // one source per wavefront and cell: the stage when every lane's cell
+        // is staged, else global memory for all lanes
+        if (__all(delta != kNotStaged)) {
+          for (int j = b + sub; j < e; j += G) {
+            const auto rc = st.rec[j + delta];
+            if (test(j, rc.w, shift)) {
+              nl.slot[cnt][tid] = (unsigned)j | code;
+              if (++cnt == CAP) flush();
+            }
+          }
+        } else {
+          for (int j = b + sub; j < e; j += G) {
+            T v[NS];
+            src(j, v);
+            if (test(j, v, shift)) {
+              nl.slot[cnt][tid] = (unsigned)j | code;
+              if (++cnt == CAP) flush();
+            }
           }
         }
       }

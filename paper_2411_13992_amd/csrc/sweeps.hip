@@ -169,6 +169,15 @@ __device__ __forceinline__ void forces_impl(
   const int n = g.n;
   const Cols<T, D> offc(off, n), velc(vel, n);
   const Cols<T, 1> rhoc(rho, n), hc(hh, n), mc(mass, n);
+  // candidate-test values: offsets, then h (variable resolution)
+  constexpr int NS = D + (VAR ? 1 : 0);
+  auto srct = [&](int j, T* v) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) v[d] = offc(d, j);
+    if constexpr (VAR) v[D] = hc(0, j);
+  };
+  __shared__ Stage<D, T, NS, StageCap<D, T>::value> st;
+  stage_positions<D, G>(g, cell, cs, st, srct);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   const bool valid = i < n;
@@ -193,15 +202,15 @@ __device__ __forceinline__ void forces_impl(
     rhoi = rho[i];
     const T pi = k.c0sq * (rhoi - k.rho0);
     const T hi = VAR ? hh[i] : k.h;
-    auto test = [&](int j, const T* sh) -> bool {
+    auto test = [&](int j, const T* v, const T* sh) -> bool {
       if (j == i) return false;
       T r2 = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        const T rv = (oi[d] - offc(d, j)) - sh[d];
+        const T rv = (oi[d] - v[d]) - sh[d];
         r2 = tfma(rv, rv, r2);
       }
-      return r2 < pair_h<D, T, VAR>(k, hi, VAR ? hc(0, j) : T(0)).sup2;
+      return r2 < pair_h<D, T, VAR>(k, hi, VAR ? v[D] : T(0)).sup2;
     };
     auto body = [&](int j, const T* sh) {
       T rv[3];
@@ -239,7 +248,7 @@ __device__ __forceinline__ void forces_impl(
         for (int d = 0; d < D; ++d) tv[d].add(w * rv[d]);
       }
     };
-    for_each_neighbour_listed<D, G, T, ForceCap<G>::value>(g, k, celli, cs, sub, nl, test, body);
+    for_each_neighbour_listed<D, G, T, NS>(g, k, celli, cs, sub, st, nl, srct, test, body);
   }
   const T s = T(2) / rhoi;
   bool bad = false;
