@@ -207,11 +207,13 @@ int32_t sph_kdk_step(const sph_params *p, sph_particles *parts, int32_t *cell_st
  * the correction sum of step n+1 at the same positions and densities (the
  * pairs, kernel values and volumes of Eq. 14 are those of the force sum),
  * then applies the second half kick of step n and the first half kick,
- * correction and drift of step n+1.  diag (optional, device) receives
- * nsteps rows of SPH_NDIAG doubles, one per step.  No tape. */
+ * correction and drift of step n+1.  tapes (optional, device, nsteps *
+ * sph_tape_size bytes) receive one tape per step, byte-identical to those of
+ * nsteps sph_kdk_step calls.  diag (optional, device) receives nsteps rows of
+ * SPH_NDIAG doubles, one per step. */
 int32_t sph_kdk_run(const sph_params *p, sph_particles *parts, int32_t *cell_start,
                     int64_t step_index, int64_t nsteps, void *ws, size_t ws_bytes,
-                    double *diag, void *stream);
+                    void *tapes, double *diag, void *stream);
 
 /* Diagnostics of the current state alone (KE, momentum, max|v|, pairs);
  * entries 6-8 are zero. */

@@ -96,7 +96,7 @@ def load():
         "sph_kdk_step": [pp, P(SphParticles), vp, ctypes.c_int64, vp, ctypes.c_size_t, vp, vp,
                          vp],
         "sph_kdk_run": [pp, P(SphParticles), vp, ctypes.c_int64, ctypes.c_int64, vp,
-                        ctypes.c_size_t, vp, vp],
+                        ctypes.c_size_t, vp, vp, vp],
         "sph_diagnostics": [pp, P(SphParticles), vp, vp, ctypes.c_size_t, vp, vp],
         "sph_adjoint_step": [pp, vp, P(SphAdjoint), vp, vp, ctypes.c_size_t, vp],
         "sph_adjoint_init": [pp, P(SphParticles), vp, P(SphAdjoint), vp, ctypes.c_size_t, vp],

@@ -3,9 +3,9 @@ respect to the initial velocities and the correction coefficient xi (Eq. 14/16).
 
 Forward: N kick-drift-kick steps, keeping a state checkpoint every K steps.
 Backward: for each segment, last first, restore its checkpoint, recompute its
-K steps recording a tape per step (sph_kdk_step with a tape), then run the
-reverse steps (sph_adjoint_step) from the last step of the segment back to
-its first.  The initial evaluation (rho^0 by summation, a^0 from v^0) is
+K steps in one fused run recording a tape per step (sph_kdk_run with tapes),
+then run the reverse steps (sph_adjoint_step) from the last step of the
+segment back to its first.  The initial evaluation (rho^0 by summation, a^0 from v^0) is
 reversed last (sph_adjoint_init).  The neighbour sets are held fixed within
 a step (the C2 kernel and its first two derivatives vanish at the support
 edge), and the limiter's jump at s0 contributes no derivative.
@@ -79,8 +79,7 @@ def backward_run(sim: Simulation, ckpts: list, nsteps: int, every: int,
         start = seg * every
         stop = min(start + every, nsteps)
         sim.restore(ckpts[seg])
-        for s in range(start, stop):
-            sim.step(1, diag=False, tape=tapes[s - start])
+        sim.run(stop - start, diag=False, tapes=tapes)
         for s in reversed(range(start, stop)):
             adjoint_step(sim, tapes[s - start], adj, xi_bar)
     sim.restore(ckpts[0])

@@ -323,9 +323,14 @@ int32_t build_cells_t(const sph_params* p, sph_particles* parts, int32_t* cs, in
 // standalone kernel; every later step takes both from the fused force sweep of
 // the step before.  The last step finishes with the standalone kick.  Per step:
 // scan, scatter, rank + gather, density, forces (fused except the last).
+// With tapes (nsteps consecutive tapes of tape_layout size), step s records
+// its state before the step, its correction sum and limiter value (from the
+// standalone sweep for the first step, from the fused force sweep of the
+// step before for the others), the cell-build permutation and its state after
+// the density sweep; the state after step s is the state before step s + 1.
 template <typename T>
 int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int64_t step0,
-                    int64_t nsteps, char* ws, char* tape, double* diag, hipStream_t stream) {
+                    int64_t nsteps, char* ws, char* tapes, double* diag, hipStream_t stream) {
   const bool var = is_var(p);
   const Sizes sz = sizes_of(p, var);
   const WsLayout w = ws_layout(sz);
@@ -344,20 +349,34 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
   const size_t n = (size_t)sz.n, dn = (size_t)sz.dim * n, t = sz.tsz;
   const size_t csb = sizeof(int) * ((size_t)sz.ncells + 1);
   auto applies = [&](int64_t s) { return p->tv_every > 0 && (s % p->tv_every) == 0; };
-  TapeLayout tl;
-  if (tape) {
-    tl = tape_layout(sz);
+  const TapeLayout tl = tape_layout(sz);
+  auto tape_of = [&](int64_t s) { return tapes + (size_t)s * tl.total; };
+  // the sorted state (cell, offsets, density, mass, h, cell_start) into a tape
+  auto record_state = [&](char* tp, size_t o_cell, size_t o_off, size_t o_rho, size_t o_mass,
+                          size_t o_h, size_t o_cs) {
     hipError_t e = hipSuccess;
-    e = e ? e : copy_d2d(tape + tl.pre_cell, a.cell, sizeof(int) * n, stream);
-    e = e ? e : copy_d2d(tape + tl.pre_off, a.off, t * dn, stream);
-    e = e ? e : copy_d2d(tape + tl.pre_rho, a.rho, t * n, stream);
+    e = e ? e : copy_d2d(tp + o_cell, a.cell, sizeof(int) * n, stream);
+    e = e ? e : copy_d2d(tp + o_off, a.off, t * dn, stream);
+    e = e ? e : copy_d2d(tp + o_rho, a.rho, t * n, stream);
     if (var) {
-      e = e ? e : copy_d2d(tape + tl.pre_mass, a.mass, t * n, stream);
-      e = e ? e : copy_d2d(tape + tl.pre_h, a.h, t * n, stream);
+      e = e ? e : copy_d2d(tp + o_mass, a.mass, t * n, stream);
+      e = e ? e : copy_d2d(tp + o_h, a.h, t * n, stream);
     }
-    e = e ? e : copy_d2d(tape + tl.pre_cs, cs, csb, stream);
-    if (e != hipSuccess) return SPH_E_HIP;
-  }
+    e = e ? e : copy_d2d(tp + o_cs, cs, csb, stream);
+    return e;
+  };
+  auto record_pre = [&](char* tp) {
+    return record_state(tp, tl.pre_cell, tl.pre_off, tl.pre_rho, tl.pre_mass, tl.pre_h,
+                        tl.pre_cs);
+  };
+  auto record_post = [&](char* tp) {
+    hipError_t e = record_state(tp, tl.post_cell, tl.post_off, tl.post_rho, tl.post_mass,
+                                tl.post_h, tl.post_cs);
+    e = e ? e : copy_d2d(tp + tl.perm, perm, sizeof(int) * n, stream);
+    e = e ? e : copy_d2d(tp + tl.post_vhalf, a.vel, t * dn, stream);
+    return e;
+  };
+  if (tapes && record_pre(tape_of(0)) != hipSuccess) return SPH_E_HIP;
   launch_fill(stream, counts, cb.fill_ints, 0);
   if (diag) launch_zero_partials(stream, sz.nblk, part[0]);
 
@@ -365,12 +384,12 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
   T* dr = nullptr;
   if (applies(step0)) {
     dr = (T*)(ws + w.dr);
-    launch_tv<T>(l, g, k, a, cs, dr, tape ? (T*)(tape + tl.beta) : nullptr, nullptr,
-                 tape ? (T*)(tape + tl.g) : nullptr, diag ? part[0] : nullptr);
-  } else if (tape) {
+    launch_tv<T>(l, g, k, a, cs, dr, tapes ? (T*)(tapes + tl.beta) : nullptr, nullptr,
+                 tapes ? (T*)(tapes + tl.g) : nullptr, diag ? part[0] : nullptr);
+  } else if (tapes) {
     // no correction this step: record g = 0, beta = 0 (the reverse then adds nothing)
-    launch_zero<T>(stream, (T*)(tape + tl.g), (long)dn);
-    launch_zero<T>(stream, (T*)(tape + tl.beta), (long)n);
+    launch_zero<T>(stream, (T*)(tapes + tl.g), (long)dn);
+    launch_zero<T>(stream, (T*)(tapes + tl.beta), (long)n);
   }
   launch_drift<T>(l, g, k, a, dr, stg, counts, slot, flags);
 
@@ -392,6 +411,12 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
     launch_rank_gather<T>(l, sz.n, st, src, dst, perm);
     // 4. density summation (Eq. 8)
     launch_density<T>(l, g, k, a, cs, a.rho, cur, nullptr, flags);
+    if (tapes) {
+      // the state after this step (half-step velocity, new density) is the
+      // state before the next
+      if (record_post(tape_of(s)) != hipSuccess) return SPH_E_HIP;
+      if (s + 1 < nsteps && record_pre(tape_of(s + 1)) != hipSuccess) return SPH_E_HIP;
+    }
     if (s + 1 < nsteps) {
       // 5-6. accelerations, 7. kick; the next step's correction and drift
       FusedOut<T> fo;
@@ -401,24 +426,22 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
       fo.slot = slot;
       fo.part_cur = cur;
       fo.part_next = nxt;
+      fo.g_next = nullptr;
+      fo.beta_next = nullptr;
+      if (tapes) {
+        char* tn = tape_of(s + 1);
+        if (fo.apply_next) {
+          fo.g_next = (T*)(tn + tl.g);
+          fo.beta_next = (T*)(tn + tl.beta);
+        } else {
+          launch_zero<T>(stream, (T*)(tn + tl.g), (long)dn);
+          launch_zero<T>(stream, (T*)(tn + tl.beta), (long)n);
+        }
+      }
       launch_forces_fused<T>(l, g, k, a, cs, fo, flags);
     } else {
       // 5-6. accelerations at (r^{n+1}, v', rho^{n+1}), 7. second half kick
       launch_forces<T>(l, g, k, a, cs, a.vel, a.acc, flags);
-      if (tape) {
-        hipError_t e = hipSuccess;
-        e = e ? e : copy_d2d(tape + tl.perm, perm, sizeof(int) * n, stream);
-        e = e ? e : copy_d2d(tape + tl.post_cell, a.cell, sizeof(int) * n, stream);
-        e = e ? e : copy_d2d(tape + tl.post_off, a.off, t * dn, stream);
-        e = e ? e : copy_d2d(tape + tl.post_vhalf, a.vel, t * dn, stream);
-        e = e ? e : copy_d2d(tape + tl.post_rho, a.rho, t * n, stream);
-        if (var) {
-          e = e ? e : copy_d2d(tape + tl.post_mass, a.mass, t * n, stream);
-          e = e ? e : copy_d2d(tape + tl.post_h, a.h, t * n, stream);
-        }
-        e = e ? e : copy_d2d(tape + tl.post_cs, cs, csb, stream);
-        if (e != hipSuccess) return SPH_E_HIP;
-      }
       launch_kick<T>(l, k, sz.n, a.vel, a.acc, a.mass, cur, true, flags);
       if (diag) launch_diag_fold(stream, DiagFold{cur, sz.nblk * kWavesPerBlock, diag + (size_t)SPH_NDIAG * s});
     }
@@ -695,9 +718,9 @@ int32_t sph_kdk_step(const sph_params* p, sph_particles* parts, int32_t* cell_st
 }
 
 int32_t sph_kdk_run(const sph_params* p, sph_particles* parts, int32_t* cell_start,
-                    int64_t step_index, int64_t nsteps, void* ws, size_t ws_bytes, double* diag,
-                    void* stream) {
-  return kdk_common(p, parts, cell_start, step_index, nsteps, ws, ws_bytes, nullptr, diag, stream);
+                    int64_t step_index, int64_t nsteps, void* ws, size_t ws_bytes, void* tapes,
+                    double* diag, void* stream) {
+  return kdk_common(p, parts, cell_start, step_index, nsteps, ws, ws_bytes, tapes, diag, stream);
 }
 
 int32_t sph_diagnostics(const sph_params* p, const sph_particles* parts, const int32_t* cell_start,

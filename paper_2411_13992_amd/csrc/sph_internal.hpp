@@ -55,6 +55,8 @@ struct FusedOut {
   int* slot;
   double* part_cur;    // null: no diagnostics
   double* part_next;
+  T* g_next;           // null: no tape; else the next step's correction sum g [D][N]
+  T* beta_next;        // and limiter value [N] (written when apply_next)
 };
 
 // ---- sweeps (sweeps.hip)

@@ -283,6 +283,11 @@ __device__ __forceinline__ void forces_impl(
       v[4] = sqrt(v2);
       if (fo.apply_next) {
         const Limited lim = limit_correction<D>(k, gi, rhoi, dr);
+        if (fo.g_next) {
+#pragma unroll
+          for (int d = 0; d < D; ++d) fo.g_next[d * n + i] = gi[d];
+          fo.beta_next[i] = (T)lim.beta;
+        }
         double d2 = 0.0;
 #pragma unroll
         for (int d = 0; d < D; ++d) d2 += (double)dr[d] * (double)dr[d];

@@ -200,11 +200,13 @@ class Simulation:
                       _vp(self.diag) if diag else None, s)
             self.step_index += 1
 
-    def run(self, nsteps: int, diag=True) -> torch.Tensor | None:
+    def run(self, nsteps: int, diag=True, tapes: torch.Tensor | None = None) -> torch.Tensor | None:
         """nsteps steps in one fused call (sph_kdk_run).  diag: True keeps every
         step's diagnostics (returned as an (nsteps, 9) FP64 device tensor, the
         last row also in self.diag), False skips them, or a preallocated
-        (nsteps, 9) FP64 device tensor to fill."""
+        (nsteps, 9) FP64 device tensor to fill.  tapes: optional uint8 device
+        tensor of at least nsteps x tape_bytes() bytes (one tape per step,
+        contiguous)."""
         if nsteps <= 0:
             return None
         if diag is True:
@@ -213,9 +215,13 @@ class Simulation:
             d = None
         else:
             d = diag
+        if tapes is not None:
+            if (tapes.dtype != torch.uint8 or not tapes.is_contiguous()
+                    or tapes.numel() < nsteps * self.tape_bytes()):
+                raise ValueError("tapes must be a contiguous uint8 tensor of nsteps x tape_bytes()")
         _lib.call("sph_kdk_run", ctypes.byref(self.params), ctypes.byref(self.parts()),
-                  _vp(self.cs), self.step_index, nsteps, _vp(self.ws), self.ws_bytes, _vp(d),
-                  _stream())
+                  _vp(self.cs), self.step_index, nsteps, _vp(self.ws), self.ws_bytes,
+                  _vp(tapes), _vp(d), _stream())
         if d is not None:
             self.diag.copy_(d[-1])
         self.step_index += nsteps

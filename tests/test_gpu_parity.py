@@ -310,6 +310,34 @@ def test_fused_run_equals_single_steps(name, dtype, tv_every):
     assert a.flags() == 0 and b.flags() == 0
 
 
+@pytest.mark.parametrize("name,dtype,mode", [("jitter64", "f32", "limited"),
+                                             ("jitter64", "f64", "limited"),
+                                             ("tg3d_12", "f32", "limited"),
+                                             ("varres_small", "f32", "limited"),
+                                             ("jitter64", "f32", "background")])
+@pytest.mark.parametrize("tv_every", [1, 3])
+def test_fused_run_tapes_equal_single_step_tapes(name, dtype, mode, tv_every):
+    """The tapes a fused run records (correction sums from the fused force
+    sweep, states shared between consecutive steps) are byte-identical to
+    those of the same number of single steps."""
+    import torch
+    case = SMALL[name]
+    a = _sim(case, dtype, tv_every=tv_every, tv_mode=mode)
+    b = _sim(case, dtype, tv_every=tv_every, tv_mode=mode)
+    nsteps, tb = 5, a.tape_bytes()
+    # both start zeroed, so the never-written alignment padding compares equal
+    ta = torch.zeros((nsteps, tb), dtype=torch.uint8, device=a.device)
+    tb_ = torch.zeros((nsteps, tb), dtype=torch.uint8, device=b.device)
+    for s in range(nsteps):
+        a.step(1, tape=ta[s])
+    b.run(nsteps, diag=False, tapes=tb_)
+    torch.cuda.synchronize()
+    for s in range(nsteps):
+        assert torch.equal(ta[s], tb_[s]), s
+    for key in ("cell", "id", "off", "vel", "acc", "rho", "cs"):
+        assert torch.equal(getattr(a, key), getattr(b, key)), key
+
+
 def test_deterministic_rerun():
     """No floating-point atomics: two identical runs agree bit for bit."""
     case = SMALL["jitter64"]
