@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void force_vjp_kernel(
       const T pj = k.c0sq * (rhoj - k.rho0);
       T vij[3], w[3];
       T vr = T(0);
-      const T mratio = VAR ? mi / mj : T(1);
+      const T mratio = VAR ? mi * frcp(mj) : T(1);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         vij[d] = vi[d] - velc(d, j);
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kBlock) void force_vjp_kernel(
       const T rhobar = T(0.5) * (rhoi + rhoj);
       const T pstar = T(0.5) * (pi + pj) + T(0.5) * br * rhobar * k.c0 * du;
       const T dP = T(0.5) * rhobar * k.c0 * (br + du * bprime);
-      const T base = T(2) * mj * inv_rhoi / rhoj;
+      const T base = T(2) * mj * inv_rhoi * frcp(rhoj);
       const T Cc = base * pk.F;
       const T Cp = base * pk.Fpr;
       T Bw = T(0), rw = T(0);
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void tv_vjp_kernel(
       T inv_r;
       if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? hc(0, j) : k.h, pk, inv_r)) return;
       const T mj = VAR ? mc(0, j) : k.mass;
-      const T Vj = mj / rhoc(0, j);
+      const T Vj = mj * frcp(rhoc(0, j));
       T u[3], gj[3];
       T ur = T(0), gjr = T(0);
 #pragma unroll
@@ -381,12 +381,19 @@ __global__ __launch_bounds__(kBlock) void adj_finish_kernel(long dn, T half_dt,
   }
 }
 
-__global__ __launch_bounds__(kBlock) void xi_final_kernel(int nblk, const double* __restrict__ partials,
+__global__ __launch_bounds__(kBlock) void xi_final_kernel(int nrows, const double* __restrict__ partials,
                                                           double* __restrict__ xi_bar) {
   __shared__ double red[kBlock / kWave];
-  double v = 0.0;
-  for (int r = threadIdx.x; r < nblk * kWavesPerBlock; r += kBlock) v += partials[r];
-  const double t = block_reduce<double, false>(v, red);
+  // four independent chains per thread (fixed order: deterministic)
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int r = threadIdx.x; r < nrows; r += 4 * kBlock) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int rr = r + u * kBlock;
+      a[u] += rr < nrows ? partials[rr] : 0.0;
+    }
+  }
+  const double t = block_reduce<double, false>((a[0] + a[1]) + (a[2] + a[3]), red);
   if (threadIdx.x == 0) xi_bar[0] += t;
 }
 
@@ -412,12 +419,14 @@ template <typename T>
 void launch_tv_ghat(const Launch& l, const Coeffs<T>& k, int n, const T* gsum, const T* beta,
                     const T* rho, const T* r_bar, T* ghat, double* partials) {
   if (n == 0) return;
+  // one thread per particle (the partials' first xi_rows(n) rows)
+  const dim3 grid((n + kBlock - 1) / kBlock);
   if (l.dim == 2)
-    hipLaunchKernelGGL((tv_ghat_kernel<2, T>), dim3(l.nblk), dim3(kBlock), 0, l.stream, k, n,
-                       gsum, beta, rho, r_bar, ghat, partials);
+    hipLaunchKernelGGL((tv_ghat_kernel<2, T>), grid, dim3(kBlock), 0, l.stream, k, n, gsum, beta,
+                       rho, r_bar, ghat, partials);
   else
-    hipLaunchKernelGGL((tv_ghat_kernel<3, T>), dim3(l.nblk), dim3(kBlock), 0, l.stream, k, n,
-                       gsum, beta, rho, r_bar, ghat, partials);
+    hipLaunchKernelGGL((tv_ghat_kernel<3, T>), grid, dim3(kBlock), 0, l.stream, k, n, gsum, beta,
+                       rho, r_bar, ghat, partials);
 }
 
 template <typename T>
@@ -453,8 +462,9 @@ void launch_adj_finish(const Launch& l, const Coeffs<T>& k, int n, const T* vhal
                      k.half_dt, vhalf_bar, v_bar, a_bar);
 }
 
-void launch_xi_final(hipStream_t s, int nblk, const double* partials, double* xi_bar) {
-  hipLaunchKernelGGL(xi_final_kernel, dim3(1), dim3(kBlock), 0, s, nblk, partials, xi_bar);
+void launch_xi_final(hipStream_t s, int n, const double* partials, double* xi_bar) {
+  const int nrows = (n + kBlock - 1) / kBlock * kWavesPerBlock;
+  hipLaunchKernelGGL(xi_final_kernel, dim3(1), dim3(kBlock), 0, s, nrows, partials, xi_bar);
 }
 
 #define SPH_INST(T)                                                                          \

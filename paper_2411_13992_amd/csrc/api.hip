@@ -498,7 +498,7 @@ int32_t adjoint_step_t(const sph_params* p, const char* tape, sph_adjoint* adj, 
   // 1^T: the correction dr = T(r^n, rho^n; xi)
   launch_tv_ghat<T>(l, k, sz.n, (const T*)(tape + tl.g), (const T*)(tape + tl.beta), pre.rho, r_n,
                     ghat, partials);
-  if (xi_bar) launch_xi_final(stream, sz.nblk, partials, xi_bar);
+  if (xi_bar) launch_xi_final(stream, sz.n, partials, xi_bar);
   launch_tv_vjp<T>(l, g, k, pre, cs_pre, ghat, (const T*)(tape + tl.g),
                    (const T*)(tape + tl.beta), r_n, r_bar, rho_bar);
   // 2^T: v' = v^n + dt/2 a^n

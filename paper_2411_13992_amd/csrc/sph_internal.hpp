@@ -147,7 +147,8 @@ void launch_adj_finish(const Launch& l, const Coeffs<T>& k, int n, const T* vhal
                        T* v_bar, T* a_bar);
 template <typename T>
 void launch_adj_kick(const Launch& l, const Coeffs<T>& k, int n, const T* v_bar, T* a_bar);
-void launch_xi_final(hipStream_t s, int nblk, const double* partials, double* xi_bar);
+// xi_bar += the xi partials tv_ghat wrote for n particles (one block, fixed order)
+void launch_xi_final(hipStream_t s, int n, const double* partials, double* xi_bar);
 
 // Launches a sweep kernel template KERNEL<D, T, VAR, G> on a grid of
 // n * G threads (G lanes per particle), dispatching on dimension, per-particle
