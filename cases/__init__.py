@@ -36,7 +36,7 @@ import numpy as np
 
 __all__ = [
     "Case", "lattice", "taylor_green_2d", "taylor_green_3d",
-    "variable_resolution_2d", "make", "CONFIGS",
+    "variable_resolution_2d", "lid_driven_cavity", "couette_2d", "make", "CONFIGS",
 ]
 
 H_OVER_DP = 1.3          # Sec. 4: h = 1.3 dp
@@ -71,6 +71,12 @@ class Case:
     steps: int = 1
     uniform: bool = True     # uniform mass and h (scalars suffice)
     extra: dict = field(default_factory=dict)
+    n_wall: int = 0          # the last n_wall ids are wall particles
+    wall_vel: np.ndarray | None = None   # (D, n_wall) prescribed wall velocity
+
+    @property
+    def n_fluid(self) -> int:
+        return self.n - self.n_wall
 
     @property
     def n(self) -> int:
@@ -249,6 +255,87 @@ def variable_resolution_2d(dp_min: float = 1.0 / 1306, jitter: float = 0.1, seed
                 extra={"jitter": jitter, "seed": seed, "columns": len(widths)})
 
 
+def _walled_box(nx: int, ny: int, layers: int, dx: float, wall_x: bool):
+    """Fluid on the nx x ny cell-centred lattice of [0, nx dx) x [0, ny dx),
+    then `layers` rows of wall particles on the same lattice below and above it
+    (and, with wall_x, `layers` columns left and right, corners included).
+    Returns (fluid positions, wall positions) in wall-box coordinates: the
+    periodic box starts `layers` spacings below / left of the fluid."""
+    lx = layers if wall_x else 0
+    ix = np.arange(-lx, nx + lx)
+    iy = np.arange(-layers, ny + layers)
+    gx, gy = np.meshgrid(ix, iy, indexing="xy")        # x fastest
+    gx, gy = gx.reshape(-1), gy.reshape(-1)
+    fluid = (gx >= 0) & (gx < nx) & (gy >= 0) & (gy < ny)
+    pts = np.stack([(gx + lx + 0.5) * dx, (gy + layers + 0.5) * dx])
+    return pts[:, fluid], pts[:, ~fluid], gy[~fluid] >= ny
+
+
+def lid_driven_cavity(n: int, re: float = 1000.0, u_lid: float = 1.0, layers: int = 3,
+                      steps: int = 1000, name: str | None = None) -> Case:
+    """2-D lid-driven square cavity of side 1 (Sec. 4.2, Re = U L / nu).
+
+    Fluid at rest on the n x n cell-centred lattice of the unit square; wall
+    particles continue the lattice `layers` spacings beyond every side (corner
+    blocks included).  The top wall (every wall particle above the fluid,
+    corner blocks included) moves at (u_lid, 0); the other walls are at rest.
+    Coordinates are shifted by layers*dp so the box [0, 1 + 2 layers dp)^2 is
+    the periodic box of the cell grid; with layers*dp >= 2h (layers >= 3 at
+    h = 1.3 dp) no fluid particle has a neighbour across its seam.  Ids: the
+    fluid first (x fastest), then the walls (x fastest).
+    """
+    if layers * 1.0 < 2 * H_OVER_DP:
+        raise ValueError("layers must cover the kernel support 2h")
+    dx = 1.0 / n
+    fluid, wall, top = _walled_box(n, n, layers, dx, True)
+    pos = np.concatenate([fluid, wall], axis=1)
+    nw = wall.shape[1]
+    wall_vel = np.zeros((2, nw))
+    wall_vel[0, top] = u_lid
+    vel = np.zeros_like(pos)
+    vel[:, fluid.shape[1]:] = wall_vel
+    rho0 = 1.0
+    c0 = 10.0 * u_lid
+    eta = rho0 * u_lid * 1.0 / re
+    npart = pos.shape[1]
+    edge = (n + 2 * layers) * dx
+    return Case(name=name or f"cavity2d_{n}", dim=2, pos=pos, vel=vel,
+                mass=np.full(npart, rho0 * dx * dx), h=np.full(npart, H_OVER_DP * dx),
+                box=(edge, edge), dx=dx, rho0=rho0, c0=c0, eta=eta, u_ref=u_lid,
+                dt=_dt(H_OVER_DP * dx, u_lid, c0, eta / rho0), steps=steps, uniform=True,
+                extra={"re": re, "layers": layers, "origin": layers * dx, "side": 1.0},
+                n_wall=nw, wall_vel=wall_vel)
+
+
+def couette_2d(n: int, re: float = 10.0, u_wall: float = 1.0, layers: int = 3,
+               width: int | None = None, steps: int = 1000, name: str | None = None) -> Case:
+    """Plane Couette start-up between walls at y = 0 (at rest) and y = 1
+    (moving at (u_wall, 0) from t = 0), periodic in x: fluid at rest on the
+    width x n lattice (dp = 1/n, width n/2 columns by default), `layers` rows
+    of wall particles below and above.  Coordinates are shifted by layers*dp
+    in y (box [0, width dp) x [0, 1 + 2 layers dp)).  Ids: fluid, then walls."""
+    width = width or max(n // 2, 8)
+    dx = 1.0 / n
+    fluid, wall, top = _walled_box(width, n, layers, dx, False)
+    pos = np.concatenate([fluid, wall], axis=1)
+    nw = wall.shape[1]
+    wall_vel = np.zeros((2, nw))
+    wall_vel[0, top] = u_wall
+    vel = np.zeros_like(pos)
+    vel[:, fluid.shape[1]:] = wall_vel
+    rho0 = 1.0
+    c0 = 10.0 * u_wall
+    eta = rho0 * u_wall * 1.0 / re
+    npart = pos.shape[1]
+    return Case(name=name or f"couette2d_{n}", dim=2, pos=pos, vel=vel,
+                mass=np.full(npart, rho0 * dx * dx), h=np.full(npart, H_OVER_DP * dx),
+                box=(width * dx, (n + 2 * layers) * dx), dx=dx, rho0=rho0, c0=c0, eta=eta,
+                u_ref=u_wall, dt=_dt(H_OVER_DP * dx, u_wall, c0, eta / rho0), steps=steps,
+                uniform=True, extra={"re": re, "layers": layers, "origin": layers * dx,
+                                     "height": 1.0},
+                n_wall=nw, wall_vel=wall_vel)
+
+
 # The five workloads of the performance/parity plan, smallest first.
 CONFIGS = {
     # 50x50 lattice, FP64, 100 steps: small enough for the oracle end to end
@@ -262,6 +349,8 @@ CONFIGS = {
     # differentiation workload: 200x200 lattice, +-1% velocity perturbation, 200 steps
     "adjoint_tg2d_200": lambda: taylor_green_2d(200, jitter=0.0, vel_perturb=0.01, seed=1,
                                                 steps=200, name="adjoint_tg2d_200"),
+    # walls: the lid-driven cavity (Sec. 4.2) at dp = 1/200, Re = 1000
+    "cavity2d_200": lambda: lid_driven_cavity(200, name="cavity2d_200"),
 }
 
 

@@ -12,7 +12,8 @@ Citations (sections and equations of arXiv 2411.13992):
   limited linear solver Eq. (5)-(6); viscous term Eq. (7); transport-velocity
   correction Eq. (14)-(16); Wendland kernel with h = 1.3 dp (Sec. 4);
   kick-drift-kick integration (Sec. 3, the time integration of the original
-  transport-velocity formulation).
+  transport-velocity formulation); wall particles for the lid-driven cavity
+  (Sec. 4.2; the wall treatment is a reading, stated in ``sph_oracle.c``).
 """
 from __future__ import annotations
 
@@ -46,7 +47,8 @@ class Params(ctypes.Structure):
         ("lim_s0", ctypes.c_double), ("riemann_eta", ctypes.c_double),
         ("h_min", ctypes.c_double), ("kappa", ctypes.c_double), ("band_tol", ctypes.c_double),
         ("tv_every", ctypes.c_int32), ("use_grid", ctypes.c_int32),
-        ("tv_mode", ctypes.c_int32),
+        ("tv_mode", ctypes.c_int32), ("n_wall", ctypes.c_int64),
+        ("wall_vel", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -90,6 +92,8 @@ def lib():
         L.oracle_forces.argtypes = [ctypes.c_int, ctypes.c_int64, _D, _D, _D, _D, _D, _D,
                                     _I64, _I32, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, _D, _D]
+        L.oracle_wall_bc.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, _D, _D, _D,
+                                     _I64, _I32, ctypes.c_double, ctypes.c_double, _D, _D, _D]
         L.oracle_init.argtypes = [ctypes.c_int, ctypes.c_int64, _D, _D, _D, _D, _D,
                                   ctypes.POINTER(Params), _D, _D]
         L.oracle_kdk_step.argtypes = [ctypes.c_int, ctypes.c_int64, _D, _D, _D, _D, _D, _D, _D,
@@ -142,12 +146,16 @@ def params(case, band_tol: float = 1e-5, tv_every: int = 1, use_grid: bool = Tru
            tv_mode: int | str = TV_LIMITED) -> Params:
     if isinstance(tv_mode, str):
         tv_mode = TV_MODES[tv_mode]
-    return Params(rho0=case.rho0, c0=case.c0, eta=case.eta, dt=case.dt,
-                  xi=case.xi if xi is None else xi, lim_c=case.lim_c, lim_s0=case.lim_s0,
-                  riemann_eta=case.riemann_eta, h_min=case.h_min,
-                  kappa=lattice_kappa(case.dim) if kappa is None else kappa,
-                  band_tol=band_tol, tv_every=tv_every, use_grid=1 if use_grid else 0,
-                  tv_mode=int(tv_mode))
+    prm = Params(rho0=case.rho0, c0=case.c0, eta=case.eta, dt=case.dt,
+                 xi=case.xi if xi is None else xi, lim_c=case.lim_c, lim_s0=case.lim_s0,
+                 riemann_eta=case.riemann_eta, h_min=case.h_min,
+                 kappa=lattice_kappa(case.dim) if kappa is None else kappa,
+                 band_tol=band_tol, tv_every=tv_every, use_grid=1 if use_grid else 0,
+                 tv_mode=int(tv_mode), n_wall=int(getattr(case, "n_wall", 0)))
+    if prm.n_wall > 0:
+        prm.wall_keep = _f64(case.wall_vel).copy()     # kept alive with the struct
+        prm.wall_vel = _p(prm.wall_keep)
+    return prm
 
 
 def neighbors(pos, h, box, method: str = "grid"):
@@ -190,6 +198,20 @@ def tv(pos, mass, rho, h, box, nbr, h_min, xi=-0.2, lim_c=1e3, lim_s0=5e-4,
                     float(bg), _p(out["g"]),
                     _p(out["s"]), _p(out["beta"]), _p(out["dr"]), _p(out["gscale"]))
     return out
+
+
+def wall_bc(pos, vel, rho, h, box, nbr, n_wall, wall_vel, rho0, c0):
+    """Wall particles (the last n_wall) from their fluid neighbours: returns
+    (rho, vel) with the wall entries replaced (Shepard-averaged pressure
+    through the inverted EOS, no-slip mirror velocity); fluid entries copied."""
+    pos, vel, rho, h, box, wall_vel = map(_f64, (pos, vel, rho, h, box, wall_vel))
+    dim, n = pos.shape
+    start, lst = nbr
+    rho = rho.copy()
+    vel = vel.copy()
+    lib().oracle_wall_bc(dim, n, int(n_wall), _p(pos), _p(h), _p(box), _p(start), _p(lst),
+                         float(rho0), float(c0), _p(wall_vel), _p(rho), _p(vel))
+    return rho, vel
 
 
 def forces(pos, vel, mass, rho, h, box, nbr, rho0, c0, eta, riemann_eta=3.0):

@@ -31,7 +31,17 @@
  *    times-step-squared step that turns Eq. 12 into Eq. 14), so
  *    dr_i = -(p0 dt^2 / rho_i) g_i with g_i = sum_j V_j grad_i W_ij;
  *  - time integration: kick-drift-kick with fixed dt; the correction is added to
- *    the drift; forces use the half-step velocity.
+ *    the drift; forces use the half-step velocity;
+ *  - walls (the lid-driven cavity of Sec. 4.2; the paper names no wall
+ *    treatment): fixed wall particles on the fluid lattice, several layers
+ *    thick, taking part in every sum of the fluid particles as ordinary
+ *    neighbours.  Before each force evaluation every wall particle a gets a
+ *    pressure and a velocity from its fluid neighbours f by kernel-weighted
+ *    (Shepard) averages, p_a = sum p_f W_af / sum W_af, rho_a = rho0 + p_a/c0^2
+ *    (EOS inverted), and the no-slip mirror v_a = 2 u_a - sum v_f W_af / sum
+ *    W_af with u_a the prescribed wall velocity (p_a = 0, v_a = u_a without
+ *    fluid neighbours).  Wall particles are not corrected, kicked or moved;
+ *    the diagnostics cover the fluid only.
  */
 #include <math.h>
 #include <stdint.h>
@@ -58,6 +68,8 @@ typedef struct {
     int32_t tv_every;   /* apply the correction every k-th step       */
     int32_t use_grid;   /* 1: bucket neighbour search, 0: brute force */
     int32_t tv_mode;    /* ORACLE_TV_* below                          */
+    int64_t n_wall;     /* the last n_wall particles are walls        */
+    const double *wall_vel; /* [D][n_wall] prescribed wall velocity   */
 } oracle_params;
 
 /* Transport-velocity formulations */
@@ -434,6 +446,39 @@ void oracle_forces(int dim, int64_t n, const double *pos, const double *vel,
 }
 
 /* ------------------------------------------------------------------ */
+/* Wall particles a = n - n_wall .. n-1 from their fluid neighbours:  */
+/*   S = sum_f W_af, p_a = sum_f p_f W_af / S, vbar = sum_f v_f W_af / S */
+/*   rho_a = rho0 + p_a / c0^2,  v_a = 2 u_a - vbar                    */
+/* (p_a = 0 and vbar = u_a when S = 0).  Writes rho and vel of walls. */
+/* ------------------------------------------------------------------ */
+void oracle_wall_bc(int dim, int64_t n, int64_t n_wall, const double *pos, const double *h,
+                    const double *box, const int64_t *start, const int32_t *list,
+                    double rho0, double c0, const double *wall_vel, double *rho, double *vel)
+{
+    int64_t nf = n - n_wall;
+#pragma omp parallel for schedule(static)
+    for (int64_t a = nf; a < n; ++a) {
+        double S = 0.0, P = 0.0, V[3] = {0.0, 0.0, 0.0};
+        for (int64_t e = start[a]; e < start[a + 1]; ++e) {
+            int64_t f = list[e];
+            if (f >= nf) continue;
+            double raf[3];
+            double r = displacement(dim, n, pos, box, a, f, raf);
+            double w = oracle_kernel_w(dim, r, 0.5 * (h[a] + h[f]));
+            S += w;
+            P += c0 * c0 * (rho[f] - rho0) * w;
+            for (int k = 0; k < dim; ++k) V[k] += vel[k * n + f] * w;
+        }
+        double pa = S > 0.0 ? P / S : 0.0;
+        rho[a] = rho0 + pa / (c0 * c0);
+        for (int k = 0; k < dim; ++k) {
+            double ua = wall_vel[k * n_wall + (a - nf)];
+            vel[k * n + a] = 2.0 * ua - (S > 0.0 ? V[k] / S : ua);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* neighbour list helper for the step: malloc'd CSR                   */
 /* ------------------------------------------------------------------ */
 typedef struct {
@@ -459,22 +504,35 @@ static void free_lists(nbr_lists *nl)
     free(nl->list);
 }
 
+/* zero the [D][N] field f on the wall particles */
+static void zero_walls(int dim, int64_t n, int64_t n_wall, double *f)
+{
+    if (!f) return;
+    for (int k = 0; k < dim; ++k)
+        for (int64_t a = n - n_wall; a < n; ++a) f[k * n + a] = 0.0;
+}
+
 /* ------------------------------------------------------------------ */
 /* initial state: rho^0 by summation, a^0 from the initial velocity    */
+/* (walls: their state from the fluid before the forces)              */
 /* ------------------------------------------------------------------ */
-void oracle_init(int dim, int64_t n, const double *pos, const double *vel,
+void oracle_init(int dim, int64_t n, const double *pos, double *vel,
                  const double *mass, const double *h, const double *box,
                  const oracle_params *p, double *rho, double *acc)
 {
     nbr_lists nl;
     make_lists(dim, n, pos, h, box, p->use_grid, &nl);
     oracle_density(dim, n, pos, mass, h, box, nl.start, nl.list, p->kappa, rho);
+    if (p->n_wall > 0)
+        oracle_wall_bc(dim, n, p->n_wall, pos, h, box, nl.start, nl.list, p->rho0, p->c0,
+                       p->wall_vel, rho, (double *)vel);
     oracle_forces(dim, n, pos, vel, mass, rho, h, box, nl.start, nl.list,
                   p->rho0, p->c0, p->eta, p->riemann_eta, acc, NULL);
+    zero_walls(dim, n, p->n_wall, acc);
     free_lists(&nl);
 }
 
-/* Diagnostics of a state, plain sequential FP64 sums:
+/* Diagnostics of a state (fluid particles), plain sequential FP64 sums:
  * diag[0] KE = 1/2 sum m |v|^2, diag[1..3] momentum, diag[4] max|v|,
  * diag[5] ordered neighbour pairs, diag[6] count(beta > 0),
  * diag[7] count of limiter-band particles, diag[8] max |dr| / dt. */
@@ -486,7 +544,7 @@ static void diagnostics(int dim, int64_t n, const double *vel, const double *mas
 {
     double ke = 0.0, mom[3] = {0.0, 0.0, 0.0}, vmax = 0.0, drmax = 0.0;
     int64_t nbeta = 0, nband = 0;
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t i = 0; i < n - p->n_wall; ++i) {
         double v2 = 0.0;
         for (int k = 0; k < dim; ++k) {
             double v = vel[k * n + i];
@@ -532,16 +590,23 @@ void oracle_kdk_step(int dim, int64_t n, double *pos, double *vel, double *acc,
     double *g = (double *)calloc(dn, sizeof(double));
     nbr_lists nl;
 
-    /* 1. transport correction at r^n with rho^n */
+    int64_t nf = n - p->n_wall;
+
+    /* 1. transport correction at r^n with rho^n (none for walls) */
     make_lists(dim, n, pos, h, box, p->use_grid, &nl);
     if (p->tv_every > 0 && step_index % p->tv_every == 0)
         oracle_tv(dim, n, pos, mass, rho, h, box, nl.start, nl.list, p->h_min, p->xi,
                   p->lim_c, p->lim_s0, p->tv_mode, p->rho0 * p->c0 * p->c0 * p->dt * p->dt,
                   g, s, beta, dr, NULL);
     free_lists(&nl);
+    zero_walls(dim, n, p->n_wall, dr);
+    zero_walls(dim, n, p->n_wall, g);
+    zero_walls(1, n, p->n_wall, beta);
+    zero_walls(1, n, p->n_wall, s);
 
-    /* 2. half kick, 3. drift with the correction, wrapped into the box */
-    for (int64_t i = 0; i < n; ++i)
+    /* 2. half kick, 3. drift with the correction, wrapped into the box
+     * (fluid only: walls keep position and velocity) */
+    for (int64_t i = 0; i < nf; ++i)
         for (int k = 0; k < dim; ++k) {
             size_t a = (size_t)k * n + i;
             vel[a] = vel[a] + 0.5 * p->dt * acc[a];
@@ -551,14 +616,23 @@ void oracle_kdk_step(int dim, int64_t n, double *pos, double *vel, double *acc,
             pos[a] = x;
         }
 
-    /* 4. density at r^{n+1}; 5-6. forces with the half-step velocity */
+    /* 4. density at r^{n+1}; walls from the fluid (density, half-step
+     * velocity); 5-6. forces with the half-step velocity */
     make_lists(dim, n, pos, h, box, p->use_grid, &nl);
     oracle_density(dim, n, pos, mass, h, box, nl.start, nl.list, p->kappa, rho);
+    if (p->n_wall > 0)
+        oracle_wall_bc(dim, n, p->n_wall, pos, h, box, nl.start, nl.list, p->rho0, p->c0,
+                       p->wall_vel, rho, vel);
     oracle_forces(dim, n, pos, vel, mass, rho, h, box, nl.start, nl.list,
                   p->rho0, p->c0, p->eta, p->riemann_eta, acc, NULL);
+    zero_walls(dim, n, p->n_wall, acc);
 
-    /* 7. second half kick */
-    for (size_t a = 0; a < dn; ++a) vel[a] = vel[a] + 0.5 * p->dt * acc[a];
+    /* 7. second half kick (fluid) */
+    for (int k = 0; k < dim; ++k)
+        for (int64_t i = 0; i < nf; ++i) {
+            size_t a = (size_t)k * n + i;
+            vel[a] = vel[a] + 0.5 * p->dt * acc[a];
+        }
 
     /* 8. diagnostics of the new state (pairs at r^{n+1}, correction at r^n) */
     if (diag) diagnostics(dim, n, vel, mass, nl.npairs, beta, s, dr, p, diag);
