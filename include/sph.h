@@ -105,6 +105,8 @@ typedef struct {
     double dt, xi, lim_c, lim_s0, riemann_eta;
     double band_tol;      /* relative half-width of the limiter band counted in
                              the diagnostics: |s - s0| <= band_tol * s0          */
+    int64_t n_wall;       /* 0 <= n_wall <= n: particles with id >= n - n_wall
+                             are wall particles (see sph_wall_state)             */
 } sph_params;
 
 /* Particle arrays, all device pointers of length N (or [D][N]). */
@@ -119,6 +121,9 @@ typedef struct {
                        NULL and params.mass applies to all                   */
     void *h;        /* [N] per-particle smoothing length (per_particle = 1),
                        else NULL and h_min applies to all                    */
+    void *wall_vel; /* [D][n_wall] prescribed velocity of wall particle
+                       id = n - n_wall + w at column w (params.n_wall > 0),
+                       else NULL; never reordered                            */
 } sph_particles;
 
 /* Cotangents (adjoint variables) of a state, device arrays in the particle
@@ -181,6 +186,25 @@ int32_t sph_density(const sph_params *p, const sph_particles *parts,
  * contribute no pressure term (their Riemann axis is undefined). */
 int32_t sph_forces(const sph_params *p, const sph_particles *parts,
                    const int32_t *cell_start, const void *vel, void *acc_out, void *stream);
+
+/* Wall particles (the lid-driven cavity of Sec. 4.2; the paper names no wall
+ * treatment, this is the library's): params.n_wall > 0 marks the particles
+ * with id >= n - n_wall as walls.  They stay where they are, take part in
+ * every sum of the fluid particles as ordinary neighbours, and get no
+ * correction, kick or drift; their acceleration is zero and the diagnostics
+ * cover the fluid only.  sph_wall_state sets, for every wall particle a, from
+ * its fluid neighbours f (kernel-weighted averages):
+ *   p_a = sum_f p_f W_af / sum_f W_af,  rho_a = rho0 + p_a / c0^2,
+ *   vel_a = 2 u_a - sum_f v_f W_af / sum_f W_af   (no-slip mirror),
+ * with u_a = parts->wall_vel (p_a = 0, vel_a = u_a without fluid
+ * neighbours).  It writes parts->rho and parts->vel of wall particles only
+ * and reads those of fluid particles.  sph_kdk_step / sph_kdk_run call it
+ * after each density summation; a caller evaluating sph_forces by hand calls
+ * it between sph_density and sph_forces.  The box stays periodic: walls at
+ * least 2 h_max thick keep the fluid from reaching across its seam.  With
+ * n_wall > 0, tapes and the adjoint entry points return SPH_E_UNSUPPORTED. */
+int32_t sph_wall_state(const sph_params *p, sph_particles *parts, const int32_t *cell_start,
+                       void *stream);
 
 /* Transport-velocity correction in the formulation params.tv_mode (Eq. 14-16,
  * or Eq. 12 for SPH_TV_BACKGROUND), from positions and parts->rho:

@@ -32,7 +32,8 @@ DIAG_NAMES = ("ke", "px", "py", "pz", "vmax", "npairs", "nbeta", "nband", "trans
 # entry points declared in include/sph.h, in declaration order
 EXPORTS = (
     "sph_workspace_size", "sph_tape_size", "sph_lattice_kappa", "sph_bin_positions",
-    "sph_build_cells", "sph_density", "sph_forces", "sph_tv_correction", "sph_kdk_step",
+    "sph_build_cells", "sph_density", "sph_forces", "sph_wall_state", "sph_tv_correction",
+    "sph_kdk_step",
     "sph_kdk_run", "sph_diagnostics", "sph_adjoint_step", "sph_adjoint_init", "sph_neighbor_counts",
     "sph_get_flags", "sph_clear_flags", "sph_status_string",
 )
@@ -49,12 +50,13 @@ class SphParams(ctypes.Structure):
         ("kappa", ctypes.c_double), ("dt", ctypes.c_double), ("xi", ctypes.c_double),
         ("lim_c", ctypes.c_double), ("lim_s0", ctypes.c_double),
         ("riemann_eta", ctypes.c_double), ("band_tol", ctypes.c_double),
+        ("n_wall", ctypes.c_int64),
     ]
 
 
 class SphParticles(ctypes.Structure):
     _fields_ = [(name, ctypes.c_void_p) for name in
-                ("cell", "id", "off", "vel", "acc", "rho", "mass", "h")]
+                ("cell", "id", "off", "vel", "acc", "rho", "mass", "h", "wall_vel")]
 
 
 class SphAdjoint(ctypes.Structure):
@@ -92,6 +94,7 @@ def load():
         "sph_build_cells": [pp, P(SphParticles), vp, vp, vp, ctypes.c_size_t, vp],
         "sph_density": [pp, P(SphParticles), vp, vp, vp],
         "sph_forces": [pp, P(SphParticles), vp, vp, vp, vp],
+        "sph_wall_state": [pp, P(SphParticles), vp, vp],
         "sph_tv_correction": [pp, P(SphParticles), vp, vp, vp, vp, vp, vp],
         "sph_kdk_step": [pp, P(SphParticles), vp, ctypes.c_int64, vp, ctypes.c_size_t, vp, vp,
                          vp],

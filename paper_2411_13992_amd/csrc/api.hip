@@ -154,6 +154,7 @@ int32_t check_params(const sph_params* p) {
   if (p->tv_mode != SPH_TV_LIMITED && p->tv_mode != SPH_TV_SCALED &&
       p->tv_mode != SPH_TV_BACKGROUND)
     return SPH_E_ARG;
+  if (p->n_wall < 0 || p->n_wall > p->n) return SPH_E_ARG;
   const double vals[] = {p->rho0, p->c0, p->h_min, p->h_max, p->kappa, p->mass};
   for (double v : vals)
     if (!std::isfinite(v)) return SPH_E_NONFINITE;
@@ -227,6 +228,7 @@ Coeffs<T> coeffs_of(const sph_params* p, const Grid& g) {
   k.inv_dt = p->dt > 0.0 ? 1.0 / p->dt : 0.0;
   k.tv_mode = p->tv_mode;
   k.bg = p->rho0 * p->c0 * p->c0 * p->dt * p->dt;
+  k.nfluid = (int)(p->n - p->n_wall);
   return k;
 }
 
@@ -273,6 +275,7 @@ int32_t check_particles(const sph_params* p, const sph_particles* s, bool need_d
   } else if (s->mass || s->h) {
     return SPH_E_ARG;
   }
+  if ((p->n_wall > 0) != (s->wall_vel != nullptr)) return SPH_E_ARG;
   return SPH_OK;
 }
 
@@ -409,8 +412,9 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
     launch_scan(stream, sz.ncells, counts, cb.scan, (unsigned)s, cs, flags, fold);
     launch_scatter(stream, sz.n, stg.cell, stg.id, slot, cs, st);
     launch_rank_gather<T>(l, sz.n, st, src, dst, perm);
-    // 4. density summation (Eq. 8)
+    // 4. density summation (Eq. 8); wall particles from the fluid
     launch_density<T>(l, g, k, a, cs, a.rho, cur, nullptr, flags);
+    launch_wall_state<T>(l, g, k, a, cs, (const T*)parts->wall_vel, (int)p->n_wall);
     if (tapes) {
       // the state after this step (half-step velocity, new density) is the
       // state before the next
@@ -442,7 +446,7 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
     } else {
       // 5-6. accelerations at (r^{n+1}, v', rho^{n+1}), 7. second half kick
       launch_forces<T>(l, g, k, a, cs, a.vel, a.acc, flags);
-      launch_kick<T>(l, k, sz.n, a.vel, a.acc, a.mass, cur, true, flags);
+      launch_kick<T>(l, k, sz.n, a.vel, a.acc, a.mass, a.id, cur, true, flags);
       if (diag) launch_diag_fold(stream, DiagFold{cur, sz.nblk * kWavesPerBlock, diag + (size_t)SPH_NDIAG * s});
     }
   }
@@ -669,6 +673,24 @@ int32_t sph_forces(const sph_params* p, const sph_particles* parts, const int32_
   });
 }
 
+int32_t sph_wall_state(const sph_params* p, sph_particles* parts, const int32_t* cell_start,
+                       void* stream) {
+  int32_t st = check_params(p);
+  if (st != SPH_OK) return st;
+  st = check_particles(p, parts, true);
+  if (st != SPH_OK) return st;
+  if (p->n == 0 || p->n_wall == 0) return SPH_OK;
+  if (!cell_start) return SPH_E_ARG;
+  const Grid g = grid_of(p);
+  const Launch l = launch_of(p, is_var(p), stream);
+  return dispatch(p, [&](auto tag) {
+    using T = decltype(tag);
+    launch_wall_state<T>(l, g, coeffs_of<T>(p, g), arrays_of<T>(parts), cell_start,
+                         (const T*)parts->wall_vel, (int)p->n_wall);
+    return hip_status();
+  });
+}
+
 int32_t sph_tv_correction(const sph_params* p, const sph_particles* parts,
                           const int32_t* cell_start, void* dr_out, void* beta_out, double* s_out,
                           void* g_out, void* stream) {
@@ -696,6 +718,7 @@ static int32_t kdk_common(const sph_params* p, sph_particles* parts, int32_t* ce
   st = check_particles(p, parts, true);
   if (st != SPH_OK) return st;
   if (!cell_start || !ws || step_index < 0 || nsteps < 0) return SPH_E_ARG;
+  if (tape && p->n_wall > 0) return SPH_E_UNSUPPORTED;
   size_t need = 0;
   sph_workspace_size(p, &need);
   if (ws_bytes < need) return SPH_E_WORKSPACE;
@@ -753,7 +776,7 @@ int32_t sph_diagnostics(const sph_params* p, const sph_particles* parts, const i
     // pair count from a density sweep into the staging buffer (state untouched)
     launch_density<T>(l, g, k, a, cell_start, (T*)((char*)ws + w.stg_rho), partials, nullptr,
                       nullptr);
-    launch_kick<T>(l, k, sz.n, a.vel, a.acc, a.mass, partials, false, nullptr);
+    launch_kick<T>(l, k, sz.n, a.vel, a.acc, a.mass, a.id, partials, false, nullptr);
     launch_diag_fold(s, DiagFold{partials, sz.nblk * kWavesPerBlock, diag});
     return SPH_OK;
   });
@@ -765,6 +788,7 @@ int32_t sph_adjoint_step(const sph_params* p, const void* tape, sph_adjoint* adj
                          void* ws, size_t ws_bytes, void* stream) {
   int32_t st = check_params(p);
   if (st != SPH_OK) return st;
+  if (p->n_wall > 0) return SPH_E_UNSUPPORTED;
   if (!tape || !adj || !ws) return SPH_E_ARG;
   size_t need = 0;
   sph_workspace_size(p, &need);
@@ -781,6 +805,7 @@ int32_t sph_adjoint_init(const sph_params* p, const sph_particles* parts, const 
                          sph_adjoint* adj, void* ws, size_t ws_bytes, void* stream) {
   int32_t st = check_params(p);
   if (st != SPH_OK) return st;
+  if (p->n_wall > 0) return SPH_E_UNSUPPORTED;
   st = check_particles(p, parts, true);
   if (st != SPH_OK) return st;
   if (!adj || !ws) return SPH_E_ARG;

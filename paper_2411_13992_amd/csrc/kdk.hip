@@ -61,15 +61,17 @@ __global__ __launch_bounds__(kBlock) void drift_kernel(Grid g, Coeffs<T> k, PArr
   const bool valid = i < n;
   int lin = 0;
   if (valid) {
+    // wall particles keep their position and velocity
+    const bool wall = is_wall(k, p.id[i]);
     T o[3], vh[3], dri[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      vh[d] = tfma(k.half_dt, p.acc[d * n + i], p.vel[d * n + i]);
+      vh[d] = wall ? p.vel[d * n + i] : tfma(k.half_dt, p.acc[d * n + i], p.vel[d * n + i]);
       o[d] = p.off[d * n + i];
       if (dr) dri[d] = dr[d * n + i];
     }
     unsigned f = 0;
-    lin = drift_rebin<D>(g, k, p.cell[i], o, vh, dri, f);
+    lin = wall ? p.cell[i] : drift_rebin<D>(g, k, p.cell[i], o, vh, dri, f);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       stg.off[d * n + i] = o[d];
@@ -107,13 +109,14 @@ template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void kick_kernel(Coeffs<T> k, int n, T* __restrict__ vel,
                                                       const T* __restrict__ acc,
                                                       const T* __restrict__ mass,
+                                                      const int* __restrict__ id,
                                                       double* __restrict__ partials, int write,
                                                       int G, unsigned* __restrict__ flags) {
   // same particle-to-block mapping as the sweeps (G lanes per particle, the
   // first does the work), so per-block partials fold in the same order
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   double ke = 0.0, mom[3] = {0.0, 0.0, 0.0}, vmax = 0.0;
-  if (i < n && threadIdx.x % G == 0) {
+  if (i < n && threadIdx.x % G == 0 && !is_wall(k, id[i])) {
     const double m = mass ? (double)mass[i] : (double)k.mass;
     double v2 = 0.0;
     bool bad = false;
@@ -141,14 +144,14 @@ __global__ __launch_bounds__(kBlock) void kick_kernel(Coeffs<T> k, int n, T* __r
 
 template <typename T>
 void launch_kick(const Launch& l, const Coeffs<T>& k, int n, T* vel, const T* acc,
-                 const T* mass, double* partials, bool write, unsigned* flags) {
+                 const T* mass, const int* id, double* partials, bool write, unsigned* flags) {
   if (n == 0) return;
   if (l.dim == 2)
     hipLaunchKernelGGL((kick_kernel<2, T>), dim3(l.nblk), dim3(kBlock), 0, l.stream, k, n, vel,
-                       acc, mass, partials, write ? 1 : 0, l.G, flags);
+                       acc, mass, id, partials, write ? 1 : 0, l.G, flags);
   else
     hipLaunchKernelGGL((kick_kernel<3, T>), dim3(l.nblk), dim3(kBlock), 0, l.stream, k, n, vel,
-                       acc, mass, partials, write ? 1 : 0, l.G, flags);
+                       acc, mass, id, partials, write ? 1 : 0, l.G, flags);
 }
 
 __global__ __launch_bounds__(kBlock) void diag_fold_kernel(const double* __restrict__ partials,
@@ -192,7 +195,7 @@ void launch_zero(hipStream_t s, T* p, long n) {
                                 const PArrays<T>&, const T*, const PArrays<T>&, int*, int*,  \
                                 unsigned*);                                                  \
   template void launch_kick<T>(const Launch&, const Coeffs<T>&, int, T*, const T*, const T*, \
-                               double*, bool, unsigned*);
+                               const int*, double*, bool, unsigned*);
 SPH_INST(float)
 SPH_INST(double)
 #undef SPH_INST

@@ -40,7 +40,11 @@ struct Coeffs {
   double xi, lim_c, lim_s0, hmin2, band_tol, inv_dt;
   int tv_mode;      // SPH_TV_LIMITED / SPH_TV_SCALED / SPH_TV_BACKGROUND
   double bg;        // rho0 c0^2 dt^2, the background-pressure coefficient
+  int nfluid;       // particles with id >= nfluid are walls (nfluid = n: none)
 };
+
+template <typename T>
+__device__ __forceinline__ bool is_wall(const Coeffs<T>& k, int id) { return id >= k.nfluid; }
 
 // ---------------------------------------------------------------- math
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }

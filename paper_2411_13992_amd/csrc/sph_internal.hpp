@@ -72,6 +72,11 @@ void launch_forces(const Launch& l, const Grid& g, const Coeffs<T>& k, const PAr
 template <typename T>
 void launch_forces_fused(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                          const int* cs, const FusedOut<T>& fo, unsigned* flags);
+// wall particles' density and mirror velocity from their fluid neighbours
+// (p.rho, p.vel of walls written; wall_vel [D][n_wall] by id - nfluid)
+template <typename T>
+void launch_wall_state(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
+                       const int* cs, const T* wall_vel, int n_wall);
 
 // ---- cells (cells.hip)
 template <typename T>
@@ -118,10 +123,11 @@ template <typename T>
 void launch_drift(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                   const T* dr, const PArrays<T>& stg, int* counts, int* slot, unsigned* flags);
 // v += dt/2 a (when `write`); with partials, writes this step's kinetic
-// energy, momentum and max |v| partials (columns 0-4)
+// energy, momentum and max |v| partials (columns 0-4).  Wall particles (by
+// id) are neither kicked nor counted.
 template <typename T>
 void launch_kick(const Launch& l, const Coeffs<T>& k, int n, T* vel, const T* acc,
-                 const T* mass, double* partials, bool write, unsigned* flags);
+                 const T* mass, const int* id, double* partials, bool write, unsigned* flags);
 void launch_zero_partials(hipStream_t s, int nblk, double* partials);
 template <typename T>
 void launch_zero(hipStream_t s, T* p, long n);

@@ -89,18 +89,20 @@ template <int D, typename T, bool VAR, int G>
 __global__ __launch_bounds__(kBlock) void tv_kernel(
     Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
     const T* __restrict__ off, const T* __restrict__ rho, const T* __restrict__ mass,
-    const T* __restrict__ hh, T* __restrict__ dr, T* __restrict__ beta_out,
-    double* __restrict__ s_out, T* __restrict__ g_out, double* __restrict__ partials) {
+    const T* __restrict__ hh, const int* __restrict__ id, T* __restrict__ dr,
+    T* __restrict__ beta_out, double* __restrict__ s_out, T* __restrict__ g_out,
+    double* __restrict__ partials) {
   const int n = g.n;
   const Cols<T, D> offc(off, n);
   const Cols<T, 1> rhoc(rho, n), hc(hh, n), mc(mass, n);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   const bool valid = i < n;
+  const bool fluid = valid && !is_wall(k, id[i]);   // walls get no correction
   Acc<T, UseKahan<T>::value> acc[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) acc[d].init(T(0));
-  if (valid) {
+  if (fluid) {
     T oi[3];
 #pragma unroll
     for (int d = 0; d < D; ++d) oi[d] = off[d * n + i];
@@ -129,7 +131,12 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
   for (int d = 0; d < D; ++d) gi[d] = tv_finish<T, VAR>(k, group_sum<G>(acc[d]));
   double v[3] = {0.0, 0.0, 0.0};   // beta > 0, in band, |dr| / dt
   if (valid && sub == 0) {
-    const Limited lim = limit_correction<D>(k, gi, rho[i], dri);
+    Limited lim = limit_correction<D>(k, gi, rho[i], dri);
+    if (!fluid) {
+      lim = Limited{};
+#pragma unroll
+      for (int d = 0; d < D; ++d) dri[d] = T(0);
+    }
     double d2 = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -182,6 +189,8 @@ __device__ __forceinline__ void forces_impl(
   const int sub = threadIdx.x % G;
   const bool valid = i < n;
   const bool lead = valid && sub == 0;
+  // wall particles: no acceleration, correction, kick or drift
+  const bool wall = valid && is_wall(k, id[i]);
   T oi[3] = {T(0), T(0), T(0)}, vi[3] = {T(0), T(0), T(0)};
   T ai[3] = {T(0), T(0), T(0)}, gi[3] = {T(0), T(0), T(0)};
   int celli = 0;
@@ -248,7 +257,8 @@ __device__ __forceinline__ void forces_impl(
         for (int d = 0; d < D; ++d) tv[d].add(w * rv[d]);
       }
     };
-    for_each_neighbour_listed<D, G, T, NS>(g, k, celli, cs, sub, st, nl, srct, test, body);
+    if (!wall)
+      for_each_neighbour_listed<D, G, T, NS>(g, k, celli, cs, sub, st, nl, srct, test, body);
   }
   const T s = T(2) / rhoi;
   bool bad = false;
@@ -268,7 +278,24 @@ __device__ __forceinline__ void forces_impl(
     // and drift; the moved particle goes to the staging buffers
     double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // ke, mom x3, vmax, nbeta, nband, drmax
     int lin = 0;
-    if (lead) {
+    if (lead && wall) {
+      // a wall particle stays in place with its velocity; its cell slot is
+      // claimed like any other
+      lin = celli;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        fo.stg.off[d * n + i] = oi[d];
+        fo.stg.vel[d * n + i] = vi[d];
+        if (fo.g_next) fo.g_next[d * n + i] = T(0);
+      }
+      if (fo.g_next) fo.beta_next[i] = T(0);
+      fo.stg.cell[i] = lin;
+      fo.stg.id[i] = id[i];
+      if constexpr (VAR) {
+        fo.stg.mass[i] = mass[i];
+        fo.stg.h[i] = hh[i];
+      }
+    } else if (lead) {
       const double m = VAR ? (double)mass[i] : (double)k.mass;
       T vh[3], dr[3] = {T(0), T(0), T(0)};
       double v2 = 0.0;
@@ -342,6 +369,78 @@ __global__ __launch_bounds__(kBlock) void forces_fused_kernel(
                                   fo);
 }
 
+// ------------------------------------------------------------------ wall state
+// For each wall particle a, from its fluid neighbours f (kernel-weighted
+// averages): p_a = sum p_f W / sum W, rho_a = rho0 + p_a / c0^2 and the
+// no-slip mirror velocity v_a = 2 u_a - sum v_f W / sum W (u_a prescribed);
+// p_a = 0 and v_a = u_a without fluid neighbours.  Only wall entries of rho
+// and vel are written and only fluid entries are read.  Wavefronts without a
+// wall particle leave at once.
+template <int D, typename T, bool VAR, int G>
+__global__ __launch_bounds__(kBlock) void wall_state_kernel(
+    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+    const T* __restrict__ off, const T* __restrict__ hh, const int* __restrict__ id,
+    const T* __restrict__ wall_vel, int n_wall, T* __restrict__ rho, T* __restrict__ vel) {
+  const int n = g.n;
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
+  const int sub = threadIdx.x % G;
+  const int idi = i < n ? id[i] : 0;
+  const bool wall = i < n && is_wall(k, idi);
+  if (!__any(wall)) return;     // whole wavefront: no lane needs a group sum
+  const Cols<T, D> offc(off, n), velc(vel, n);
+  const Cols<T, 1> rhoc(rho, n), hc(hh, n);
+  Acc<T, UseKahan<T>::value> sw, sp, sv[3];
+  sw.init(T(0));
+  sp.init(T(0));
+#pragma unroll
+  for (int d = 0; d < 3; ++d) sv[d].init(T(0));
+  if (wall) {
+    T oi[3];
+#pragma unroll
+    for (int d = 0; d < D; ++d) oi[d] = off[d * n + i];
+    const T hi = VAR ? hh[i] : k.h;
+    for_each_candidate<D, G>(g, k, cell[i], cs, sub, [&](int j, const T* sh) {
+      T r2 = T(0);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const T rv = (oi[d] - offc(d, j)) - sh[d];
+        r2 = tfma(rv, rv, r2);
+      }
+      T w;
+      if constexpr (VAR) {
+        const T sup = hi + hc(0, j);
+        if (!(r2 < sup * sup)) return;
+        const T inv = frcp(T(0.5) * sup);
+        w = wendland_alpha<D>(inv) * wendland_shape(fsqrt(r2) * inv);
+      } else {
+        if (!(r2 < k.sup2)) return;
+        w = wendland_shape(fsqrt(r2) * k.inv_h);   // alpha cancels in the ratios
+      }
+      if (is_wall(k, id[j])) return;               // fluid neighbours only
+      sw.add(w);
+      sp.add(k.c0sq * (rhoc(0, j) - k.rho0) * w);
+#pragma unroll
+      for (int d = 0; d < D; ++d) sv[d].add(velc(d, j) * w);
+    });
+  }
+  const T S = group_sum<G>(sw);
+  const T P = group_sum<G>(sp);
+  T V[3];
+#pragma unroll
+  for (int d = 0; d < D; ++d) V[d] = group_sum<G>(sv[d]);
+  if (wall && sub == 0) {
+    const int w = idi - k.nfluid;      // < n_wall for ids below n
+    const bool any = S > T(0);
+    const T inv = any ? T(1) / S : T(0);
+    rho[i] = k.rho0 + (any ? P * inv : T(0)) / k.c0sq;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const T ua = w < n_wall ? wall_vel[(size_t)d * n_wall + w] : T(0);
+      vel[d * n + i] = T(2) * ua - (any ? V[d] * inv : ua);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 
 
@@ -357,8 +456,8 @@ template <typename T>
 void launch_tv(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                const int* cs, T* dr, T* beta, double* s_out, T* g_out, double* partials) {
   if (g.n == 0) return;
-  SPH_SWEEP(tv_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.rho, p.mass, p.h, dr, beta, s_out,
-                                g_out, partials));
+  SPH_SWEEP(tv_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.rho, p.mass, p.h, p.id, dr, beta,
+                                s_out, g_out, partials));
 }
 
 template <typename T>
@@ -378,7 +477,17 @@ void launch_forces_fused(const Launch& l, const Grid& g, const Coeffs<T>& k, con
                                           p.acc, flags, fo));
 }
 
+template <typename T>
+void launch_wall_state(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
+                       const int* cs, const T* wall_vel, int n_wall) {
+  if (g.n == 0 || n_wall == 0) return;
+  SPH_SWEEP(wall_state_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.h, p.id, wall_vel, n_wall,
+                                        p.rho, p.vel));
+}
+
 #define SPH_INST(T)                                                                          \
+  template void launch_wall_state<T>(const Launch&, const Grid&, const Coeffs<T>&,           \
+                                     const PArrays<T>&, const int*, const T*, int);          \
   template void launch_density<T>(const Launch&, const Grid&, const Coeffs<T>&,              \
                                   const PArrays<T>&, const int*, T*, double*, int*,          \
                                   unsigned*);                                                \

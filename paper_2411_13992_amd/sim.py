@@ -87,7 +87,9 @@ class Simulation:
     """Particles on one GPU advanced by libsph's kick-drift-kick step."""
 
     def __init__(self, cfg: Config, pos, vel, mass=None, h=None, dtype: str = "f32",
-                 device: str = "cuda"):
+                 device: str = "cuda", wall_vel=None):
+        """pos, vel: (D, N) FP64 in particle-id order.  wall_vel: (D, n_wall)
+        prescribed velocities of wall particles, which are the last n_wall ids."""
         _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("Simulation needs a GPU (HIP device); there is no CPU path")
@@ -100,6 +102,8 @@ class Simulation:
         self.n = int(pos.shape[1])
         self.var = mass is not None
         self.params = make_params(cfg, self.n, dtype, self.var)
+        self.n_wall = 0 if wall_vel is None else int(np.asarray(wall_vel).shape[1])
+        self.params.n_wall = self.n_wall
         d, n, dev, T = self.dim, self.n, self.device, self.T
         self.ws_bytes = _lib.workspace_size(self.params)
         self.ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=dev)
@@ -113,6 +117,8 @@ class Simulation:
                      .contiguous() if self.var else None)
         self.h = (torch.as_tensor(np.asarray(h, dtype=np.float64), device=dev).to(T).contiguous()
                   if self.var else None)
+        self.wall_vel = (torch.as_tensor(np.asarray(wall_vel, dtype=np.float64), device=dev)
+                         .to(T).contiguous() if self.n_wall else None)
         ncells = int(np.prod(cfg.cells()[:d]))
         self.ncells = ncells
         self.cs = torch.zeros(ncells + 1, dtype=torch.int32, device=dev)
@@ -131,9 +137,10 @@ class Simulation:
     @classmethod
     def from_case(cls, case, dtype: str = "f32", **overrides):
         cfg = config_from_case(case, **overrides)
+        wv = case.wall_vel if getattr(case, "n_wall", 0) else None
         if case.uniform:
-            return cls(cfg, case.pos, case.vel, dtype=dtype)
-        return cls(cfg, case.pos, case.vel, mass=case.mass, h=case.h, dtype=dtype)
+            return cls(cfg, case.pos, case.vel, dtype=dtype, wall_vel=wv)
+        return cls(cfg, case.pos, case.vel, mass=case.mass, h=case.h, dtype=dtype, wall_vel=wv)
 
     # ------------------------------------------------------------ plumbing
     def parts(self) -> _lib.SphParticles:
@@ -143,6 +150,7 @@ class Simulation:
                                       self.acc.data_ptr(), self.rho.data_ptr())
         p.mass = self.mass.data_ptr() if self.var else None
         p.h = self.h.data_ptr() if self.var else None
+        p.wall_vel = self.wall_vel.data_ptr() if self.n_wall else None
         return p
 
     # ------------------------------------------------------------ hot path
@@ -181,9 +189,18 @@ class Simulation:
                   _vp(self.cs), _vp(out), _stream())
         return out
 
+    def wall_state(self) -> None:
+        """Wall particles' density and no-slip mirror velocity from the fluid
+        (sph_wall_state); nothing without walls."""
+        if self.n_wall:
+            _lib.call("sph_wall_state", ctypes.byref(self.params), ctypes.byref(self.parts()),
+                      _vp(self.cs), _stream())
+
     def init_fields(self) -> None:
-        """rho^0 by summation (Eq. 8) and a^0 from the initial velocity."""
+        """rho^0 by summation (Eq. 8), the walls' state, and a^0 from the
+        initial velocity."""
         self.density()
+        self.wall_state()
         self.forces()
 
     def step(self, nsteps: int = 1, diag: bool = True,

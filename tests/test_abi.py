@@ -21,10 +21,14 @@ def _declared():
 
 def test_params_layout_matches_header():
     """The ctypes mirror of sph_params has the header's field order: the
-    doubles start at byte 40 (after eight 32-bit and one 64-bit fields)."""
+    doubles start at byte 40 (after eight 32-bit and one 64-bit fields), the
+    wall count follows the sixteen doubles; sph_particles holds nine pointers."""
     assert _lib.SphParams.box.offset == 40
     assert _lib.SphParams.tv_mode.offset == 36
-    assert ctypes.sizeof(_lib.SphParams) == 40 + 8 * 16
+    assert _lib.SphParams.n_wall.offset == 40 + 8 * 16
+    assert ctypes.sizeof(_lib.SphParams) == 40 + 8 * 16 + 8
+    assert _lib.SphParticles.wall_vel.offset == 64
+    assert ctypes.sizeof(_lib.SphParticles) == 72
 
 
 def test_library_exports_every_declared_symbol():
@@ -78,6 +82,9 @@ def test_argument_validation():
         assert _status(_params(tv_mode=mode))[0] == 0
     assert _status(_params(tv_mode=3))[0] == -1
     assert _status(_params(tv_mode=-1))[0] == -1
+    assert _status(_params(n_wall=1000))[0] == 0
+    assert _status(_params(n_wall=1001))[0] == -1
+    assert _status(_params(n_wall=-1))[0] == -1
     L = _lib.load()
     assert L.sph_workspace_size(None, None) == -1
     assert b"cell grid" in L.sph_status_string(-4)
@@ -100,6 +107,26 @@ def test_null_pointers_rejected_before_launch():
                           None) == -1
     st = L.sph_build_cells(ctypes.byref(p), None, None, None, None, 0, None)
     assert st == -1
+
+
+def test_wall_arguments_checked_before_launch():
+    """Walls need their prescribed velocities; the adjoint entry points and
+    tapes refuse walled runs (SPH_E_UNSUPPORTED), all before any launch."""
+    L = _lib.load()
+    p = _params(n_wall=100)
+    parts = _lib.SphParticles()
+    for name in ("cell", "id", "off", "vel", "acc", "rho"):
+        setattr(parts, name, 4096)       # never dereferenced: the checks fail first
+    assert L.sph_wall_state(ctypes.byref(p), ctypes.byref(parts), None, None) == -1
+    assert L.sph_density(ctypes.byref(p), ctypes.byref(parts), 4096, 4096, None) == -1
+    parts.wall_vel = 4096
+    assert L.sph_kdk_step(ctypes.byref(p), ctypes.byref(parts), 4096, 0, 4096, 1 << 40,
+                          4096, None, None) == -6
+    adj = _lib.SphAdjoint(4096, 4096, 4096, 4096)
+    assert L.sph_adjoint_step(ctypes.byref(p), 4096, ctypes.byref(adj), None, 4096, 1 << 40,
+                              None) == -6
+    assert L.sph_adjoint_init(ctypes.byref(p), ctypes.byref(parts), 4096, ctypes.byref(adj),
+                              4096, 1 << 40, None) == -6
 
 
 @pytest.mark.parametrize("dim", [2, 3])

@@ -1,0 +1,186 @@
+"""Wall particles on the GPU path (the lid-driven cavity of Sec. 4.2) against
+the FP64 oracle: the wall-state sweep, the density / correction / force sweeps
+with walls among the neighbours, whole steps, fused runs, a 100-step FP64
+cavity trajectory, and FP32 Couette start-up against its series solution."""
+import numpy as np
+import pytest
+
+import cases
+import oracle
+from tests import parity_utils as pu
+
+pytestmark = pytest.mark.gpu
+
+CAVITY = cases.lid_driven_cavity(24, name="cavity24")
+
+
+def _sim(case, dtype, warm=0, **kw):
+    import torch
+    from paper_2411_13992_amd import Simulation
+    sim = Simulation.from_case(case, dtype=dtype, **kw)
+    if warm:
+        sim.run(warm, diag=False)
+    torch.cuda.synchronize()
+    return sim
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_wall_state_parity(dtype):
+    """After 30 steps of the cavity, sph_wall_state from the current fluid
+    density and velocity against the oracle's wall state: every wall
+    particle's density (/ rho0) and mirror velocity (/ U)."""
+    sim = _sim(CAVITY, dtype, warm=30)
+    sim.wall_state()
+    st, mass, h = pu.gpu_inputs(sim, CAVITY)
+    nb = oracle.neighbors(st["pos"], h, CAVITY.box)
+    rho, vel = oracle.wall_bc(st["pos"], st["vel"], st["rho"], h, CAVITY.box, nb,
+                              CAVITY.n_wall, CAVITY.wall_vel, CAVITY.rho0, CAVITY.c0)
+    nf = CAVITY.n_fluid
+    tol = pu.TOL[dtype]
+    assert np.abs(st["rho"][nf:] - rho[nf:]).max() / CAVITY.rho0 < tol
+    assert np.abs(st["vel"][:, nf:] - vel[:, nf:]).max() / CAVITY.u_ref < 10 * tol
+    # the lid's mirror velocity is well away from zero: the test is not vacuous
+    assert np.abs(vel[0, nf:]).max() > 1.0
+    assert sim.flags() == 0
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_sweeps_with_walls(dtype):
+    """Density of every particle; correction and accelerations of the fluid
+    (walls get none: zero on the GPU) on the summation-error scale."""
+    import torch
+    sim = _sim(CAVITY, dtype, warm=30)
+    st, mass, h = pu.gpu_inputs(sim, CAVITY)
+    nb = oracle.neighbors(st["pos"], h, CAVITY.box)
+    nf = CAVITY.n_fluid
+    order = st["order"]
+    tol = pu.TOL[dtype]
+    rho_gpu = sim.density(out=torch.empty_like(sim.rho)).cpu().double().numpy()[order]
+    rho = oracle.density(st["pos"], mass, h, CAVITY.box, nb, oracle.lattice_kappa(2))
+    assert np.abs(rho_gpu - rho).max() / CAVITY.rho0 < tol
+    acc_gpu = sim.forces(out=torch.empty_like(sim.acc)).cpu().double().numpy()[:, order]
+    acc, scale = oracle.forces(st["pos"], st["vel"], mass, st["rho"], h, CAVITY.box, nb,
+                               CAVITY.rho0, CAVITY.c0, CAVITY.eta, CAVITY.riemann_eta)
+    assert np.max(np.abs(acc_gpu[:, :nf] - acc[:, :nf]) / scale[:nf]) < tol
+    assert np.all(acc_gpu[:, nf:] == 0.0)
+    ref = oracle.tv(st["pos"], mass, st["rho"], h, CAVITY.box, nb, CAVITY.h_min, xi=CAVITY.xi,
+                    lim_c=CAVITY.lim_c, lim_s0=CAVITY.lim_s0, tv_mode="scaled")
+    sim.cfg.tv_mode = "scaled"
+    from paper_2411_13992_amd import _lib
+    sim.params.tv_mode = _lib.TV_SCALED
+    out = sim.tv_correction()
+    g = out["g"].cpu().double().numpy()[:, order]
+    dr = out["dr"].cpu().double().numpy()[:, order]
+    beta = out["beta"].cpu().double().numpy()[order]
+    assert np.max(np.abs(g[:, :nf] - ref["g"][:, :nf]) / ref["gscale"][:nf]) < tol
+    assert np.all(g[:, nf:] == 0.0) and np.all(dr[:, nf:] == 0.0) and np.all(beta[nf:] == 0.0)
+    assert np.all(beta[:nf] == 1.0)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("mode", ["limited", "scaled"])
+def test_step_parity_walls(dtype, mode):
+    """One kick-drift-kick step of the cavity from an identical state (after 30
+    steps, the lid's boundary layer developing): every particle's position,
+    velocity (walls: the mirror velocity) and density, and the fluid's
+    acceleration.  Limiter-branch flips (limited form) must lie in the rounding
+    band of Eq. 15 and are excluded with two neighbour hops, as for the
+    periodic cases."""
+    import torch
+    sim = _sim(CAVITY, dtype, warm=30, tv_mode=mode)
+    st, mass, h = pu.gpu_inputs(sim, CAVITY)
+    rc = pu.case_with(CAVITY, mass, h)
+    ref = oracle.State(rc, pos=st["pos"], vel=st["vel"], rho=st["rho"], acc=st["acc"],
+                       tv_mode=mode)
+    ref.step_index = sim.step_index
+    nb0 = oracle.neighbors(st["pos"], h, CAVITY.box)
+    tv0 = oracle.tv(st["pos"], mass, st["rho"], h, CAVITY.box, nb0, CAVITY.h_min, tv_mode=mode)
+    nf = CAVITY.n_fluid
+    tv0["beta"][nf:] = 0.0
+    band = pu.limiter_band(tv0["s"], tv0["g"], tv0["gscale"], CAVITY.h_min, CAVITY.lim_s0,
+                           dtype)
+    beta_gpu = sim.tv_correction()["beta"].cpu().double().numpy()[st["order"]]
+    torch.cuda.synchronize()
+    flipped = (beta_gpu > 0) != (tv0["beta"] > 0)
+    assert not np.any(flipped & ~band)
+    sim.step(1)
+    d = ref.step()
+    out = sim.export()
+    skip = pu.widen(oracle.neighbors(ref.pos, h, CAVITY.box), flipped, 2)
+    assert skip.mean() < 0.5
+    ok = ~skip
+    tol = pu.TOL[dtype]
+    e_pos = np.abs(pu.min_image(out["pos"], ref.pos, CAVITY.box)[:, ok]).max() / CAVITY.dx
+    e_vel = np.abs(out["vel"] - ref.vel)[:, ok].max() / CAVITY.u_ref
+    e_rho = np.abs(out["rho"] - ref.rho)[ok].max() / CAVITY.rho0
+    okf = ok[:nf]
+    e_acc = (np.abs(out["acc"][:, :nf] - ref.acc[:, :nf])[:, okf].max()
+             / (CAVITY.c0 ** 2 / CAVITY.h_min))
+    assert e_pos < tol and e_vel < 10 * tol and e_rho < tol and e_acc < tol, \
+        (e_pos, e_vel, e_rho, e_acc)
+    assert np.array_equal(out["pos"][:, nf:], st["pos"][:, nf:])
+    assert np.all(out["acc"][:, nf:] == 0.0)
+    diag = sim.diagnostics()
+    assert abs(diag["ke"] / d["ke"] - 1.0) < 10 * tol
+    assert sim.flags() == 0
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_fused_run_equals_single_steps_walls(dtype):
+    """sph_kdk_run and repeated sph_kdk_step agree bit for bit with walls."""
+    import torch
+    a = _sim(CAVITY, dtype)
+    b = _sim(CAVITY, dtype)
+    rows = []
+    for _ in range(6):
+        a.step(1)
+        rows.append(a.diag.clone())
+    d = b.run(6)
+    torch.cuda.synchronize()
+    for key in ("cell", "id", "off", "vel", "acc", "rho", "cs"):
+        assert torch.equal(getattr(a, key), getattr(b, key)), key
+    assert torch.equal(torch.stack(rows), d)
+
+
+def test_walls_refuse_tapes():
+    import torch
+    from paper_2411_13992_amd import _lib
+    sim = _sim(CAVITY, "f32")
+    tapes = torch.empty(2 * sim.tape_bytes(), dtype=torch.uint8, device=sim.device)
+    with pytest.raises(_lib.SphError) as e:
+        sim.run(2, diag=False, tapes=tapes)
+    assert e.value.status == -6
+
+
+def test_cavity_fp64_trajectory():
+    """100 FP64 steps of a 30x30 cavity (Re = 1000), GPU against the oracle
+    from the same initial state: kinetic energy and the largest speed every
+    step, positions and velocities of every particle at the end."""
+    case = cases.lid_driven_cavity(30, name="cavity30")
+    sim = _sim(case, "f64")
+    st, mass, h = pu.gpu_inputs(sim, case)
+    ref = oracle.State(case, pos=st["pos"], vel=st["vel"], rho=st["rho"], acc=st["acc"])
+    rows = sim.run(100, diag=True).cpu().numpy()
+    d = ref.run(100)
+    assert np.max(np.abs(rows[:, 0] / d[:, 0] - 1.0)) < 1e-9
+    assert np.max(np.abs(rows[:, 4] / d[:, 4] - 1.0)) < 1e-9
+    out = sim.export()
+    assert np.abs(pu.min_image(out["pos"], ref.pos, case.box)).max() / case.dx < 1e-9
+    assert np.abs(out["vel"] - ref.vel).max() / case.u_ref < 1e-9
+    assert sim.flags() == 0
+
+
+def test_couette_fp32_startup():
+    """FP32 Couette start-up on the GPU (Re = 10, 20 particles across) against
+    the series solution of the diffusion equation at t = 0.5: within 1% U."""
+    from tests.test_oracle_walls import _couette_series
+    case = cases.couette_2d(20, re=10.0)
+    sim = _sim(case, "f32")
+    sim.run(int(round(0.5 / case.dt)), diag=False)
+    out = sim.export()
+    nf = case.n_fluid
+    t = sim.step_index * case.dt
+    y = out["pos"][1, :nf] - case.extra["origin"]
+    err = np.abs(out["vel"][0, :nf] - _couette_series(y, t, case.nu))
+    assert err.max() < 1e-2, err.max()
+    assert sim.flags() == 0
