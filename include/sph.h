@@ -107,6 +107,11 @@ typedef struct {
                              the diagnostics: |s - s0| <= band_tol * s0          */
     int64_t n_wall;       /* 0 <= n_wall <= n: particles with id >= n - n_wall
                              are wall particles (see sph_wall_state)             */
+    int32_t lanes;        /* lanes per particle in the neighbour sweeps: 2, 4 or
+                             8, or 0 to let the library choose by size (more
+                             lanes for small n); other values: SPH_E_ARG.  The
+                             choice changes only the summation order (results
+                             within rounding, not bit-identical across lanes)  */
 } sph_params;
 
 /* Particle arrays, all device pointers of length N (or [D][N]). */

@@ -50,7 +50,7 @@ class SphParams(ctypes.Structure):
         ("kappa", ctypes.c_double), ("dt", ctypes.c_double), ("xi", ctypes.c_double),
         ("lim_c", ctypes.c_double), ("lim_s0", ctypes.c_double),
         ("riemann_eta", ctypes.c_double), ("band_tol", ctypes.c_double),
-        ("n_wall", ctypes.c_int64),
+        ("n_wall", ctypes.c_int64), ("lanes", ctypes.c_int32),
     ]
 
 

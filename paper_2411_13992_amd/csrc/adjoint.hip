@@ -51,7 +51,7 @@ __device__ __forceinline__ bool pair_kernel(const Coeffs<T>& k, T r2, T hi, T hj
 // v_perp = v_ij - (v_ij . r) r / |r|^2.  The long pair body runs over a
 // per-thread neighbour list (positions are tested first).
 template <int G>
-struct VjpCap { static constexpr int value = G == 1 ? 48 : (G == 2 ? 24 : 16); };
+struct VjpCap { static constexpr int value = G == 2 ? 24 : (G == 4 ? 16 : 8); };
 
 template <int D, typename T, bool VAR, int G>
 __global__ __launch_bounds__(kBlock) void force_vjp_kernel(

@@ -71,12 +71,17 @@ struct Cursor {
   }
 };
 
+// lanes per particle of every sweep: params.lanes, or chosen by size (0)
+int lanes_of(const sph_params* p) {
+  return p->lanes != 0 ? p->lanes : lanes_per_particle(p->dim, (long)p->n);
+}
+
 Sizes sizes_of(const sph_params* p, bool var) {
   Sizes s;
   s.dim = p->dim;
   s.n = (int)p->n;
   s.ncells = p->ncell[0] * p->ncell[1] * (p->dim == 3 ? p->ncell[2] : 1);
-  s.nblk = blocks_for((long)s.n * lanes_per_particle(s.dim));
+  s.nblk = blocks_for((long)s.n * lanes_of(p));
   s.tsz = p->dtype == SPH_F64 ? 8 : 4;
   s.var = var;
   return s;
@@ -155,6 +160,7 @@ int32_t check_params(const sph_params* p) {
       p->tv_mode != SPH_TV_BACKGROUND)
     return SPH_E_ARG;
   if (p->n_wall < 0 || p->n_wall > p->n) return SPH_E_ARG;
+  if (p->lanes != 0 && p->lanes != 2 && p->lanes != 4 && p->lanes != 8) return SPH_E_ARG;
   const double vals[] = {p->rho0, p->c0, p->h_min, p->h_max, p->kappa, p->mass};
   for (double v : vals)
     if (!std::isfinite(v)) return SPH_E_NONFINITE;
@@ -286,7 +292,7 @@ Launch launch_of(const sph_params* p, bool var, void* stream) {
   l.dim = p->dim;
   l.var = var;
   l.stream = (hipStream_t)stream;
-  l.G = lanes_per_particle(p->dim);
+  l.G = lanes_of(p);
   l.nblk = blocks_for(p->n * l.G);
   return l;
 }

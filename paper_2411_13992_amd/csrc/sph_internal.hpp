@@ -20,13 +20,22 @@ struct Launch {
                        // diagnostic partials: ceil(n * G / kBlock)
 };
 
-// Lanes per particle for the neighbour sweeps.  A group of lanes shares one
-// particle's candidate cells, which puts more wavefronts in flight and splits
-// the serial candidate walk; the price is the group reduction and an epilogue
-// run by one lane in G.  Measured on gfx950: in 2-D (9 cells, about 60
-// candidates per particle) two lanes beat one and four; in 3-D (27 cells,
-// about 470 candidates) four lanes cut the force sweep by 2x over two.
-inline int lanes_per_particle(int dim) { return dim == 3 ? 4 : 2; }
+// Lanes per particle for the neighbour sweeps (2, 4 or 8).  A group of lanes
+// shares one particle's candidate cells, which puts more wavefronts in flight
+// and splits the serial candidate walk; the price is the group reduction and
+// an epilogue run by one lane in G.  The largest G whose n * G lanes fit a
+// budget (2^18 in 2-D, 2^19 in 3-D: the 3-D walk is ~8x longer), at least 2
+// in 2-D and 4 in 3-D.  Measured on gfx950 (FP32 step, us): 2-D 2.5k
+// particles 39.9 / 33.7 / 28.9 for G = 2 / 4 / 8, 40k 46.3 / 39.8 / 42.1,
+// 160k 66.1 / 79.7 / 114.8; 3-D 4k 420 / 119 / 86, 33k 310 / 136 / 120,
+// 262k 883 / 510 / 609.
+inline int lanes_per_particle(int dim, long n) {
+  const long budget = dim == 3 ? (1L << 19) : (1L << 18);
+  const int gmin = dim == 3 ? 4 : 2;
+  for (int g = 8; g > gmin; g /= 2)
+    if (n * g <= budget) return g;
+  return gmin;
+}
 
 inline int blocks_for(long n) { return (int)((n + kBlock - 1) / kBlock); }
 
@@ -166,7 +175,7 @@ void launch_xi_final(hipStream_t s, int n, const double* partials, double* xi_ba
     else if (l.G == 2)                                                                        \
       hipLaunchKernelGGL((KERNEL<DD, T, VV, 2>), grid_, block_, 0, l.stream, __VA_ARGS__);    \
     else                                                                                      \
-      hipLaunchKernelGGL((KERNEL<DD, T, VV, 1>), grid_, block_, 0, l.stream, __VA_ARGS__);    \
+      hipLaunchKernelGGL((KERNEL<DD, T, VV, 8>), grid_, block_, 0, l.stream, __VA_ARGS__);    \
   } while (0)
 #define SPH_SWEEP(KERNEL, ARGS)                                                               \
   do {                                                                                        \

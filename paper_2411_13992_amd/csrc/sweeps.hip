@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
 // per-thread LDS list (for_each_neighbour_listed): positions are tested for
 // every candidate, the body runs for neighbours only.
 template <int G>
-struct ForceCap { static constexpr int value = G == 1 ? 48 : (G == 2 ? 24 : 16); };
+struct ForceCap { static constexpr int value = G == 2 ? 24 : (G == 4 ? 16 : 8); };
 
 template <int D, typename T, bool VAR, bool FUSED, int G>
 __device__ __forceinline__ void forces_impl(

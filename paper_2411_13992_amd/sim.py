@@ -46,6 +46,7 @@ class Config:
     band_tol: float = 1.0e-5
     h_over_dx: float = 1.3    # Sec. 4: h = 1.3 dp, fixes the reference kernel sum
     ncell: tuple | None = None
+    lanes: int = 0            # lanes per particle in the sweeps (0: chosen by size)
 
     def cells(self):
         if self.ncell is not None:
@@ -80,6 +81,7 @@ def make_params(cfg: Config, n: int, dtype: str, per_particle: bool = False) -> 
     p.kappa = _lib.lattice_kappa(cfg.dim, cfg.h_over_dx)
     p.dt, p.xi, p.lim_c, p.lim_s0 = cfg.dt, cfg.xi, cfg.lim_c, cfg.lim_s0
     p.riemann_eta, p.band_tol = cfg.riemann_eta, cfg.band_tol
+    p.lanes = cfg.lanes
     return p
 
 

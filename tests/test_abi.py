@@ -22,11 +22,13 @@ def _declared():
 def test_params_layout_matches_header():
     """The ctypes mirror of sph_params has the header's field order: the
     doubles start at byte 40 (after eight 32-bit and one 64-bit fields), the
-    wall count follows the sixteen doubles; sph_particles holds nine pointers."""
+    wall count and the lane count follow the sixteen doubles; sph_particles
+    holds nine pointers."""
     assert _lib.SphParams.box.offset == 40
     assert _lib.SphParams.tv_mode.offset == 36
     assert _lib.SphParams.n_wall.offset == 40 + 8 * 16
-    assert ctypes.sizeof(_lib.SphParams) == 40 + 8 * 16 + 8
+    assert _lib.SphParams.lanes.offset == 40 + 8 * 16 + 8
+    assert ctypes.sizeof(_lib.SphParams) == 40 + 8 * 16 + 16
     assert _lib.SphParticles.wall_vel.offset == 64
     assert ctypes.sizeof(_lib.SphParticles) == 72
 
@@ -85,6 +87,10 @@ def test_argument_validation():
     assert _status(_params(n_wall=1000))[0] == 0
     assert _status(_params(n_wall=1001))[0] == -1
     assert _status(_params(n_wall=-1))[0] == -1
+    for lanes in (0, 2, 4, 8):
+        assert _status(_params(lanes=lanes))[0] == 0
+    assert _status(_params(lanes=3))[0] == -1
+    assert _status(_params(lanes=16))[0] == -1
     L = _lib.load()
     assert L.sph_workspace_size(None, None) == -1
     assert b"cell grid" in L.sph_status_string(-4)
@@ -95,6 +101,8 @@ def test_sizes_grow_with_n_and_dtype():
     s32b = _status(_params(n=5000))[1]
     s64 = _status(_params(n=1000, dtype=_lib.SPH_F64))[1]
     assert s32b > s32 and s64 > s32
+    # more lanes per particle: more diagnostic partial rows
+    assert _status(_params(lanes=8))[1] > _status(_params(lanes=2))[1]
     assert _lib.tape_size(_params()) > 0
 
 
@@ -134,3 +142,21 @@ def test_library_kappa_matches_oracle(dim):
     """The library's reference kernel sum (Eq. 8) agrees with the oracle's,
     two independent codes of the same lattice sum."""
     assert abs(_lib.lattice_kappa(dim, 1.3) - oracle.lattice_kappa(dim, 1.3)) < 1e-14
+
+
+def test_automatic_lane_choice():
+    """0 picks by size: 8 for small inputs, 2 (2-D) or 4 (3-D) for the
+    benchmark workloads; the choice shows in the workspace size."""
+    from paper_2411_13992_amd import _lib
+    from paper_2411_13992_amd.sim import config_from_case, make_params
+
+    def ws(case, lanes):
+        p = make_params(config_from_case(case, lanes=lanes), case.n, "f32")
+        return _lib.workspace_size(p)
+    import cases
+    small = cases.taylor_green_2d(37, jitter=0.05, seed=9)
+    assert ws(small, 0) == ws(small, 8)
+    big = cases.taylor_green_2d(400, jitter=0.05)
+    assert ws(big, 0) == ws(big, 2)
+    cube = cases.taylor_green_3d(128)
+    assert ws(cube, 0) == ws(cube, 4)

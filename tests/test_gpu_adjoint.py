@@ -92,19 +92,22 @@ def _step_loss(sim, c, base_snap):
                  + np.sum(c["rho"] * ex["rho"]))
 
 
-@pytest.mark.parametrize("name,mode", [(name, "limited") for name in INIT] +
-                         [("tg2d_jit", "scaled"), ("tg2d_jit", "background"),
-                          ("tg3d_jit", "background"), ("varres", "scaled")])
-def test_step_vjp_matches_fd(name, mode):
+@pytest.mark.parametrize("name,mode,lanes", [(name, "limited", 0) for name in INIT] +
+                         [("tg2d_jit", "scaled", 0), ("tg2d_jit", "background", 0),
+                          ("tg3d_jit", "background", 0), ("varres", "scaled", 0)] +
+                         [(name, "limited", lanes) for name in INIT for lanes in (2, 4)])
+def test_step_vjp_matches_fd(name, mode, lanes):
     """One kick-drift-kick step as a map of (r^n, v^n, a^n, rho^n, xi): the
     reverse step agrees with a central difference of the FP64 forward, with
     the correction active (jittered input; the limited formulation with its
     limiter in all three branches, the unlimited ones of Eq. 14 and Eq. 12,
-    where the latter has no xi and a 1/rho_i factor)."""
+    where the latter has no xi and a 1/rho_i factor).  These small inputs run
+    eight lanes per particle by default; lanes 2 and 4 cover the sweeps of
+    the larger workloads."""
     import torch
     from paper_2411_13992_amd.adjoint import Adjoint, adjoint_step
     case = INIT[name]
-    sim = _sim(case, "f64", tv_mode=mode)
+    sim = _sim(case, "f64", tv_mode=mode, lanes=lanes)
     d, n = sim.dim, sim.n
     rng = np.random.default_rng(5)
     start = sim.snapshot()

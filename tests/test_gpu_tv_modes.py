@@ -119,7 +119,10 @@ def test_tg2d_50_fp64_trajectory_modes(mode):
     1e-14 dx separate by ~2e-6 dx with Eq. 14 and ~1e-4 dx with Eq. 12, against
     ~2e-10 dx with the limiter), since without the threshold of Eq. 15 every
     particle's correction is applied, including sums g that on the deforming
-    lattice are cancellation residues."""
+    lattice are cancellation residues.  The same two oracle runs differ in
+    kinetic energy by up to 2.5e-10 (Eq. 14) and 2.5e-9 (Eq. 12) relative
+    over the 100 steps, so the energy gate is 1e-8 and 3e-8 (about ten
+    times that), not the limited form's 1e-9."""
     case = cases.make("tg2d_50")
     sim = _sim(case, "f64", tv_mode=mode)
     st, mass, h = pu.gpu_inputs(sim, case)
@@ -132,7 +135,8 @@ def test_tg2d_50_fp64_trajectory_modes(mode):
     rows.append(sim.run(case.steps - 60, diag=True).cpu().numpy())
     d.append(ref.run(case.steps - 60))
     rows, d = np.concatenate(rows), np.concatenate(d)
-    assert np.max(np.abs(rows[:, 0] / d[:, 0] - 1.0)) < 1e-9
+    ke_gate = {"scaled": 1e-8, "background": 3e-8}[mode]
+    assert np.max(np.abs(rows[:, 0] / d[:, 0] - 1.0)) < ke_gate
     late = d[:, 8] > 1e-3 * case.u_ref
     assert late.any()
     assert np.max(np.abs(rows[late, 8] / d[late, 8] - 1.0)) < 1e-6

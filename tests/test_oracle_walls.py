@@ -169,3 +169,4 @@ def test_couette_startup_matches_series_and_settles_linear():
     d = st.run(1)
     assert abs(d[0, 0] - 0.5 * np.sum(case.mass[:nf] * np.sum(st.vel[:, :nf] ** 2, axis=0))) \
         < 1e-12 * ke
+
