@@ -46,6 +46,10 @@ WORKLOADS = {
                     "particles at rest inside three layers of wall particles (42,436 "
                     "particles), lid at U = 1, correction with limiter every step, FP32 "
                     "sweeps with FP64 reductions",
+    "cavity3d_128": "3-D lid-driven cavity, dp = 1/128, Re = 100, 128^3 fluid particles at "
+                    "rest inside three layers of wall particles (2,406,104 particles), lid "
+                    "velocity (1, 0, 0), correction with limiter every step, FP32 sweeps "
+                    "with FP64 reductions",
 }
 
 # Algorithmic work per interacting pair of the force sweep: the operations of

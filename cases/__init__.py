@@ -255,42 +255,58 @@ def variable_resolution_2d(dp_min: float = 1.0 / 1306, jitter: float = 0.1, seed
                 extra={"jitter": jitter, "seed": seed, "columns": len(widths)})
 
 
-def _walled_box(nx: int, ny: int, layers: int, dx: float, wall_x: bool):
-    """Fluid on the nx x ny cell-centred lattice of [0, nx dx) x [0, ny dx),
-    then `layers` rows of wall particles on the same lattice below and above it
-    (and, with wall_x, `layers` columns left and right, corners included).
-    Returns (fluid positions, wall positions) in wall-box coordinates: the
-    periodic box starts `layers` spacings below / left of the fluid."""
+def _walled_box(nx: int, ny: int, layers: int, dx: float, wall_x: bool, nz: int = 0):
+    """Fluid on the cell-centred lattice of [0, nx dx) x [0, ny dx) (x [0, nz dx)
+    in 3-D), then `layers` rows of wall particles on the same lattice below and
+    above it in y (and, with wall_x, `layers` columns left and right in x and,
+    in 3-D, in front and behind in z; edges and corners included).  Returns
+    (fluid positions, wall positions, wall-above-the-fluid mask) in wall-box
+    coordinates: the periodic box starts `layers` spacings below / left of /
+    in front of the fluid on every walled axis (x fastest, then y, then z)."""
     lx = layers if wall_x else 0
     ix = np.arange(-lx, nx + lx)
     iy = np.arange(-layers, ny + layers)
-    gx, gy = np.meshgrid(ix, iy, indexing="xy")        # x fastest
-    gx, gy = gx.reshape(-1), gy.reshape(-1)
-    fluid = (gx >= 0) & (gx < nx) & (gy >= 0) & (gy < ny)
-    pts = np.stack([(gx + lx + 0.5) * dx, (gy + layers + 0.5) * dx])
+    if nz:
+        iz = np.arange(-layers, nz + layers)
+        gz, gy, gx = np.meshgrid(iz, iy, ix, indexing="ij")     # x fastest
+        gx, gy, gz = gx.reshape(-1), gy.reshape(-1), gz.reshape(-1)
+        fluid = ((gx >= 0) & (gx < nx) & (gy >= 0) & (gy < ny) & (gz >= 0) & (gz < nz))
+        pts = np.stack([(gx + lx + 0.5) * dx, (gy + layers + 0.5) * dx,
+                        (gz + layers + 0.5) * dx])
+    else:
+        gx, gy = np.meshgrid(ix, iy, indexing="xy")            # x fastest
+        gx, gy = gx.reshape(-1), gy.reshape(-1)
+        fluid = (gx >= 0) & (gx < nx) & (gy >= 0) & (gy < ny)
+        pts = np.stack([(gx + lx + 0.5) * dx, (gy + layers + 0.5) * dx])
     return pts[:, fluid], pts[:, ~fluid], gy[~fluid] >= ny
 
 
-def lid_driven_cavity(n: int, re: float = 1000.0, u_lid: float = 1.0, layers: int = 3,
-                      steps: int = 1000, name: str | None = None) -> Case:
-    """2-D lid-driven square cavity of side 1 (Sec. 4.2, Re = U L / nu).
+def lid_driven_cavity(n: int, re: float | None = None, u_lid: float = 1.0, layers: int = 3,
+                      dim: int = 2, steps: int = 1000, name: str | None = None) -> Case:
+    """Lid-driven cavity of side 1: 2-D (Sec. 4.2, Re = 1000 by default) or
+    3-D (the cube of the three-dimensional cavity section, Re = 100 by
+    default), Re = U L / nu.
 
-    Fluid at rest on the n x n cell-centred lattice of the unit square; wall
-    particles continue the lattice `layers` spacings beyond every side (corner
-    blocks included).  The top wall (every wall particle above the fluid,
-    corner blocks included) moves at (u_lid, 0); the other walls are at rest.
-    Coordinates are shifted by layers*dp so the box [0, 1 + 2 layers dp)^2 is
-    the periodic box of the cell grid; with layers*dp >= 2h (layers >= 3 at
-    h = 1.3 dp) no fluid particle has a neighbour across its seam.  Ids: the
-    fluid first (x fastest), then the walls (x fastest).
+    Fluid at rest on the n^D cell-centred lattice of the unit square / cube;
+    wall particles continue the lattice `layers` spacings beyond every face
+    (edges and corners included).  The top wall (every wall particle above
+    the fluid in y, its edge and corner blocks included) moves at (u_lid, 0[,
+    0]); the other walls are at rest.  Coordinates are shifted by layers*dp so
+    the box [0, 1 + 2 layers dp)^D is the periodic box of the cell grid; with
+    layers*dp >= 2h (layers >= 3 at h = 1.3 dp) no fluid particle has a
+    neighbour across its seams.  Ids: the fluid first (x fastest), then the
+    walls (x fastest).
     """
     if layers * 1.0 < 2 * H_OVER_DP:
         raise ValueError("layers must cover the kernel support 2h")
+    if dim not in (2, 3):
+        raise ValueError("dim is 2 or 3")
+    re = (1000.0 if dim == 2 else 100.0) if re is None else re
     dx = 1.0 / n
-    fluid, wall, top = _walled_box(n, n, layers, dx, True)
+    fluid, wall, top = _walled_box(n, n, layers, dx, True, nz=n if dim == 3 else 0)
     pos = np.concatenate([fluid, wall], axis=1)
     nw = wall.shape[1]
-    wall_vel = np.zeros((2, nw))
+    wall_vel = np.zeros((dim, nw))
     wall_vel[0, top] = u_lid
     vel = np.zeros_like(pos)
     vel[:, fluid.shape[1]:] = wall_vel
@@ -299,9 +315,9 @@ def lid_driven_cavity(n: int, re: float = 1000.0, u_lid: float = 1.0, layers: in
     eta = rho0 * u_lid * 1.0 / re
     npart = pos.shape[1]
     edge = (n + 2 * layers) * dx
-    return Case(name=name or f"cavity2d_{n}", dim=2, pos=pos, vel=vel,
-                mass=np.full(npart, rho0 * dx * dx), h=np.full(npart, H_OVER_DP * dx),
-                box=(edge, edge), dx=dx, rho0=rho0, c0=c0, eta=eta, u_ref=u_lid,
+    return Case(name=name or f"cavity{dim}d_{n}", dim=dim, pos=pos, vel=vel,
+                mass=np.full(npart, rho0 * dx ** dim), h=np.full(npart, H_OVER_DP * dx),
+                box=(edge,) * dim, dx=dx, rho0=rho0, c0=c0, eta=eta, u_ref=u_lid,
                 dt=_dt(H_OVER_DP * dx, u_lid, c0, eta / rho0), steps=steps, uniform=True,
                 extra={"re": re, "layers": layers, "origin": layers * dx, "side": 1.0},
                 n_wall=nw, wall_vel=wall_vel)
@@ -351,6 +367,8 @@ CONFIGS = {
                                                 steps=200, name="adjoint_tg2d_200"),
     # walls: the lid-driven cavity (Sec. 4.2) at dp = 1/200, Re = 1000
     "cavity2d_200": lambda: lid_driven_cavity(200, name="cavity2d_200"),
+    # the three-dimensional cavity at dp = 1/128, Re = 100 (2.4M particles)
+    "cavity3d_128": lambda: lid_driven_cavity(128, dim=3, name="cavity3d_128"),
 }
 
 

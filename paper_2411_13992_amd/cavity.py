@@ -1,13 +1,14 @@
-"""Lid-driven cavity study of Sec. 4.2 on the GPU: a unit square cavity whose
-top wall moves at U = 1, Re = U L / nu = 1000, run to t_end at several
-resolutions dp = 1/n with the limited correction (Eq. 16) and, for
-comparison, the unlimited h-scaled one (Eq. 14).  Reported: the horizontal
-velocity u along the vertical centre line x = L/2 and the vertical velocity v
-along the horizontal centre line y = L/2, and their self-convergence (the
-paper's reference data are not used here: only differences between
-resolutions).
+"""Lid-driven cavity studies on the GPU: the unit square of Sec. 4.2 (top
+wall moving at U = 1, Re = U L / nu = 1000) and the unit cube of the
+three-dimensional cavity section (lid velocity (1, 0, 0), Re = 100), run to
+t_end at several resolutions dp = 1/n with the limited correction (Eq. 16)
+and, for comparison, the unlimited h-scaled one (Eq. 14).  Reported: the
+horizontal velocity u along the vertical centre line x = L/2 and the vertical
+velocity v along the horizontal centre line y = L/2 (in the middle plane
+z = L/2 in 3-D), and their self-convergence (the paper's reference data are
+not used here: only differences between resolutions).
 
-    python -m paper_2411_13992_amd.cavity [--n 50 100 200] [--t-end 30]
+    python -m paper_2411_13992_amd.cavity [--dim 2] [--n 50 100 200] [--t-end 30]
         [--modes limited scaled] [--dtype f32] [--json out.json]
 
 Every step runs through sph_kdk_run.  The centre-line values are
@@ -45,26 +46,29 @@ def shepard(points: np.ndarray, pos: np.ndarray, values: np.ndarray, h: float) -
 
 
 def centre_lines(case, state: dict) -> dict:
-    """u(x = 1/2, y) and v(x, y = 1/2) at PROBES (cavity coordinates)."""
+    """u(x = 1/2, y) and v(x, y = 1/2) at PROBES (cavity coordinates; z = 1/2
+    in 3-D)."""
     nf = case.n_fluid
     o = case.extra["origin"]
     pos = state["pos"][:, :nf] - o
     vel = state["vel"][:, :nf]
     h = float(case.h_min)
-    vline = np.stack([np.full_like(PROBES, 0.5), PROBES])
-    hline = np.stack([PROBES, np.full_like(PROBES, 0.5)])
+    half = np.full_like(PROBES, 0.5)
+    vline = np.stack([half, PROBES] + [half] * (case.dim - 2))
+    hline = np.stack([PROBES, half] + [half] * (case.dim - 2))
     return {"y": PROBES.tolist(), "u": shepard(vline, pos, vel[:1], h)[0].tolist(),
-            "x": PROBES.tolist(), "v": shepard(hline, pos, vel[1:], h)[0].tolist()}
+            "x": PROBES.tolist(), "v": shepard(hline, pos, vel[1:2], h)[0].tolist()}
 
 
-def run(n: int, t_end: float, mode: str = "limited", dtype: str = "f32", re: float = 1000.0,
-        chunk: int = 5000) -> dict:
+def run(n: int, t_end: float, mode: str = "limited", dtype: str = "f32",
+        re: float | None = None, chunk: int = 5000, dim: int = 2) -> dict:
     import torch
 
     import cases
     from .sim import Simulation
 
-    case = cases.lid_driven_cavity(n, re=re)
+    case = cases.lid_driven_cavity(n, re=re, dim=dim)
+    re = case.extra["re"]
     sim = Simulation.from_case(case, dtype=dtype, tv_mode=mode)
     nsteps = int(round(t_end / case.dt))
     ke = []
@@ -82,7 +86,7 @@ def run(n: int, t_end: float, mode: str = "limited", dtype: str = "f32", re: flo
     # steadiness: relative change of the kinetic energy over the last tenth of the run
     tenth = max(len(ke) // 10, 1)
     drift = abs(ke[-1] - ke[-1 - tenth]) / ke[-1] if len(ke) > tenth else float("nan")
-    out = {"n": n, "mode": mode, "dtype": dtype, "re": re, "particles": case.n,
+    out = {"n": n, "dim": dim, "mode": mode, "dtype": dtype, "re": re, "particles": case.n,
            "fluid": case.n_fluid, "dt": case.dt, "steps": nsteps, "t": nsteps * case.dt,
            "wall_s": wall, "us_per_step": wall / nsteps * 1e6, "flags": sim.flags(),
            "ke_per_chunk": ke, "ke_final": ke[-1], "ke_change_last_tenth": drift}
@@ -116,7 +120,10 @@ def main(argv=None):
     ap.add_argument("--n", type=int, nargs="+", default=[50, 100, 200],
                     help="particles per side (dp = 1/n)")
     ap.add_argument("--t-end", type=float, default=30.0)
-    ap.add_argument("--re", type=float, default=1000.0)
+    ap.add_argument("--dim", type=int, default=2, choices=(2, 3))
+    ap.add_argument("--re", type=float, default=None,
+                    help="Reynolds number (default 1000 in 2-D, 100 in 3-D)")
+    ap.add_argument("--chunk", type=int, default=5000, help="steps per fused run")
     ap.add_argument("--dtype", default="f32", choices=("f32", "f64"))
     ap.add_argument("--modes", nargs="+", default=["limited", "scaled"],
                     choices=("limited", "scaled", "background"))
@@ -126,7 +133,7 @@ def main(argv=None):
     for mode in args.modes:
         runs = []
         for n in args.n:
-            r = run(n, args.t_end, mode, args.dtype, args.re)
+            r = run(n, args.t_end, mode, args.dtype, args.re, args.chunk, args.dim)
             runs.append(r)
             print(f"{mode:8s} n {n:4d} ({r['particles']} particles, {r['steps']} steps, "
                   f"{r['wall_s']:.1f} s, {r['us_per_step']:.1f} us/step) flags {r['flags']}; "

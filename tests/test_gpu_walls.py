@@ -11,7 +11,9 @@ from tests import parity_utils as pu
 
 pytestmark = pytest.mark.gpu
 
-CAVITY = cases.lid_driven_cavity(24, name="cavity24")
+CAVITIES = {"cavity24": cases.lid_driven_cavity(24, name="cavity24"),
+            "cavity3d_8": cases.lid_driven_cavity(8, dim=3, name="cavity3d_8")}
+CAVITY = CAVITIES["cavity24"]
 
 
 def _sim(case, dtype, warm=0, **kw):
@@ -25,10 +27,12 @@ def _sim(case, dtype, warm=0, **kw):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_wall_state_parity(dtype):
-    """After 30 steps of the cavity, sph_wall_state from the current fluid
-    density and velocity against the oracle's wall state: every wall
-    particle's density (/ rho0) and mirror velocity (/ U)."""
+@pytest.mark.parametrize("cname", list(CAVITIES))
+def test_wall_state_parity(cname, dtype):
+    """After 30 steps of the cavity (2-D and 3-D), sph_wall_state from the
+    current fluid density and velocity against the oracle's wall state: every
+    wall particle's density (/ rho0) and mirror velocity (/ U)."""
+    CAVITY = CAVITIES[cname]
     sim = _sim(CAVITY, dtype, warm=30)
     sim.wall_state()
     st, mass, h = pu.gpu_inputs(sim, CAVITY)
@@ -45,10 +49,12 @@ def test_wall_state_parity(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_sweeps_with_walls(dtype):
+@pytest.mark.parametrize("cname", list(CAVITIES))
+def test_sweeps_with_walls(cname, dtype):
     """Density of every particle; correction and accelerations of the fluid
     (walls get none: zero on the GPU) on the summation-error scale."""
     import torch
+    CAVITY = CAVITIES[cname]
     sim = _sim(CAVITY, dtype, warm=30)
     st, mass, h = pu.gpu_inputs(sim, CAVITY)
     nb = oracle.neighbors(st["pos"], h, CAVITY.box)
@@ -56,7 +62,7 @@ def test_sweeps_with_walls(dtype):
     order = st["order"]
     tol = pu.TOL[dtype]
     rho_gpu = sim.density(out=torch.empty_like(sim.rho)).cpu().double().numpy()[order]
-    rho = oracle.density(st["pos"], mass, h, CAVITY.box, nb, oracle.lattice_kappa(2))
+    rho = oracle.density(st["pos"], mass, h, CAVITY.box, nb, oracle.lattice_kappa(CAVITY.dim))
     assert np.abs(rho_gpu - rho).max() / CAVITY.rho0 < tol
     acc_gpu = sim.forces(out=torch.empty_like(sim.acc)).cpu().double().numpy()[:, order]
     acc, scale = oracle.forces(st["pos"], st["vel"], mass, st["rho"], h, CAVITY.box, nb,
@@ -78,8 +84,9 @@ def test_sweeps_with_walls(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("mode", ["limited", "scaled"])
-def test_step_parity_walls(dtype, mode):
+@pytest.mark.parametrize("mode,cname", [("limited", "cavity24"), ("scaled", "cavity24"),
+                                        ("limited", "cavity3d_8")])
+def test_step_parity_walls(cname, mode, dtype):
     """One kick-drift-kick step of the cavity from an identical state (after 30
     steps, the lid's boundary layer developing): every particle's position,
     velocity (walls: the mirror velocity) and density, and the fluid's
@@ -87,6 +94,7 @@ def test_step_parity_walls(dtype, mode):
     band of Eq. 15 and are excluded with two neighbour hops, as for the
     periodic cases."""
     import torch
+    CAVITY = CAVITIES[cname]
     sim = _sim(CAVITY, dtype, warm=30, tv_mode=mode)
     st, mass, h = pu.gpu_inputs(sim, CAVITY)
     rc = pu.case_with(CAVITY, mass, h)
@@ -126,11 +134,12 @@ def test_step_parity_walls(dtype, mode):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_fused_run_equals_single_steps_walls(dtype):
+@pytest.mark.parametrize("cname", list(CAVITIES))
+def test_fused_run_equals_single_steps_walls(cname, dtype):
     """sph_kdk_run and repeated sph_kdk_step agree bit for bit with walls."""
     import torch
-    a = _sim(CAVITY, dtype)
-    b = _sim(CAVITY, dtype)
+    a = _sim(CAVITIES[cname], dtype)
+    b = _sim(CAVITIES[cname], dtype)
     rows = []
     for _ in range(6):
         a.step(1)
@@ -152,16 +161,18 @@ def test_walls_refuse_tapes():
     assert e.value.status == -6
 
 
-def test_cavity_fp64_trajectory():
-    """100 FP64 steps of a 30x30 cavity (Re = 1000), GPU against the oracle
-    from the same initial state: kinetic energy and the largest speed every
-    step, positions and velocities of every particle at the end."""
-    case = cases.lid_driven_cavity(30, name="cavity30")
+@pytest.mark.parametrize("dim,n,steps", [(2, 30, 100), (3, 10, 40)])
+def test_cavity_fp64_trajectory(dim, n, steps):
+    """FP64 cavity runs (30x30 at Re = 1000 for 100 steps; 10^3 at Re = 100
+    for 40 steps), GPU against the oracle from the same initial state: kinetic
+    energy and the largest speed every step, positions and velocities of
+    every particle at the end."""
+    case = cases.lid_driven_cavity(n, dim=dim)
     sim = _sim(case, "f64")
     st, mass, h = pu.gpu_inputs(sim, case)
     ref = oracle.State(case, pos=st["pos"], vel=st["vel"], rho=st["rho"], acc=st["acc"])
-    rows = sim.run(100, diag=True).cpu().numpy()
-    d = ref.run(100)
+    rows = sim.run(steps, diag=True).cpu().numpy()
+    d = ref.run(steps)
     assert np.max(np.abs(rows[:, 0] / d[:, 0] - 1.0)) < 1e-9
     assert np.max(np.abs(rows[:, 4] / d[:, 4] - 1.0)) < 1e-9
     out = sim.export()

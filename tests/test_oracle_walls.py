@@ -24,6 +24,7 @@ def _brute_pairs(pos, h, box):
 
 
 @pytest.mark.parametrize("make", [lambda: cases.lid_driven_cavity(12),
+                                  lambda: cases.lid_driven_cavity(6, dim=3),
                                   lambda: cases.couette_2d(16)])
 def test_fluid_never_reaches_across_the_seam(make):
     case = make()
@@ -38,21 +39,23 @@ def test_fluid_never_reaches_across_the_seam(make):
         assert np.all(ydirect[fluid_pairs])
 
 
-def _cavity_with(rho_f, vel_f, u_lid=0.7):
-    case = cases.lid_driven_cavity(12, u_lid=u_lid)
+def _cavity_with(rho_f, vel_f, u_lid=0.7, dim=2):
+    case = cases.lid_driven_cavity(12 if dim == 2 else 6, u_lid=u_lid, dim=dim)
     nf = case.n_fluid
     rho = np.full(case.n, case.rho0)
     rho[:nf] = rho_f
     vel = case.vel.copy()
-    vel[:, :nf] = np.asarray(vel_f).reshape(2, -1)
+    vel[:, :nf] = np.asarray(vel_f).reshape(dim, -1)
     return case, rho, vel
 
 
-def test_wall_state_reproduces_constant_fields():
+@pytest.mark.parametrize("dim", [2, 3])
+def test_wall_state_reproduces_constant_fields(dim):
     """Uniform fluid pressure and velocity: every wall particle with fluid
     neighbours gets the fluid's density and 2 u_w - u; the others get rho0 and
     u_w (their own prescribed velocity)."""
-    case, rho, vel = _cavity_with(1.013, [[0.3], [-0.2]])
+    u = [[0.3], [-0.2], [0.1]][:dim]
+    case, rho, vel = _cavity_with(1.013, u, dim=dim)
     nb = oracle.neighbors(case.pos, case.h, case.box)
     rho2, vel2 = oracle.wall_bc(case.pos, vel, rho, case.h, case.box, nb, case.n_wall,
                                 case.wall_vel, case.rho0, case.c0)
@@ -63,14 +66,14 @@ def test_wall_state_reproduces_constant_fields():
     uw = case.wall_vel
     assert np.allclose(rho2[nf:][has_fluid], 1.013, rtol=0, atol=1e-14)
     assert np.allclose(vel2[:, nf:][:, has_fluid],
-                       2 * uw[:, has_fluid] - np.array([[0.3], [-0.2]]), rtol=0, atol=1e-14)
+                       2 * uw[:, has_fluid] - np.array(u), rtol=0, atol=1e-14)
     assert np.all(rho2[nf:][~has_fluid] == case.rho0)
     assert np.array_equal(vel2[:, nf:][:, ~has_fluid], uw[:, ~has_fluid])
     # fluid entries untouched
     assert np.array_equal(rho2[:nf], rho[:nf]) and np.array_equal(vel2[:, :nf], vel[:, :nf])
     # the lid moves (top wall, corner blocks included); the rest is at rest
     top = case.pos[1][nf:] > case.extra["origin"] + 1.0
-    assert np.all(uw[0, top] == 0.7) and np.all(uw[0, ~top] == 0.0) and np.all(uw[1] == 0.0)
+    assert np.all(uw[0, top] == 0.7) and np.all(uw[0, ~top] == 0.0) and np.all(uw[1:] == 0.0)
 
 
 def test_wall_state_averages_with_kernel_weights():
@@ -99,11 +102,12 @@ def test_wall_state_averages_with_kernel_weights():
         assert y[js].min() <= ybar <= y[js].max()
 
 
-def test_resting_fluid_between_walls_feels_no_force():
+@pytest.mark.parametrize("dim", [2, 3])
+def test_resting_fluid_between_walls_feels_no_force(dim):
     """Fluid at rest with uniform density 1.01 rho0 and walls at rest: the
     walls take the fluid's pressure, every fluid particle's support holds a
     complete lattice, and the pressure forces cancel to rounding."""
-    case = cases.lid_driven_cavity(12)
+    case = cases.lid_driven_cavity(12 if dim == 2 else 6, dim=dim)
     case.wall_vel = np.zeros_like(case.wall_vel)
     nf = case.n_fluid
     rho = np.full(case.n, 1.01)
