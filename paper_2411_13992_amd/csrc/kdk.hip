@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void drift_kernel(Grid g, Coeffs<T> k, PArr
   int lin = 0;
   if (valid) {
     // wall particles keep their position and velocity
-    const bool wall = is_wall(k, p.id[i]);
+    const bool wall = wall_at(k, n, p.id, i);
     T o[3], vh[3], dri[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kBlock) void kick_kernel(Coeffs<T> k, int n, T* __r
   // first does the work), so per-block partials fold in the same order
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   double ke = 0.0, mom[3] = {0.0, 0.0, 0.0}, vmax = 0.0;
-  if (i < n && threadIdx.x % G == 0 && !is_wall(k, id[i])) {
+  if (i < n && threadIdx.x % G == 0 && !wall_at(k, n, id, i)) {
     const double m = mass ? (double)mass[i] : (double)k.mass;
     double v2 = 0.0;
     bool bad = false;

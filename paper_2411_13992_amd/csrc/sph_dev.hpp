@@ -46,6 +46,14 @@ struct Coeffs {
 template <typename T>
 __device__ __forceinline__ bool is_wall(const Coeffs<T>& k, int id) { return id >= k.nfluid; }
 
+// Whether particle i (of n) is a wall particle; reads its id only when the
+// run has walls (a uniform branch), so wall-free sweeps load no ids.
+template <typename T>
+__device__ __forceinline__ bool wall_at(const Coeffs<T>& k, int n, const int* __restrict__ id,
+                                        int i) {
+  return k.nfluid < n && id[i] >= k.nfluid;
+}
+
 // ---------------------------------------------------------------- math
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double fsqrt(double x) { return __builtin_sqrt(x); }

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   const bool valid = i < n;
-  const bool fluid = valid && !is_wall(k, id[i]);   // walls get no correction
+  const bool fluid = valid && !wall_at(k, n, id, i);   // walls get no correction
   Acc<T, UseKahan<T>::value> acc[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) acc[d].init(T(0));
@@ -190,7 +190,7 @@ __device__ __forceinline__ void forces_impl(
   const bool valid = i < n;
   const bool lead = valid && sub == 0;
   // wall particles: no acceleration, correction, kick or drift
-  const bool wall = valid && is_wall(k, id[i]);
+  const bool wall = valid && wall_at(k, n, id, i);
   T oi[3] = {T(0), T(0), T(0)}, vi[3] = {T(0), T(0), T(0)};
   T ai[3] = {T(0), T(0), T(0)}, gi[3] = {T(0), T(0), T(0)};
   int celli = 0;
