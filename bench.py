@@ -210,8 +210,8 @@ def main():
                          "64 MiB device copy of known size (for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path; use --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     import cases
