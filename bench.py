@@ -242,15 +242,13 @@ def main():
     sim64 = Simulation.from_case(case, dtype="f64")
     t64, pairs64 = time_steps(sim64, max(steps // 2, 1), max(warmup // 2, 1))
     del sim64
-    adjoint = None      # walls: the adjoint entry points refuse walled runs
-    if not case.n_wall:
-        simadj = Simulation.from_case(case, dtype="f32")
-        t_fwd, t_bwd = time_adjoint(simadj, 40, 20)
-        del simadj
-        adjoint = {"forward_ms_per_step": t_fwd * 1e3, "reverse_ms_per_step": t_bwd * 1e3,
-                   "adjoint_over_forward": t_bwd / t_fwd,
-                   "rollout": "40 FP32 steps, checkpoints every 20, reverse includes "
-                              "recomputation with tapes"}
+    simadj = Simulation.from_case(case, dtype="f32")
+    t_fwd, t_bwd = time_adjoint(simadj, 40, 20)
+    del simadj
+    adjoint = {"forward_ms_per_step": t_fwd * 1e3, "reverse_ms_per_step": t_bwd * 1e3,
+               "adjoint_over_forward": t_bwd / t_fwd,
+               "rollout": "40 FP32 steps, checkpoints every 20, reverse includes "
+                          "recomputation with tapes"}
     out = {
         "metric": METRIC,
         "value": pairs / t32,

@@ -282,7 +282,8 @@ def _walled_box(nx: int, ny: int, layers: int, dx: float, wall_x: bool, nz: int 
 
 
 def lid_driven_cavity(n: int, re: float | None = None, u_lid: float = 1.0, layers: int = 3,
-                      dim: int = 2, steps: int = 1000, name: str | None = None) -> Case:
+                      dim: int = 2, jitter: float = 0.0, seed: int = 1, steps: int = 1000,
+                      name: str | None = None) -> Case:
     """Lid-driven cavity of side 1: 2-D (Sec. 4.2, Re = 1000 by default) or
     3-D (the cube of the three-dimensional cavity section, Re = 100 by
     default), Re = U L / nu.
@@ -295,7 +296,8 @@ def lid_driven_cavity(n: int, re: float | None = None, u_lid: float = 1.0, layer
     the box [0, 1 + 2 layers dp)^D is the periodic box of the cell grid; with
     layers*dp >= 2h (layers >= 3 at h = 1.3 dp) no fluid particle has a
     neighbour across its seams.  Ids: the fluid first (x fastest), then the
-    walls (x fastest).
+    walls (x fastest).  ``jitter`` (in units of dp, at most 0.25) moves the
+    fluid particles by seeded uniform noise; the walls stay on the lattice.
     """
     if layers * 1.0 < 2 * H_OVER_DP:
         raise ValueError("layers must cover the kernel support 2h")
@@ -304,6 +306,11 @@ def lid_driven_cavity(n: int, re: float | None = None, u_lid: float = 1.0, layer
     re = (1000.0 if dim == 2 else 100.0) if re is None else re
     dx = 1.0 / n
     fluid, wall, top = _walled_box(n, n, layers, dx, True, nz=n if dim == 3 else 0)
+    if jitter > 0.0:
+        if jitter > 0.25:
+            raise ValueError("jitter above 0.25 dp could bring fluid onto the walls")
+        rng = np.random.default_rng(seed)
+        fluid = fluid + rng.uniform(-1.0, 1.0, size=(fluid.shape[1], dim)).T * jitter * dx
     pos = np.concatenate([fluid, wall], axis=1)
     nw = wall.shape[1]
     wall_vel = np.zeros((dim, nw))

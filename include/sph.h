@@ -206,8 +206,13 @@ int32_t sph_forces(const sph_params *p, const sph_particles *parts,
  * and reads those of fluid particles.  sph_kdk_step / sph_kdk_run call it
  * after each density summation; a caller evaluating sph_forces by hand calls
  * it between sph_density and sph_forces.  The box stays periodic: walls at
- * least 2 h_max thick keep the fluid from reaching across its seam.  With
- * n_wall > 0, tapes and the adjoint entry points return SPH_E_UNSUPPORTED. */
+ * least 2 h_max thick keep the fluid from reaching across its seam.  Walled
+ * runs are differentiable: their tapes also record the particle ids, and the
+ * adjoint entry points reverse the wall state too (the walls' density and
+ * velocity cotangents go to their fluid neighbours, and to both sides'
+ * positions); the walls' acceleration is not an output (its cotangent is
+ * ignored) and their velocity before a step does not reach its outputs (its
+ * cotangent comes back zero). */
 int32_t sph_wall_state(const sph_params *p, sph_particles *parts, const int32_t *cell_start,
                        void *stream);
 

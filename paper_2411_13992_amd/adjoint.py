@@ -121,10 +121,13 @@ def rollout(sim: Simulation, v0: torch.Tensor, xi: torch.Tensor, nsteps: int,
 
 
 def kinetic_energy(sim: Simulation, vel_by_id: torch.Tensor) -> torch.Tensor:
-    """1/2 sum m |v|^2 in FP64 (a torch loss on the rollout output)."""
+    """1/2 sum m |v|^2 over the fluid particles in FP64 (a torch loss on the
+    rollout output; wall particles, the last n_wall ids, carry their no-slip
+    mirror velocity and are left out)."""
     if sim.var:
         m = torch.empty(sim.n, dtype=torch.float64, device=sim.device)
         m[sim.id.long()] = sim.mass.double()
     else:
         m = torch.full((sim.n,), float(sim.cfg.mass), dtype=torch.float64, device=sim.device)
-    return 0.5 * (m * (vel_by_id.double() ** 2).sum(0)).sum()
+    nf = sim.n - sim.n_wall
+    return 0.5 * (m[:nf] * (vel_by_id[:, :nf].double() ** 2).sum(0)).sum()

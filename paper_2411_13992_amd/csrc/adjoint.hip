@@ -175,12 +175,14 @@ __global__ __launch_bounds__(kBlock) void force_vjp_kernel(
 
 // ------------------------------------------------------------------ density^T
 // rbar_i += sum_j (rhobar_i m_j + rhobar_j m_i) F_ij r_ij / kappa, then
-// vbar_i += vcoef * rbar_i (the drift r' = r + dt v' of the same step).
+// vbar_i += vcoef * rbar_i (the drift r' = r + dt v' of the same step; wall
+// particles, told by id when id is given, do not drift).
 template <int D, typename T, bool VAR, int G>
 __global__ __launch_bounds__(kBlock) void density_vjp_kernel(
     Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
     const T* __restrict__ off, const T* __restrict__ mass, const T* __restrict__ hh,
-    const T* __restrict__ rho_bar, T* __restrict__ r_bar, T* __restrict__ v_bar, T vcoef) {
+    const int* __restrict__ id, const T* __restrict__ rho_bar, T* __restrict__ r_bar,
+    T* __restrict__ v_bar, T vcoef) {
   const int n = g.n;
   const Cols<T, D> offc(off, n);
   const Cols<T, 1> rbarc(rho_bar, n), hc(hh, n), mc(mass, n);
@@ -219,13 +221,202 @@ __global__ __launch_bounds__(kBlock) void density_vjp_kernel(
 #pragma unroll
   for (int d = 0; d < D; ++d) sums[d] = group_sum<G>(acc[d]);
   if (valid && sub == 0) {
+    const bool drifts = v_bar && !(id && is_wall(k, id[i]));
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const T rb = r_bar[d * n + i] + sums[d] * k.inv_kappa;
       r_bar[d * n + i] = rb;
-      if (v_bar) v_bar[d * n + i] += vcoef * rb;
+      if (drifts) v_bar[d * n + i] += vcoef * rb;
     }
   }
+}
+
+// ------------------------------------------------------------------ wall state^T
+// The wall state (sph_wall_state) for wall a over its fluid neighbours f:
+//   S_a = sum W_af,  rho_a = rho0 + sum (rho_f - rho0) W_af / S_a,
+//   v_a = 2 u_a - Vbar_a,  Vbar_a = sum v_f W_af / S_a.
+// Pass 1 stores S_a and Vbar_a per wall particle (sorted order) and marks
+// the cells that hold walls.  Pass 2 is a gather over the fluid-wall pairs
+// (particles whose 3^D cells hold no wall skip it): with
+//   c_af = (rhobar_a (rho_f - rho_a) - vbar_a . (v_f - Vbar_a)) / S_a,
+// a fluid particle f collects rhobar_f += rhobar_a W_af / S_a,
+// vbar_f -= vbar_a W_af / S_a and rbar_f += c_af F_af (r_f - r_a); a wall
+// particle a collects rbar_a += c_af F_af (r_a - r_f).  Pass 3 clears the
+// walls' rhobar and vbar (consumed; the walls' summation densities and
+// earlier velocities feed nothing).
+template <int D, typename T, bool VAR, int G>
+__global__ __launch_bounds__(kBlock) void wall_sums_kernel(
+    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+    const T* __restrict__ off, const T* __restrict__ hh, const int* __restrict__ id,
+    const T* __restrict__ vel, T* __restrict__ wsum, T* __restrict__ wavg,
+    int* __restrict__ wall_cells) {
+  const int n = g.n;
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
+  const int sub = threadIdx.x % G;
+  const bool wall = i < n && is_wall(k, id[i]);
+  if (!__any(wall)) return;     // whole wavefront: no lane needs a group sum
+  const Cols<T, D> offc(off, n), velc(vel, n);
+  const Cols<T, 1> hc(hh, n);
+  VjpAcc<T> sw, sv[3];
+  sw.init(T(0));
+#pragma unroll
+  for (int d = 0; d < 3; ++d) sv[d].init(T(0));
+  if (wall) {
+    T oi[3];
+#pragma unroll
+    for (int d = 0; d < D; ++d) oi[d] = off[d * n + i];
+    const T hi = VAR ? hh[i] : k.h;
+    for_each_candidate<D, G>(g, k, cell[i], cs, sub, [&](int j, const T* sh) {
+      T r2 = T(0);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const T rv = (oi[d] - offc(d, j)) - sh[d];
+        r2 = tfma(rv, rv, r2);
+      }
+      const PairH<D, T, VAR> ph = pair_h<D, T, VAR>(k, hi, VAR ? hc(0, j) : T(0));
+      if (!(r2 < ph.sup2) || is_wall(k, id[j])) return;
+      const T w = wendland_alpha<D>(ph.inv_h) * wendland_shape(fsqrt(r2) * ph.inv_h);
+      sw.add(w);
+#pragma unroll
+      for (int d = 0; d < D; ++d) sv[d].add(velc(d, j) * w);
+    });
+  }
+  const T S = group_sum<G>(sw);
+  T V[3];
+#pragma unroll
+  for (int d = 0; d < D; ++d) V[d] = group_sum<G>(sv[d]);
+  if (wall && sub == 0) {
+    wall_cells[cell[i]] = 1;      // every writer stores the same value
+    wsum[i] = S;
+#pragma unroll
+    for (int d = 0; d < D; ++d) wavg[d * n + i] = S > T(0) ? V[d] / S : T(0);
+  }
+}
+
+template <int D, typename T, bool VAR, int G>
+__global__ __launch_bounds__(kBlock) void wall_vjp_kernel(
+    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+    const T* __restrict__ off, const T* __restrict__ hh, const int* __restrict__ id,
+    const T* __restrict__ vel, const T* __restrict__ rho, const T* __restrict__ wsum,
+    const T* __restrict__ wavg, const int* __restrict__ wall_cells, T* __restrict__ r_bar,
+    T* __restrict__ v_bar, T* __restrict__ rho_bar) {
+  const int n = g.n;
+  const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
+  const int sub = threadIdx.x % G;
+  const bool valid = i < n;
+  const bool wall_i = valid && is_wall(k, id[i]);
+  // a fluid particle takes part only if a cell around it holds a wall
+  bool near = wall_i;
+  if (valid && !wall_i) {
+    int c[3];
+    decode_cell<D>(g, cell[i], c);
+    constexpr int zlo = (D == 3) ? -1 : 0;
+    constexpr int zhi = (D == 3) ? 1 : 0;
+#pragma unroll
+    for (int dz = zlo; dz <= zhi; ++dz) {
+      const int z = (D == 3) ? wrap_index(c[2] + dz, g.nc[2]) : 0;
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int row = g.nc[0] * (wrap_index(c[1] + dy, g.nc[1]) + g.nc[1] * z);
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) near |= wall_cells[row + wrap_index(c[0] + dx, g.nc[0])] != 0;
+      }
+    }
+  }
+  if (!__any(near)) return;       // whole wavefront: no lane needs a group sum
+  const Cols<T, D> offc(off, n), velc(vel, n), vbarc(v_bar, n), wavgc(wavg, n);
+  const Cols<T, 1> hc(hh, n), rhoc(rho, n), rbarc(rho_bar, n), wsumc(wsum, n);
+  VjpAcc<T> ra[3], va[3], pa;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    ra[d].init(T(0));
+    va[d].init(T(0));
+  }
+  pa.init(T(0));
+  if (valid && near) {
+    T oi[3], vi[3], vbi[3], avi[3];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      oi[d] = off[d * n + i];
+      vi[d] = vel[d * n + i];
+      vbi[d] = wall_i ? v_bar[d * n + i] : T(0);
+      avi[d] = wall_i ? wavg[d * n + i] : T(0);
+    }
+    const T rhoi = rho[i];
+    const T pbi = wall_i ? rho_bar[i] : T(0);
+    const T si = wall_i ? wsum[i] : T(0);
+    const T hi = VAR ? hh[i] : k.h;
+    for_each_candidate<D, G>(g, k, cell[i], cs, sub, [&](int j, const T* sh) {
+      T r[3];
+      T r2 = T(0);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        r[d] = (oi[d] - offc(d, j)) - sh[d];
+        r2 = tfma(r[d], r[d], r2);
+      }
+      const PairH<D, T, VAR> ph = pair_h<D, T, VAR>(k, hi, VAR ? hc(0, j) : T(0));
+      if (!(r2 < ph.sup2) || is_wall(k, id[j]) == wall_i) return;   // fluid-wall pairs
+      const PairGeo<T> pg = pair_geo(r2);
+      const T t = kernel_t(pg.r, ph.inv_h);
+      const T F = ph.fc * (t * t * t);
+      if (!wall_i) {
+        // i = f (fluid), j = a (wall)
+        const T sa = wsumc(0, j);
+        if (!(sa > T(0))) return;
+        const T inv = T(1) / sa;
+        const T w = wendland_alpha<D>(ph.inv_h) * wendland_shape(pg.r * ph.inv_h);
+        const T pbj = rbarc(0, j);
+        T c = pbj * (rhoi - rhoc(0, j));
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const T vbj = vbarc(d, j);
+          c -= vbj * (vi[d] - wavgc(d, j));
+          va[d].add(-vbj * w * inv);
+        }
+        pa.add(pbj * w * inv);
+        c *= inv;
+#pragma unroll
+        for (int d = 0; d < D; ++d) ra[d].add(c * F * r[d]);
+      } else {
+        // i = a (wall), j = f (fluid)
+        if (!(si > T(0))) return;
+        T c = pbi * (rhoc(0, j) - rhoi);
+#pragma unroll
+        for (int d = 0; d < D; ++d) c -= vbi[d] * (velc(d, j) - avi[d]);
+        c /= si;
+#pragma unroll
+        for (int d = 0; d < D; ++d) ra[d].add(c * F * r[d]);
+      }
+    });
+  }
+  T rs[3], vs[3];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    rs[d] = group_sum<G>(ra[d]);
+    vs[d] = group_sum<G>(va[d]);
+  }
+  const T ps = group_sum<G>(pa);
+  if (valid && near && sub == 0) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) r_bar[d * n + i] += rs[d];
+    if (!wall_i) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) v_bar[d * n + i] += vs[d];
+      rho_bar[i] += ps;
+    }
+  }
+}
+
+// x[c][i] = 0 (c < ncomp) and, when given, y[i] = 0 for the wall particles i
+template <typename T>
+__global__ __launch_bounds__(kBlock) void zero_walls_kernel(Coeffs<T> k, int n, int ncomp,
+                                                            const int* __restrict__ id,
+                                                            T* __restrict__ x,
+                                                            T* __restrict__ y) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n || !is_wall(k, id[i])) return;
+  for (int c = 0; c < ncomp; ++c) x[(size_t)c * n + i] = T(0);
+  if (y) y[i] = T(0);
 }
 
 // ------------------------------------------------------------------ correction^T, pass 1
@@ -369,21 +560,30 @@ __global__ __launch_bounds__(kBlock) void unpermute_kernel(int n, int ncomp, con
   for (int d = 0; d < ncomp; ++d) dst[d * n + p] = src[d * n + q];
 }
 
+// Wall particles (told by id when id is given) are not kicked: their
+// velocity cotangent is that of the wall state, not of a kick, and their
+// acceleration is not an output (its cotangent is cleared).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void adj_kick_kernel(long dn, T half_dt, const T* __restrict__ v_bar,
+__global__ __launch_bounds__(kBlock) void adj_kick_kernel(long dn, int n, T half_dt, int nfluid,
+                                                          const int* __restrict__ id,
+                                                          const T* __restrict__ v_bar,
                                                           T* __restrict__ a_bar) {
   const long i = (long)blockIdx.x * kBlock + threadIdx.x;
-  if (i < dn) a_bar[i] += half_dt * v_bar[i];
+  if (i >= dn) return;
+  if (id && id[i % n] >= nfluid) a_bar[i] = T(0);
+  else a_bar[i] += half_dt * v_bar[i];
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void adj_finish_kernel(long dn, T half_dt,
+__global__ __launch_bounds__(kBlock) void adj_finish_kernel(long dn, int n, T half_dt, int nfluid,
+                                                            const int* __restrict__ id,
                                                             const T* __restrict__ vh_bar,
                                                             T* __restrict__ v_bar,
                                                             T* __restrict__ a_bar) {
   const long i = (long)blockIdx.x * kBlock + threadIdx.x;
   if (i < dn) {
-    const T v = vh_bar[i];
+    const bool wall = id && id[i % n] >= nfluid;
+    const T v = wall ? T(0) : vh_bar[i];
     v_bar[i] = v;
     a_bar[i] = half_dt * v;
   }
@@ -419,8 +619,8 @@ template <typename T>
 void launch_density_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                         const int* cs, const T* rho_bar, T* r_bar, T* v_bar, T vcoef) {
   if (g.n == 0) return;
-  SPH_SWEEP(density_vjp_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.mass, p.h, rho_bar, r_bar,
-                                         v_bar, vcoef));
+  SPH_SWEEP(density_vjp_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.mass, p.h, p.id, rho_bar,
+                                         r_bar, v_bar, vcoef));
 }
 
 template <typename T>
@@ -454,20 +654,42 @@ void launch_unpermute(const Launch& l, int n, const int* perm, const T* src, T* 
 }
 
 template <typename T>
-void launch_adj_kick(const Launch& l, const Coeffs<T>& k, int n, const T* v_bar, T* a_bar) {
+void launch_adj_kick(const Launch& l, const Coeffs<T>& k, int n, const int* id, const T* v_bar,
+                     T* a_bar) {
   const long dn = (long)l.dim * n;
   if (dn == 0) return;
   hipLaunchKernelGGL((adj_kick_kernel<T>), dim3(blocks_for(dn)), dim3(kBlock), 0, l.stream, dn,
-                     k.half_dt, v_bar, a_bar);
+                     n, k.half_dt, k.nfluid, id, v_bar, a_bar);
 }
 
 template <typename T>
-void launch_adj_finish(const Launch& l, const Coeffs<T>& k, int n, const T* vhalf_bar, T* v_bar,
-                       T* a_bar) {
+void launch_adj_finish(const Launch& l, const Coeffs<T>& k, int n, const int* id,
+                       const T* vhalf_bar, T* v_bar, T* a_bar) {
   const long dn = (long)l.dim * n;
   if (dn == 0) return;
   hipLaunchKernelGGL((adj_finish_kernel<T>), dim3(blocks_for(dn)), dim3(kBlock), 0, l.stream, dn,
-                     k.half_dt, vhalf_bar, v_bar, a_bar);
+                     n, k.half_dt, k.nfluid, id, vhalf_bar, v_bar, a_bar);
+}
+
+template <typename T>
+void launch_wall_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
+                     const int* cs, const T* vel, T* wsum, T* wavg, int* wall_cells, T* r_bar,
+                     T* v_bar, T* rho_bar) {
+  if (g.n == 0) return;
+  launch_fill(l.stream, wall_cells, g.ncells, 0);
+  SPH_SWEEP(wall_sums_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.h, p.id, vel, wsum, wavg,
+                                       wall_cells));
+  SPH_SWEEP(wall_vjp_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.h, p.id, vel, p.rho, wsum, wavg,
+                                      wall_cells, r_bar, v_bar, rho_bar));
+  launch_zero_walls<T>(l, k, g.n, p.id, l.dim, v_bar, rho_bar);
+}
+
+template <typename T>
+void launch_zero_walls(const Launch& l, const Coeffs<T>& k, int n, const int* id, int ncomp,
+                       T* x, T* y) {
+  if (n == 0) return;
+  hipLaunchKernelGGL((zero_walls_kernel<T>), dim3(blocks_for(n)), dim3(kBlock), 0, l.stream, k,
+                     n, ncomp, id, x, y);
 }
 
 void launch_xi_final(hipStream_t s, int n, const double* partials, double* xi_bar) {
@@ -487,8 +709,15 @@ void launch_xi_final(hipStream_t s, int n, const double* partials, double* xi_ba
                                  const PArrays<T>&, const int*, const T*, const T*,          \
                                  const T*, const T*, T*, T*);                                \
   template void launch_unpermute<T>(const Launch&, int, const int*, const T*, T*, int);      \
-  template void launch_adj_kick<T>(const Launch&, const Coeffs<T>&, int, const T*, T*);      \
-  template void launch_adj_finish<T>(const Launch&, const Coeffs<T>&, int, const T*, T*, T*);
+  template void launch_adj_kick<T>(const Launch&, const Coeffs<T>&, int, const int*,          \
+                                   const T*, T*);                                            \
+  template void launch_adj_finish<T>(const Launch&, const Coeffs<T>&, int, const int*,        \
+                                     const T*, T*, T*);                                      \
+  template void launch_wall_vjp<T>(const Launch&, const Grid&, const Coeffs<T>&,             \
+                                   const PArrays<T>&, const int*, const T*, T*, T*, int*,    \
+                                   T*, T*, T*);                                              \
+  template void launch_zero_walls<T>(const Launch&, const Coeffs<T>&, int, const int*, int,  \
+                                     T*, T*);
 SPH_INST(float)
 SPH_INST(double)
 #undef SPH_INST

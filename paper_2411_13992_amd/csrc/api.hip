@@ -14,7 +14,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Sizes {
-  int dim, n, ncells, nblk;
+  int dim, n, ncells, nblk, nwall;
   size_t tsz;     // bytes per float element
   bool var;
 };
@@ -25,6 +25,7 @@ struct WsLayout {
   size_t stg_cell, stg_id, stg_off, stg_vel, stg_acc, stg_rho, stg_mass, stg_h;
   size_t dr, partials, partials2;
   size_t adj_r, adj_v, adj_rho, adj_g, adj_r2;
+  size_t wall_cells;   // cells holding a wall particle (reverse of the wall state)
   size_t total;
 };
 
@@ -35,6 +36,7 @@ struct WsLayout {
 struct TapeLayout {
   size_t pre_cell, pre_off, pre_rho, pre_mass, pre_h, pre_cs, g, beta, perm;
   size_t post_cell, post_off, post_vhalf, post_rho, post_mass, post_h, post_cs;
+  size_t pre_id, post_id;   // particle ids (walled runs only: walls are told by id)
   size_t total;
 };
 
@@ -82,6 +84,7 @@ Sizes sizes_of(const sph_params* p, bool var) {
   s.n = (int)p->n;
   s.ncells = p->ncell[0] * p->ncell[1] * (p->dim == 3 ? p->ncell[2] : 1);
   s.nblk = blocks_for((long)s.n * lanes_of(p));
+  s.nwall = (int)p->n_wall;
   s.tsz = p->dtype == SPH_F64 ? 8 : 4;
   s.var = var;
   return s;
@@ -116,6 +119,7 @@ WsLayout ws_layout(const Sizes& s) {
   w.adj_rho = c.take(t * n);
   w.adj_g = c.take(t * dn);
   w.adj_r2 = c.take(t * dn);
+  w.wall_cells = c.take(s.nwall > 0 ? sizeof(int) * (size_t)s.ncells : 0);
   w.total = c.o;
   return w;
 }
@@ -141,6 +145,8 @@ TapeLayout tape_layout(const Sizes& s) {
   tl.post_mass = c.take(s.var ? t * n : 0);
   tl.post_h = c.take(s.var ? t * n : 0);
   tl.post_cs = c.take(cs);
+  tl.pre_id = c.take(s.nwall > 0 ? sizeof(int) * n : 0);
+  tl.post_id = c.take(s.nwall > 0 ? sizeof(int) * n : 0);
   tl.total = c.o;
   return tl;
 }
@@ -362,9 +368,10 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
   auto tape_of = [&](int64_t s) { return tapes + (size_t)s * tl.total; };
   // the sorted state (cell, offsets, density, mass, h, cell_start) into a tape
   auto record_state = [&](char* tp, size_t o_cell, size_t o_off, size_t o_rho, size_t o_mass,
-                          size_t o_h, size_t o_cs) {
+                          size_t o_h, size_t o_cs, size_t o_id) {
     hipError_t e = hipSuccess;
     e = e ? e : copy_d2d(tp + o_cell, a.cell, sizeof(int) * n, stream);
+    if (p->n_wall > 0) e = e ? e : copy_d2d(tp + o_id, a.id, sizeof(int) * n, stream);
     e = e ? e : copy_d2d(tp + o_off, a.off, t * dn, stream);
     e = e ? e : copy_d2d(tp + o_rho, a.rho, t * n, stream);
     if (var) {
@@ -376,11 +383,11 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
   };
   auto record_pre = [&](char* tp) {
     return record_state(tp, tl.pre_cell, tl.pre_off, tl.pre_rho, tl.pre_mass, tl.pre_h,
-                        tl.pre_cs);
+                        tl.pre_cs, tl.pre_id);
   };
   auto record_post = [&](char* tp) {
     hipError_t e = record_state(tp, tl.post_cell, tl.post_off, tl.post_rho, tl.post_mass,
-                                tl.post_h, tl.post_cs);
+                                tl.post_h, tl.post_cs, tl.post_id);
     e = e ? e : copy_d2d(tp + tl.perm, perm, sizeof(int) * n, stream);
     e = e ? e : copy_d2d(tp + tl.post_vhalf, a.vel, t * dn, stream);
     return e;
@@ -422,8 +429,8 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
     launch_density<T>(l, g, k, a, cs, a.rho, cur, nullptr, flags);
     launch_wall_state<T>(l, g, k, a, cs, (const T*)parts->wall_vel, (int)p->n_wall);
     if (tapes) {
-      // the state after this step (half-step velocity, new density) is the
-      // state before the next
+      // the state after this step (half-step velocity, new density, the
+      // walls' state) is the state before the next
       if (record_post(tape_of(s)) != hipSuccess) return SPH_E_HIP;
       if (s + 1 < nsteps && record_pre(tape_of(s + 1)) != hipSuccess) return SPH_E_HIP;
     }
@@ -477,6 +484,7 @@ int32_t adjoint_step_t(const sph_params* p, const char* tape, sph_adjoint* adj, 
   // state after the step (order n+1) and before it (order n), as recorded
   PArrays<T> post{};
   post.cell = (int*)(tape + tl.post_cell);
+  post.id = p->n_wall > 0 ? (int*)(tape + tl.post_id) : nullptr;
   post.off = (T*)(tape + tl.post_off);
   post.vel = (T*)(tape + tl.post_vhalf);
   post.rho = (T*)(tape + tl.post_rho);
@@ -484,6 +492,7 @@ int32_t adjoint_step_t(const sph_params* p, const char* tape, sph_adjoint* adj, 
   post.h = var ? (T*)(tape + tl.post_h) : nullptr;
   PArrays<T> pre{};
   pre.cell = (int*)(tape + tl.pre_cell);
+  pre.id = p->n_wall > 0 ? (int*)(tape + tl.pre_id) : nullptr;
   pre.off = (T*)(tape + tl.pre_off);
   pre.rho = (T*)(tape + tl.pre_rho);
   pre.mass = var ? (T*)(tape + tl.pre_mass) : nullptr;
@@ -495,10 +504,16 @@ int32_t adjoint_step_t(const sph_params* p, const char* tape, sph_adjoint* adj, 
   T* ghat = (T*)(ws + w.adj_g);
   double* partials = (double*)(ws + w.partials);
 
-  // 7^T: v = v' + dt/2 a  =>  abar += dt/2 vbar, v'bar = vbar
-  launch_adj_kick<T>(l, k, sz.n, v_bar, a_bar);
+  // 7^T: v = v' + dt/2 a  =>  abar += dt/2 vbar, v'bar = vbar (fluid); the
+  // walls' acceleration is not an output (always zero): no cotangent
+  launch_adj_kick<T>(l, k, sz.n, post.id, v_bar, a_bar);
   // 6^T, 5^T: accelerations (r^{n+1}, v', rho^{n+1})
   launch_force_vjp<T>(l, g, k, post, cs_post, post.vel, a_bar, r_bar, v_bar, rho_bar);
+  // the walls' state from the fluid (r^{n+1}, rho^{n+1}, v'), reversed: the
+  // walls' density and velocity cotangents go to their fluid neighbours
+  if (p->n_wall > 0)
+    launch_wall_vjp<T>(l, g, k, post, cs_post, post.vel, (T*)(ws + w.adj_rho),
+                       (T*)(ws + w.adj_r2), (int*)(ws + w.wall_cells), r_bar, v_bar, rho_bar);
   // 4^T: density, then 2-3^T: r^{n+1} = r^n + dt v' + dr  =>  v'bar += dt rbar
   launch_density_vjp<T>(l, g, k, post, cs_post, rho_bar, r_bar, v_bar, k.dt);
   // the cell build is a permutation: back to order n
@@ -511,16 +526,17 @@ int32_t adjoint_step_t(const sph_params* p, const char* tape, sph_adjoint* adj, 
   if (xi_bar) launch_xi_final(stream, sz.n, partials, xi_bar);
   launch_tv_vjp<T>(l, g, k, pre, cs_pre, ghat, (const T*)(tape + tl.g),
                    (const T*)(tape + tl.beta), r_n, r_bar, rho_bar);
-  // 2^T: v' = v^n + dt/2 a^n
-  launch_adj_finish<T>(l, k, sz.n, vh_n, v_bar, a_bar);
+  // 2^T: v' = v^n + dt/2 a^n (fluid)
+  launch_adj_finish<T>(l, k, sz.n, pre.id, vh_n, v_bar, a_bar);
   return hip_status();
 }
 
 template <typename T>
 int32_t adjoint_init_t(const sph_params* p, const sph_particles* parts, const int32_t* cs,
-                       sph_adjoint* adj, hipStream_t stream) {
+                       sph_adjoint* adj, char* ws, hipStream_t stream) {
   const bool var = is_var(p);
   const Sizes sz = sizes_of(p, var);
+  const WsLayout w = ws_layout(sz);
   const Grid g = grid_of(p);
   const Coeffs<T> k = coeffs_of<T>(p, g);
   const Launch l = launch_of(p, var, stream);
@@ -529,7 +545,13 @@ int32_t adjoint_init_t(const sph_params* p, const sph_particles* parts, const in
   T* v_bar = (T*)adj->v_bar;
   T* a_bar = (T*)adj->a_bar;
   T* rho_bar = (T*)adj->rho_bar;
+  if (p->n_wall > 0) launch_zero_walls<T>(l, k, sz.n, a.id, sz.dim, a_bar, (T*)nullptr);
   launch_force_vjp<T>(l, g, k, a, cs, a.vel, a_bar, r_bar, v_bar, rho_bar);
+  // the walls' state from the fluid, reversed (their velocity and density
+  // cotangents go to the fluid; walls' initial velocities are overwritten)
+  if (p->n_wall > 0)
+    launch_wall_vjp<T>(l, g, k, a, cs, a.vel, (T*)(ws + w.adj_rho), (T*)(ws + w.adj_r2),
+                       (int*)(ws + w.wall_cells), r_bar, v_bar, rho_bar);
   launch_density_vjp<T>(l, g, k, a, cs, rho_bar, r_bar, nullptr, T(0));
   launch_zero<T>(stream, a_bar, (long)sz.dim * sz.n);
   launch_zero<T>(stream, rho_bar, (long)sz.n);
@@ -724,7 +746,6 @@ static int32_t kdk_common(const sph_params* p, sph_particles* parts, int32_t* ce
   st = check_particles(p, parts, true);
   if (st != SPH_OK) return st;
   if (!cell_start || !ws || step_index < 0 || nsteps < 0) return SPH_E_ARG;
-  if (tape && p->n_wall > 0) return SPH_E_UNSUPPORTED;
   size_t need = 0;
   sph_workspace_size(p, &need);
   if (ws_bytes < need) return SPH_E_WORKSPACE;
@@ -794,7 +815,6 @@ int32_t sph_adjoint_step(const sph_params* p, const void* tape, sph_adjoint* adj
                          void* ws, size_t ws_bytes, void* stream) {
   int32_t st = check_params(p);
   if (st != SPH_OK) return st;
-  if (p->n_wall > 0) return SPH_E_UNSUPPORTED;
   if (!tape || !adj || !ws) return SPH_E_ARG;
   size_t need = 0;
   sph_workspace_size(p, &need);
@@ -811,7 +831,6 @@ int32_t sph_adjoint_init(const sph_params* p, const sph_particles* parts, const 
                          sph_adjoint* adj, void* ws, size_t ws_bytes, void* stream) {
   int32_t st = check_params(p);
   if (st != SPH_OK) return st;
-  if (p->n_wall > 0) return SPH_E_UNSUPPORTED;
   st = check_particles(p, parts, true);
   if (st != SPH_OK) return st;
   if (!adj || !ws) return SPH_E_ARG;
@@ -822,7 +841,7 @@ int32_t sph_adjoint_init(const sph_params* p, const sph_particles* parts, const 
   if (!cell_start || !adj->r_bar || !adj->v_bar || !adj->a_bar || !adj->rho_bar) return SPH_E_ARG;
   return dispatch(p, [&](auto tag) {
     using T = decltype(tag);
-    return adjoint_init_t<T>(p, parts, cell_start, adj, (hipStream_t)stream);
+    return adjoint_init_t<T>(p, parts, cell_start, adj, (char*)ws, (hipStream_t)stream);
   });
 }
 

@@ -157,11 +157,26 @@ void launch_tv_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PAr
                    T* r_out, T* rho_out);
 template <typename T>
 void launch_unpermute(const Launch& l, int n, const int* perm, const T* src, T* dst, int ncomp);
+// id (optional) tells wall particles, which are neither kicked nor drifted
 template <typename T>
-void launch_adj_finish(const Launch& l, const Coeffs<T>& k, int n, const T* vhalf_bar,
-                       T* v_bar, T* a_bar);
+void launch_adj_finish(const Launch& l, const Coeffs<T>& k, int n, const int* id,
+                       const T* vhalf_bar, T* v_bar, T* a_bar);
 template <typename T>
-void launch_adj_kick(const Launch& l, const Coeffs<T>& k, int n, const T* v_bar, T* a_bar);
+void launch_adj_kick(const Launch& l, const Coeffs<T>& k, int n, const int* id, const T* v_bar,
+                     T* a_bar);
+// reverse of the wall state: wall particles' velocity and density cotangents
+// to their fluid neighbours (and position cotangents of both); wsum [N],
+// wavg [D][N] and wall_cells [ncells] are scratch; the walls' v_bar and
+// rho_bar are cleared
+template <typename T>
+void launch_wall_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
+                     const int* cs, const T* vel, T* wsum, T* wavg, int* wall_cells, T* r_bar,
+                     T* v_bar, T* rho_bar);
+// x[c][i] = 0 (c < ncomp) and, when given, y[i] = 0 for every wall particle i
+// (told by id)
+template <typename T>
+void launch_zero_walls(const Launch& l, const Coeffs<T>& k, int n, const int* id, int ncomp,
+                       T* x, T* y);
 // xi_bar += the xi partials tv_ghat wrote for n particles (one block, fixed order)
 void launch_xi_final(hipStream_t s, int n, const double* partials, double* xi_bar);
 

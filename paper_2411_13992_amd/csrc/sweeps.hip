@@ -133,9 +133,13 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
   if (valid && sub == 0) {
     Limited lim = limit_correction<D>(k, gi, rho[i], dri);
     if (!fluid) {
+      // walls: no correction; g written as +0, as the fused sweep does
       lim = Limited{};
 #pragma unroll
-      for (int d = 0; d < D; ++d) dri[d] = T(0);
+      for (int d = 0; d < D; ++d) {
+        dri[d] = T(0);
+        gi[d] = T(0);
+      }
     }
     double d2 = 0.0;
 #pragma unroll

@@ -35,11 +35,26 @@ def central_fd(f, eps0, tries=5):
     raise AssertionError("limiter branch flips at every tried step size")
 
 
+def _walled(n, dim, seed):
+    """A jittered cavity whose fluid already moves (a smooth field of speed
+    ~0.3 U), so every kind of pair term is active."""
+    case = cases.lid_driven_cavity(n, dim=dim, jitter=0.15, seed=seed)
+    nf = case.n_fluid
+    x = case.pos[:, :nf] - case.extra["origin"]
+    vel = case.vel.copy()
+    vel[0, :nf] = 0.3 * np.sin(np.pi * x[0]) * np.sin(2 * np.pi * x[1])
+    vel[1, :nf] = -0.2 * np.sin(2 * np.pi * x[0]) * np.sin(np.pi * x[1])
+    case.vel = vel
+    return case
+
+
 def _init_cases():
     return {
         "tg2d_jit": cases.taylor_green_2d(24, jitter=0.2, seed=12),
         "tg3d_jit": cases.taylor_green_3d(10, jitter=0.2, seed=13),
         "varres": cases.variable_resolution_2d(dp_min=1.0 / 60, jitter=0.1, seed=14),
+        "cavity": _walled(12, 2, 15),
+        "cavity3d": _walled(6, 3, 16),
     }
 
 
@@ -49,7 +64,9 @@ INIT = _init_cases()
 @pytest.mark.parametrize("name", list(INIT))
 def test_init_vjp_matches_fd(name):
     """(r, v) -> (rho = R(r), a = A(r, v, rho)): <abar, da> + <rhobar, drho> along
-    a random direction equals <rbar, dr> + <vbar, dv> from sph_adjoint_init."""
+    a random direction equals <rbar, dr> + <vbar, dv> from sph_adjoint_init.
+    With walls, the walls' density and velocity come from the fluid between
+    the two (their rho is an output, their acceleration is none)."""
     import torch
     from paper_2411_13992_amd.adjoint import Adjoint, adjoint_init
     case = INIT[name]
@@ -74,6 +91,8 @@ def test_init_vjp_matches_fd(name):
         rho = sim.density(out=torch.empty_like(sim.rho))
         saved = sim.rho.clone()
         sim.rho.copy_(rho)
+        sim.wall_state()
+        rho = sim.rho.clone()
         acc = sim.forces(out=torch.empty_like(sim.acc))
         sim.rho.copy_(saved)
         vals.append(float((abar * acc).sum() + (rbar_in * rho).sum()))
@@ -94,7 +113,8 @@ def _step_loss(sim, c, base_snap):
 
 @pytest.mark.parametrize("name,mode,lanes", [(name, "limited", 0) for name in INIT] +
                          [("tg2d_jit", "scaled", 0), ("tg2d_jit", "background", 0),
-                          ("tg3d_jit", "background", 0), ("varres", "scaled", 0)] +
+                          ("tg3d_jit", "background", 0), ("varres", "scaled", 0),
+                          ("cavity", "scaled", 0), ("cavity", "background", 0)] +
                          [(name, "limited", lanes) for name in INIT for lanes in (2, 4)])
 def test_step_vjp_matches_fd(name, mode, lanes):
     """One kick-drift-kick step as a map of (r^n, v^n, a^n, rho^n, xi): the
@@ -203,6 +223,48 @@ def test_rollout_gradient_matches_oracle_fd(dtype, tol, mode):
         return
     assert fd != 0.0
     assert abs(gxi - fd) <= tol * abs(fd), (gxi, fd)
+
+
+def _oracle_fluid_ke(case, pos, v0, xi, nsteps):
+    st = oracle.State(case, pos=pos, vel=v0, xi=xi)
+    d = st.run(nsteps)
+    return d[-1, 0], d[:, 6]          # the oracle's diagnostics cover the fluid only
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-6), ("f32", 1e-4)])
+def test_walled_rollout_gradient_matches_oracle_fd(dtype, tol):
+    """A jittered 12x12 cavity (lid moving, fluid in motion), 12 steps with
+    checkpoints every 5: the gradient of the fluid's kinetic energy with
+    respect to the fluid's initial velocities (three random directions) and xi
+    against central differences of the FP64 oracle with its walls."""
+    import torch
+    from paper_2411_13992_amd.adjoint import rollout, kinetic_energy
+    case = INIT["cavity"]
+    sim = _sim(case, dtype)
+    pos0 = sim.positions_fp64(sim.initial["cell"], sim.initial["off"])
+    ids0 = sim.initial["id"].cpu().numpy()
+    pos_by_id = np.empty_like(pos0)
+    pos_by_id[:, ids0] = pos0
+    v0 = torch.tensor(case.vel, dtype=torch.float64, device="cuda", requires_grad=True)
+    xi = torch.tensor(case.xi, dtype=torch.float64, device="cuda", requires_grad=True)
+    nsteps = 12
+    loss = kinetic_energy(sim, rollout(sim, v0, xi, nsteps, every=5))
+    loss.backward()
+    gv = v0.grad.cpu().numpy()
+    nf = case.n_fluid
+    # the walls' initial velocities are overwritten by their state: no gradient
+    assert np.all(gv[:, nf:] == 0.0)
+    rng = np.random.default_rng(6)
+    for k in range(3):
+        u = np.zeros_like(case.vel)
+        u[:, :nf] = rng.normal(size=(case.dim, nf))
+        fd = central_fd(lambda e: _oracle_fluid_ke(case, pos_by_id, case.vel + e * u, case.xi,
+                                                   nsteps), 1e-6)
+        assert abs(np.sum(gv * u) - fd) <= tol * abs(fd), (k, np.sum(gv * u), fd)
+    fd = central_fd(lambda e: _oracle_fluid_ke(case, pos_by_id, case.vel, case.xi + e, nsteps),
+                    1e-6)
+    assert fd != 0.0
+    assert abs(xi.grad.item() - fd) <= tol * abs(fd), (xi.grad.item(), fd)
 
 
 def _gpu_ke(sim, v0, xi, nsteps):
