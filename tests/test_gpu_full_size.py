@@ -1,6 +1,7 @@
 """The full-size workloads (the benchmark's 160k-particle Taylor-Green
 square, the 2.1M-particle 3-D Taylor-Green cube, the 1M-particle
-variable-resolution box and the 42k-particle walled cavity), in the launch
+variable-resolution box and the walled 2-D and 3-D cavities of 42k and 2.4M
+particles), in the launch
 configuration of a multi-step run: after three fused steps, the density,
 correction and force sweeps and the neighbour counts are compared with the
 FP64 oracle on a random sample of particles.  The oracle evaluates only the sampled particles (their
@@ -31,7 +32,8 @@ def _rows(nb, sample):
     return sub_start, sub_lst
 
 
-@pytest.mark.parametrize("name", ["tg2d_400", "tg3d_128", "varres2d_1m", "cavity2d_200"])
+@pytest.mark.parametrize("name", ["tg2d_400", "tg3d_128", "varres2d_1m", "cavity2d_200",
+                                  "cavity3d_128"])
 def test_full_size_sweeps_sampled(name):
     import torch
     from paper_2411_13992_amd import Simulation
