@@ -75,11 +75,16 @@ def run(n: int, t_end: float, mode: str = "limited", dtype: str = "f32",
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
+    last = time.perf_counter()
     while done < nsteps:
         k = min(chunk, nsteps - done)
         d = sim.run(k, diag=True)
         ke.append(float(d[-1, 0]))
         done += k
+        if time.perf_counter() - last > 30.0:      # progress on long runs
+            last = time.perf_counter()
+            print(f"  {mode} n {n}: t = {done * case.dt:.2f} of {nsteps * case.dt:.2f}, "
+                  f"KE {ke[-1]:.5f}", flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     state = sim.export()
