@@ -165,13 +165,17 @@ def _pmc_traffic():
 
 
 def source_digest():
-    """SHA-256 over the HIP sources (sorted by name): a counter summary taken on
-    other kernel code is not used."""
+    """SHA-256 over the HIP sources (sorted by name) with comments and
+    whitespace removed: a counter summary taken on other kernel code is not
+    used, one taken before a comment-only edit still is."""
     h = hashlib.sha256()
     for name in sorted(os.listdir(KERNEL_SOURCES)):
         if name.endswith((".hip", ".hpp")):
+            text = open(os.path.join(KERNEL_SOURCES, name)).read()
+            text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", " ", text)
             h.update(name.encode())
-            h.update(open(os.path.join(KERNEL_SOURCES, name), "rb").read())
+            h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

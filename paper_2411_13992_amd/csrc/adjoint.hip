@@ -627,7 +627,7 @@ template <typename T>
 void launch_tv_ghat(const Launch& l, const Coeffs<T>& k, int n, const T* gsum, const T* beta,
                     const T* rho, const T* r_bar, T* ghat, double* partials) {
   if (n == 0) return;
-  // one thread per particle (the partials' first xi_rows(n) rows)
+  // one thread per particle: the partials' first ceil(n / kBlock) * waves-per-block rows
   const dim3 grid((n + kBlock - 1) / kBlock);
   if (l.dim == 2)
     hipLaunchKernelGGL((tv_ghat_kernel<2, T>), grid, dim3(kBlock), 0, l.stream, k, n, gsum, beta,

@@ -2,10 +2,13 @@
 // transport-velocity correction with its limiter (Eq. 14-16) and the
 // Riemann pressure + viscous accelerations (Eq. 2, 3b, 5-7).
 //
-// One thread per particle in (cell, id) order; each thread walks the 3^D
-// cells around its own through cell_start.  Consecutive threads sit in the
-// same or adjacent cells, so their neighbour reads hit the same cache lines.
-// No floating-point atomics: every particle gathers its own sum.
+// A group of G consecutive lanes per particle (G = 2, 4 or 8, by size), the
+// particles in (cell, id) order; the group walks the 3^D cells around the
+// particle's own through cell_start, each lane every G-th candidate.
+// Consecutive groups sit in the same or adjacent cells, so their neighbour
+// reads hit the same cache lines.  No floating-point atomics: every particle
+// gathers its own sum.  Wall particles (told by id) take part as neighbours
+// and get the wall state of wall_state_kernel instead of their own sums.
 //
 // The force sweep has a fused form used inside multi-step runs: it also
 // accumulates the transport-velocity sum g at the same positions and
