@@ -8,12 +8,12 @@ libsph (include/sph.h).  PyTorch supplies device memory and streams only.
 from ._lib import SphError, load as load_library, lattice_kappa  # noqa: F401
 
 __all__ = ["SphError", "load_library", "lattice_kappa", "Simulation", "Config",
-           "config_from_case"]
+           "config_from_case", "StepFlagError"]
 
 
 def __getattr__(name):
     # the torch-based driver is imported on first use
-    if name in ("Simulation", "Config", "config_from_case", "make_params"):
+    if name in ("Simulation", "Config", "config_from_case", "make_params", "StepFlagError"):
         from . import sim
         return getattr(sim, name)
     raise AttributeError(name)

@@ -26,6 +26,7 @@ TV_MODES = {"limited": TV_LIMITED, "scaled": TV_SCALED, "background": TV_BACKGRO
 FLAG_NONFINITE = 1
 FLAG_CFL = 2
 FLAG_OUT_OF_BOX = 4
+FLAG_INTERNAL = 8
 
 DIAG_NAMES = ("ke", "px", "py", "pz", "vmax", "npairs", "nbeta", "nband", "transport_vmax")
 

@@ -85,6 +85,21 @@ def make_params(cfg: Config, n: int, dtype: str, per_particle: bool = False) -> 
     return p
 
 
+class StepFlagError(RuntimeError):
+    """A fused run raised a device flag; the state was restored to the
+    snapshot taken before that run (step_index is where it stands now)."""
+
+    def __init__(self, flags: int, step_index: int):
+        names = [n for bit, n in ((_lib.FLAG_NONFINITE, "non-finite value"),
+                                  (_lib.FLAG_CFL, "a particle moved more than one cell"),
+                                  (_lib.FLAG_OUT_OF_BOX, "position outside the box"),
+                                  (_lib.FLAG_INTERNAL, "internal wait gave up")) if flags & bit]
+        super().__init__(f"device flags {flags:#x} ({', '.join(names)}); state restored to "
+                         f"step {step_index}")
+        self.flags = flags
+        self.step_index = step_index
+
+
 class Simulation:
     """Particles on one GPU advanced by libsph's kick-drift-kick step."""
 
@@ -291,6 +306,60 @@ class Simulation:
                       _vp(self.cs), _vp(self.ws), self.ws_bytes, _vp(self.diag), _stream())
         vals = self.diag.cpu().numpy()
         return dict(zip(_lib.DIAG_NAMES, vals))
+
+    # ------------------------------------------------------------ recovery
+    def save_checkpoint(self, path: str) -> None:
+        """Write the state (sorted arrays, cell_start, step index, and the
+        run parameters it belongs to) to an uncompressed .npz file; no
+        pickled objects, so np.load with its default allow_pickle=False reads
+        it back."""
+        arrays = {k: getattr(self, k).cpu().numpy() for k in self._STATE}
+        if self.var:
+            arrays["mass"] = self.mass.cpu().numpy()
+            arrays["h"] = self.h.cpu().numpy()
+        if self.n_wall:
+            arrays["wall_vel"] = self.wall_vel.cpu().numpy()
+        arrays["step_index"] = np.array(self.step_index, dtype=np.int64)
+        arrays["params"] = np.frombuffer(bytes(self.params), dtype=np.uint8)
+        np.savez(path, **arrays)
+
+    def load_checkpoint(self, path: str) -> None:
+        """Restore a state written by save_checkpoint for the same run
+        parameters (checked byte for byte, xi aside)."""
+        with np.load(path) as z:
+            mine = bytearray(bytes(self.params))
+            theirs = bytearray(z["params"].tobytes())
+            off = _lib.SphParams.xi.offset
+            mine[off:off + 8] = theirs[off:off + 8] = bytes(8)
+            if mine != theirs:
+                raise ValueError(f"{path}: checkpoint of a different configuration")
+            for k in self._STATE:
+                getattr(self, k).copy_(torch.from_numpy(z[k]))
+            if self.var:
+                self.mass.copy_(torch.from_numpy(z["mass"]))
+                self.h.copy_(torch.from_numpy(z["h"]))
+            if self.n_wall:
+                self.wall_vel.copy_(torch.from_numpy(z["wall_vel"]))
+            self.step_index = int(z["step_index"])
+
+    def run_checked(self, nsteps: int, chunk: int = 500, diag=False) -> int:
+        """nsteps steps in fused runs of at most `chunk`, checking the device
+        flags after each; a run that raised a flag (non-finite value, a
+        particle moving more than a cell in a step, ...) is undone: the state
+        goes back to the snapshot taken before it and StepFlagError reports
+        the flag word and the step index reached (recovery: restart from the
+        last good state, e.g. with a smaller dt).  Returns the steps done."""
+        done = 0
+        while done < nsteps:
+            k = min(chunk, nsteps - done)
+            snap = self.snapshot()
+            self.run(k, diag=diag)
+            f = self.flags()
+            if f:
+                self.restore(snap)
+                raise StepFlagError(f, self.step_index)
+            done += k
+        return done
 
     def flags(self) -> int:
         out = ctypes.c_uint32(0)
