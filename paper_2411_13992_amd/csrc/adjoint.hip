@@ -235,9 +235,10 @@ __global__ __launch_bounds__(kBlock) void density_vjp_kernel(
 // The wall state (sph_wall_state) for wall a over its fluid neighbours f:
 //   S_a = sum W_af,  rho_a = rho0 + sum (rho_f - rho0) W_af / S_a,
 //   v_a = 2 u_a - Vbar_a,  Vbar_a = sum v_f W_af / S_a.
-// Pass 1 stores S_a and Vbar_a per wall particle (sorted order) and marks
-// the cells that hold walls.  Pass 2 is a gather over the fluid-wall pairs
-// (particles whose 3^D cells hold no wall skip it): with
+// S_a and Vbar_a per wall particle (by id - nfluid) come from the forward
+// wall state recorded in the tape, or, for the initial state, from pass 1;
+// the cells that hold walls are marked first.  Pass 2 is a gather over the
+// fluid-wall pairs (particles whose 3^D cells hold no wall skip it): with
 //   c_af = (rhobar_a (rho_f - rho_a) - vbar_a . (v_f - Vbar_a)) / S_a,
 // a fluid particle f collects rhobar_f += rhobar_a W_af / S_a,
 // vbar_f -= vbar_a W_af / S_a and rbar_f += c_af F_af (r_f - r_a); a wall
@@ -248,7 +249,7 @@ template <int D, typename T, bool VAR, int G>
 __global__ __launch_bounds__(kBlock) void wall_sums_kernel(
     Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
     const T* __restrict__ off, const T* __restrict__ hh, const int* __restrict__ id,
-    const T* __restrict__ vel, T* __restrict__ wsum, T* __restrict__ wavg,
+    const T* __restrict__ vel, T* __restrict__ wsum, T* __restrict__ wavg, int n_wall,
     int* __restrict__ wall_cells) {
   const int n = g.n;
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
@@ -285,11 +286,11 @@ __global__ __launch_bounds__(kBlock) void wall_sums_kernel(
   T V[3];
 #pragma unroll
   for (int d = 0; d < D; ++d) V[d] = group_sum<G>(sv[d]);
-  if (wall && sub == 0) {
-    wall_cells[cell[i]] = 1;      // every writer stores the same value
-    wsum[i] = S;
+  const int iw = wall ? id[i] - k.nfluid : 0;
+  if (wall && sub == 0 && iw < n_wall) {
+    wsum[iw] = S;
 #pragma unroll
-    for (int d = 0; d < D; ++d) wavg[d * n + i] = S > T(0) ? V[d] / S : T(0);
+    for (int d = 0; d < D; ++d) wavg[(size_t)d * n_wall + iw] = S > T(0) ? V[d] / S : T(0);
   }
 }
 
@@ -298,8 +299,8 @@ __global__ __launch_bounds__(kBlock) void wall_vjp_kernel(
     Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
     const T* __restrict__ off, const T* __restrict__ hh, const int* __restrict__ id,
     const T* __restrict__ vel, const T* __restrict__ rho, const T* __restrict__ wsum,
-    const T* __restrict__ wavg, const int* __restrict__ wall_cells, T* __restrict__ r_bar,
-    T* __restrict__ v_bar, T* __restrict__ rho_bar) {
+    const T* __restrict__ wavg, int n_wall, const int* __restrict__ wall_cells,
+    T* __restrict__ r_bar, T* __restrict__ v_bar, T* __restrict__ rho_bar) {
   const int n = g.n;
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
@@ -324,8 +325,8 @@ __global__ __launch_bounds__(kBlock) void wall_vjp_kernel(
     }
   }
   if (!__any(near)) return;       // whole wavefront: no lane needs a group sum
-  const Cols<T, D> offc(off, n), velc(vel, n), vbarc(v_bar, n), wavgc(wavg, n);
-  const Cols<T, 1> hc(hh, n), rhoc(rho, n), rbarc(rho_bar, n), wsumc(wsum, n);
+  const Cols<T, D> offc(off, n), velc(vel, n), vbarc(v_bar, n);
+  const Cols<T, 1> hc(hh, n), rhoc(rho, n), rbarc(rho_bar, n);
   VjpAcc<T> ra[3], va[3], pa;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -334,17 +335,19 @@ __global__ __launch_bounds__(kBlock) void wall_vjp_kernel(
   }
   pa.init(T(0));
   if (valid && near) {
+    // a wall's own sums, by wall index (id - nfluid < n_wall for ids below n)
+    const int iw = wall_i ? min(id[i] - k.nfluid, n_wall - 1) : 0;
     T oi[3], vi[3], vbi[3], avi[3];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       oi[d] = off[d * n + i];
       vi[d] = vel[d * n + i];
       vbi[d] = wall_i ? v_bar[d * n + i] : T(0);
-      avi[d] = wall_i ? wavg[d * n + i] : T(0);
+      avi[d] = wall_i ? wavg[(size_t)d * n_wall + iw] : T(0);
     }
     const T rhoi = rho[i];
     const T pbi = wall_i ? rho_bar[i] : T(0);
-    const T si = wall_i ? wsum[i] : T(0);
+    const T si = wall_i ? wsum[iw] : T(0);
     const T hi = VAR ? hh[i] : k.h;
     for_each_candidate<D, G>(g, k, cell[i], cs, sub, [&](int j, const T* sh) {
       T r[3];
@@ -355,13 +358,15 @@ __global__ __launch_bounds__(kBlock) void wall_vjp_kernel(
         r2 = tfma(r[d], r[d], r2);
       }
       const PairH<D, T, VAR> ph = pair_h<D, T, VAR>(k, hi, VAR ? hc(0, j) : T(0));
-      if (!(r2 < ph.sup2) || is_wall(k, id[j]) == wall_i) return;   // fluid-wall pairs
+      const int idj = id[j];
+      if (!(r2 < ph.sup2) || is_wall(k, idj) == wall_i) return;     // fluid-wall pairs
       const PairGeo<T> pg = pair_geo(r2);
       const T t = kernel_t(pg.r, ph.inv_h);
       const T F = ph.fc * (t * t * t);
       if (!wall_i) {
         // i = f (fluid), j = a (wall)
-        const T sa = wsumc(0, j);
+        const int jw = min(idj - k.nfluid, n_wall - 1);
+        const T sa = wsum[jw];
         if (!(sa > T(0))) return;
         const T inv = T(1) / sa;
         const T w = wendland_alpha<D>(ph.inv_h) * wendland_shape(pg.r * ph.inv_h);
@@ -370,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void wall_vjp_kernel(
 #pragma unroll
         for (int d = 0; d < D; ++d) {
           const T vbj = vbarc(d, j);
-          c -= vbj * (vi[d] - wavgc(d, j));
+          c -= vbj * (vi[d] - wavg[(size_t)d * n_wall + jw]);
           va[d].add(-vbj * w * inv);
         }
         pa.add(pbj * w * inv);
@@ -671,16 +676,29 @@ void launch_adj_finish(const Launch& l, const Coeffs<T>& k, int n, const int* id
                      n, k.half_dt, k.nfluid, id, vhalf_bar, v_bar, a_bar);
 }
 
+// wall_cells[c] = 1 for the cells holding a wall particle (cells cleared first)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void mark_wall_cells_kernel(Coeffs<T> k, int n,
+                                                                 const int* __restrict__ id,
+                                                                 const int* __restrict__ cell,
+                                                                 int* __restrict__ wall_cells) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n && is_wall(k, id[i])) wall_cells[cell[i]] = 1;   // every writer stores 1
+}
+
 template <typename T>
 void launch_wall_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
-                     const int* cs, const T* vel, T* wsum, T* wavg, int* wall_cells, T* r_bar,
-                     T* v_bar, T* rho_bar) {
-  if (g.n == 0) return;
+                     const int* cs, const T* vel, T* wsum, T* wavg, int n_wall, bool sums_given,
+                     int* wall_cells, T* r_bar, T* v_bar, T* rho_bar) {
+  if (g.n == 0 || n_wall == 0) return;
   launch_fill(l.stream, wall_cells, g.ncells, 0);
-  SPH_SWEEP(wall_sums_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.h, p.id, vel, wsum, wavg,
-                                       wall_cells));
+  hipLaunchKernelGGL((mark_wall_cells_kernel<T>), dim3(blocks_for(g.n)), dim3(kBlock), 0,
+                     l.stream, k, g.n, p.id, p.cell, wall_cells);
+  if (!sums_given)
+    SPH_SWEEP(wall_sums_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.h, p.id, vel, wsum, wavg,
+                                         n_wall, wall_cells));
   SPH_SWEEP(wall_vjp_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.h, p.id, vel, p.rho, wsum, wavg,
-                                      wall_cells, r_bar, v_bar, rho_bar));
+                                      n_wall, wall_cells, r_bar, v_bar, rho_bar));
   launch_zero_walls<T>(l, k, g.n, p.id, l.dim, v_bar, rho_bar);
 }
 
@@ -714,8 +732,8 @@ void launch_xi_final(hipStream_t s, int n, const double* partials, double* xi_ba
   template void launch_adj_finish<T>(const Launch&, const Coeffs<T>&, int, const int*,        \
                                      const T*, T*, T*);                                      \
   template void launch_wall_vjp<T>(const Launch&, const Grid&, const Coeffs<T>&,             \
-                                   const PArrays<T>&, const int*, const T*, T*, T*, int*,    \
-                                   T*, T*, T*);                                              \
+                                   const PArrays<T>&, const int*, const T*, T*, T*, int,     \
+                                   bool, int*, T*, T*, T*);                                  \
   template void launch_zero_walls<T>(const Launch&, const Coeffs<T>&, int, const int*, int,  \
                                      T*, T*);
 SPH_INST(float)

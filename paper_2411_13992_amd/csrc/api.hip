@@ -37,6 +37,7 @@ struct TapeLayout {
   size_t pre_cell, pre_off, pre_rho, pre_mass, pre_h, pre_cs, g, beta, perm;
   size_t post_cell, post_off, post_vhalf, post_rho, post_mass, post_h, post_cs;
   size_t pre_id, post_id;   // particle ids (walled runs only: walls are told by id)
+  size_t wsum, wavg;        // walls' kernel sums and averaged fluid velocity (walled runs)
   size_t total;
 };
 
@@ -147,6 +148,8 @@ TapeLayout tape_layout(const Sizes& s) {
   tl.post_cs = c.take(cs);
   tl.pre_id = c.take(s.nwall > 0 ? sizeof(int) * n : 0);
   tl.post_id = c.take(s.nwall > 0 ? sizeof(int) * n : 0);
+  tl.wsum = c.take(t * (size_t)s.nwall);
+  tl.wavg = c.take(t * (size_t)s.dim * (size_t)s.nwall);
   tl.total = c.o;
   return tl;
 }
@@ -427,7 +430,9 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
     launch_rank_gather<T>(l, sz.n, st, src, dst, perm);
     // 4. density summation (Eq. 8); wall particles from the fluid
     launch_density<T>(l, g, k, a, cs, a.rho, cur, nullptr, flags);
-    launch_wall_state<T>(l, g, k, a, cs, (const T*)parts->wall_vel, (int)p->n_wall);
+    launch_wall_state<T>(l, g, k, a, cs, (const T*)parts->wall_vel, (int)p->n_wall,
+                         tapes ? (T*)(tape_of(s) + tl.wsum) : nullptr,
+                         tapes ? (T*)(tape_of(s) + tl.wavg) : nullptr);
     if (tapes) {
       // the state after this step (half-step velocity, new density, the
       // walls' state) is the state before the next
@@ -512,8 +517,9 @@ int32_t adjoint_step_t(const sph_params* p, const char* tape, sph_adjoint* adj, 
   // the walls' state from the fluid (r^{n+1}, rho^{n+1}, v'), reversed: the
   // walls' density and velocity cotangents go to their fluid neighbours
   if (p->n_wall > 0)
-    launch_wall_vjp<T>(l, g, k, post, cs_post, post.vel, (T*)(ws + w.adj_rho),
-                       (T*)(ws + w.adj_r2), (int*)(ws + w.wall_cells), r_bar, v_bar, rho_bar);
+    launch_wall_vjp<T>(l, g, k, post, cs_post, post.vel, (T*)(tape + tl.wsum),
+                       (T*)(tape + tl.wavg), (int)p->n_wall, true, (int*)(ws + w.wall_cells),
+                       r_bar, v_bar, rho_bar);
   // 4^T: density, then 2-3^T: r^{n+1} = r^n + dt v' + dr  =>  v'bar += dt rbar
   launch_density_vjp<T>(l, g, k, post, cs_post, rho_bar, r_bar, v_bar, k.dt);
   // the cell build is a permutation: back to order n
@@ -551,7 +557,7 @@ int32_t adjoint_init_t(const sph_params* p, const sph_particles* parts, const in
   // cotangents go to the fluid; walls' initial velocities are overwritten)
   if (p->n_wall > 0)
     launch_wall_vjp<T>(l, g, k, a, cs, a.vel, (T*)(ws + w.adj_rho), (T*)(ws + w.adj_r2),
-                       (int*)(ws + w.wall_cells), r_bar, v_bar, rho_bar);
+                       (int)p->n_wall, false, (int*)(ws + w.wall_cells), r_bar, v_bar, rho_bar);
   launch_density_vjp<T>(l, g, k, a, cs, rho_bar, r_bar, nullptr, T(0));
   launch_zero<T>(stream, a_bar, (long)sz.dim * sz.n);
   launch_zero<T>(stream, rho_bar, (long)sz.n);
@@ -714,7 +720,7 @@ int32_t sph_wall_state(const sph_params* p, sph_particles* parts, const int32_t*
   return dispatch(p, [&](auto tag) {
     using T = decltype(tag);
     launch_wall_state<T>(l, g, coeffs_of<T>(p, g), arrays_of<T>(parts), cell_start,
-                         (const T*)parts->wall_vel, (int)p->n_wall);
+                         (const T*)parts->wall_vel, (int)p->n_wall, (T*)nullptr, (T*)nullptr);
     return hip_status();
   });
 }

@@ -82,10 +82,12 @@ template <typename T>
 void launch_forces_fused(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                          const int* cs, const FusedOut<T>& fo, unsigned* flags);
 // wall particles' density and mirror velocity from their fluid neighbours
-// (p.rho, p.vel of walls written; wall_vel [D][n_wall] by id - nfluid)
+// (p.rho, p.vel of walls written; wall_vel [D][n_wall] by id - nfluid); with
+// wsum_out / wavg_out ([n_wall], [D][n_wall] by id - nfluid) also the kernel
+// sum S_a and the averaged fluid velocity the adjoint needs
 template <typename T>
 void launch_wall_state(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
-                       const int* cs, const T* wall_vel, int n_wall);
+                       const int* cs, const T* wall_vel, int n_wall, T* wsum_out, T* wavg_out);
 
 // ---- cells (cells.hip)
 template <typename T>
@@ -168,10 +170,13 @@ void launch_adj_kick(const Launch& l, const Coeffs<T>& k, int n, const int* id, 
 // to their fluid neighbours (and position cotangents of both); wsum [N],
 // wavg [D][N] and wall_cells [ncells] are scratch; the walls' v_bar and
 // rho_bar are cleared
+// wsum [n_wall] / wavg [D][n_wall] (by id - nfluid) hold the walls' kernel
+// sums and averaged fluid velocities when sums_given (recorded by the forward
+// wall state), else they are computed into them first
 template <typename T>
 void launch_wall_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
-                     const int* cs, const T* vel, T* wsum, T* wavg, int* wall_cells, T* r_bar,
-                     T* v_bar, T* rho_bar);
+                     const int* cs, const T* vel, T* wsum, T* wavg, int n_wall, bool sums_given,
+                     int* wall_cells, T* r_bar, T* v_bar, T* rho_bar);
 // x[c][i] = 0 (c < ncomp) and, when given, y[i] = 0 for every wall particle i
 // (told by id)
 template <typename T>

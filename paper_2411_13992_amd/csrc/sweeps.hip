@@ -387,7 +387,8 @@ template <int D, typename T, bool VAR, int G>
 __global__ __launch_bounds__(kBlock) void wall_state_kernel(
     Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
     const T* __restrict__ off, const T* __restrict__ hh, const int* __restrict__ id,
-    const T* __restrict__ wall_vel, int n_wall, T* __restrict__ rho, T* __restrict__ vel) {
+    const T* __restrict__ wall_vel, int n_wall, T* __restrict__ rho, T* __restrict__ vel,
+    T* __restrict__ wsum_out, T* __restrict__ wavg_out) {
   const int n = g.n;
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
@@ -445,6 +446,12 @@ __global__ __launch_bounds__(kBlock) void wall_state_kernel(
       const T ua = w < n_wall ? wall_vel[(size_t)d * n_wall + w] : T(0);
       vel[d * n + i] = T(2) * ua - (any ? V[d] * inv : ua);
     }
+    // for the adjoint: sum W (with alpha) and the averaged fluid velocity
+    if (wsum_out && w < n_wall) {
+      wsum_out[w] = VAR ? S : S * k.alpha;
+#pragma unroll
+      for (int d = 0; d < D; ++d) wavg_out[(size_t)d * n_wall + w] = any ? V[d] * inv : T(0);
+    }
   }
 }
 
@@ -486,15 +493,15 @@ void launch_forces_fused(const Launch& l, const Grid& g, const Coeffs<T>& k, con
 
 template <typename T>
 void launch_wall_state(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
-                       const int* cs, const T* wall_vel, int n_wall) {
+                       const int* cs, const T* wall_vel, int n_wall, T* wsum_out, T* wavg_out) {
   if (g.n == 0 || n_wall == 0) return;
   SPH_SWEEP(wall_state_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.h, p.id, wall_vel, n_wall,
-                                        p.rho, p.vel));
+                                        p.rho, p.vel, wsum_out, wavg_out));
 }
 
 #define SPH_INST(T)                                                                          \
   template void launch_wall_state<T>(const Launch&, const Grid&, const Coeffs<T>&,           \
-                                     const PArrays<T>&, const int*, const T*, int);          \
+                                     const PArrays<T>&, const int*, const T*, int, T*, T*);  \
   template void launch_density<T>(const Launch&, const Grid&, const Coeffs<T>&,              \
                                   const PArrays<T>&, const int*, T*, double*, int*,          \
                                   unsigned*);                                                \
