@@ -7,9 +7,12 @@ is the whole hot path: correction sweep, kick + drift + rebin, cell build,
 density sweep, force sweep, kick + FP64 diagnostics.  Inputs are resident on
 the GPU before timing starts.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+        [--workload tg2d_400 | tg3d_128 | varres2d_1m | cavity2d_200 | cavity3d_128]
 
-Prints one JSON line.  `value` is FP32 pair interactions per second (ordered
+Prints one JSON line.  The default workload is the benchmark; the others
+(3-D Taylor-Green cube, variable-resolution box, walled 2-D and 3-D cavities)
+print the same line format.  `value` is FP32 pair interactions per second (ordered
 neighbour pairs j != i with r < 2h, counted by the step itself, divided by the
 step time).  Extra fields: the FP64 rate, the adjoint / forward time ratio,
 the roofline of the dominant kernel (the force sweep, timed live with HIP
