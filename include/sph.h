@@ -142,8 +142,10 @@ typedef struct {
 
 /* Number of diagnostics written by sph_kdk_step / sph_diagnostics. */
 #define SPH_NDIAG 9
-/* diag[0] kinetic energy 1/2 sum m |v|^2, diag[1..3] momentum sum m v,
- * diag[4] max |v|, diag[5] ordered neighbour pairs at r^{n+1},
+/* Over the fluid particles (all particles without walls):
+ * diag[0] kinetic energy 1/2 sum m |v|^2, diag[1..3] momentum sum m v,
+ * diag[4] max |v|, diag[5] ordered neighbour pairs at r^{n+1} (every
+ * particle's),
  * diag[6] particles with beta > 0 at step n, diag[7] particles in the
  * limiter band, diag[8] max |dr| / dt (the transport-velocity magnitude of
  * Sec. 3's overcorrection discussion).  All reductions are FP64 and
@@ -207,7 +209,8 @@ int32_t sph_forces(const sph_params *p, const sph_particles *parts,
  * after each density summation; a caller evaluating sph_forces by hand calls
  * it between sph_density and sph_forces.  The box stays periodic: walls at
  * least 2 h_max thick keep the fluid from reaching across its seam.  Walled
- * runs are differentiable: their tapes also record the particle ids, and the
+ * runs are differentiable: their tapes also record the particle ids and each
+ * wall's kernel sum and averaged fluid velocity, and the
  * adjoint entry points reverse the wall state too (the walls' density and
  * velocity cotangents go to their fluid neighbours, and to both sides'
  * positions); the walls' acceleration is not an output (its cotangent is
