@@ -106,7 +106,8 @@ typedef struct {
     double band_tol;      /* relative half-width of the limiter band counted in
                              the diagnostics: |s - s0| <= band_tol * s0          */
     int64_t n_wall;       /* 0 <= n_wall <= n: particles with id >= n - n_wall
-                             are wall particles (see sph_wall_state)             */
+                             are wall particles (see sph_wall_state); with
+                             per_particle = 1: SPH_E_UNSUPPORTED                 */
     int32_t lanes;        /* lanes per particle in the neighbour sweeps: 2, 4 or
                              8, or 0 to let the library choose by size (more
                              lanes for small n); other values: SPH_E_ARG.  The

@@ -169,6 +169,8 @@ int32_t check_params(const sph_params* p) {
       p->tv_mode != SPH_TV_BACKGROUND)
     return SPH_E_ARG;
   if (p->n_wall < 0 || p->n_wall > p->n) return SPH_E_ARG;
+  // walls are built and tested for uniform resolution only
+  if (p->n_wall > 0 && p->per_particle) return SPH_E_UNSUPPORTED;
   if (p->lanes != 0 && p->lanes != 2 && p->lanes != 4 && p->lanes != 8) return SPH_E_ARG;
   const double vals[] = {p->rho0, p->c0, p->h_min, p->h_max, p->kappa, p->mass};
   for (double v : vals)

@@ -87,6 +87,7 @@ def test_argument_validation():
     assert _status(_params(n_wall=1000))[0] == 0
     assert _status(_params(n_wall=1001))[0] == -1
     assert _status(_params(n_wall=-1))[0] == -1
+    assert _status(_params(n_wall=10, per_particle=1))[0] == -6    # walls: uniform resolution
     for lanes in (0, 2, 4, 8):
         assert _status(_params(lanes=lanes))[0] == 0
     assert _status(_params(lanes=3))[0] == -1
