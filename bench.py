@@ -167,13 +167,18 @@ def _pmc_traffic():
     return float(b.group(1)) if source_digest() == m.group(1) else None
 
 
+# the sources the force sweep is compiled from
+FORCE_SWEEP_SOURCES = ("sph_dev.hpp", "sph_internal.hpp", "sweeps.hip")
+
+
 def source_digest():
-    """SHA-256 over the HIP sources (sorted by name) with comments and
-    whitespace removed: a counter summary taken on other kernel code is not
-    used, one taken before a comment-only edit still is."""
+    """SHA-256 over the force sweep's sources (sorted by name) with comments
+    and whitespace removed: a counter summary taken on other kernel code is
+    not used, one taken before a comment-only edit (or an edit of code the
+    force sweep does not contain) still is."""
     h = hashlib.sha256()
     for name in sorted(os.listdir(KERNEL_SOURCES)):
-        if name.endswith((".hip", ".hpp")):
+        if name in FORCE_SWEEP_SOURCES:
             text = open(os.path.join(KERNEL_SOURCES, name)).read()
             text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
             text = re.sub(r"//[^\n]*", " ", text)
