@@ -597,16 +597,7 @@ __global__ __launch_bounds__(kBlock) void adj_finish_kernel(long dn, int n, T ha
 __global__ __launch_bounds__(kBlock) void xi_final_kernel(int nrows, const double* __restrict__ partials,
                                                           double* __restrict__ xi_bar) {
   __shared__ double red[kBlock / kWave];
-  // four independent chains per thread (fixed order: deterministic)
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int r = threadIdx.x; r < nrows; r += 4 * kBlock) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int rr = r + u * kBlock;
-      a[u] += rr < nrows ? partials[rr] : 0.0;
-    }
-  }
-  const double t = block_reduce<double, false>((a[0] + a[1]) + (a[2] + a[3]), red);
+  const double t = block_reduce<double, false>(fold_rows<false>(partials, nrows), red);
   if (threadIdx.x == 0) xi_bar[0] += t;
 }
 

@@ -192,14 +192,69 @@ __device__ __forceinline__ void for_each_candidate(const Grid& g, const Coeffs<T
   }
 }
 
+// ---------------------------------------------------------------- lane moves
+// DPP (data-parallel primitive) moves: a lane reads a register of another
+// lane in its row of 16 with one VALU instruction per 32-bit half, instead of
+// a round trip through the LDS crossbar (ds_bpermute, which __shfl uses).
+// A source lane that is switched off reads as 0; every caller runs with the
+// whole wavefront on.  Control codes of the GFX9 DPP encoding: a quad
+// permutation [p0, p1, p2, p3] is p0 | p1 << 2 | p2 << 4 | p3 << 6.
+constexpr int kDppQuadXor1 = 0xB1;        // [1, 0, 3, 2]
+constexpr int kDppQuadXor2 = 0x4E;        // [2, 3, 0, 1]
+constexpr int kDppRowHalfMirror = 0x141;  // lane l of 8 reads lane 7 - l
+constexpr int kDppRowMirror = 0x140;      // lane l of 16 reads lane 15 - l
+
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_move(T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(
+        T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
+  } else {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __builtin_bit_cast(T, (long long)(((unsigned long long)(unsigned)hi << 32) |
+                                             (unsigned)lo));
+  }
+}
+
+// Lane `LANE`'s value of a double, in every lane (a wave-uniform read).
+template <int LANE>
+__device__ __forceinline__ double read_lane(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, LANE);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), LANE);
+  return __builtin_bit_cast(double,
+                            (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Quad permutation by which every lane of a group of G (2 or 4) consecutive
+// lanes reads the group's lane Q.
+template <int G, int Q>
+constexpr int quad_group_read() {
+  static_assert((G == 2 || G == 4) && Q < G, "groups of 2 or 4 lanes");
+  return G == 4 ? Q * 0x55 : (Q | Q << 2 | (2 + Q) << 4 | (2 + Q) << 6);
+}
+
 // Combines the partial sums of a lane group (G consecutive lanes) in a fixed
-// order, compensated when the accumulator is: the result is the same in every
-// lane of the group and does not depend on timing.
+// order (lane 0 of the group first), compensated when the accumulator is:
+// the result is the same in every lane of the group and does not depend on
+// timing.
 template <int G, typename T, bool COMP>
 __device__ __forceinline__ T group_sum(const Acc<T, COMP>& a) {
   const T v = a.value();
   if constexpr (G == 1) {
     return v;
+  } else if constexpr (G == 2 || G == 4) {
+    Acc<T, COMP> tot;
+    tot.init(dpp_move<quad_group_read<G, 0>()>(v));
+    tot.add(dpp_move<quad_group_read<G, 1>()>(v));
+    if constexpr (G == 4) {
+      tot.add(dpp_move<quad_group_read<G, 2>()>(v));
+      tot.add(dpp_move<quad_group_read<G, 3>()>(v));
+    }
+    return tot.value();
   } else {
     const int lane = threadIdx.x % kWave;
     const int base = lane - lane % G;
@@ -211,15 +266,15 @@ __device__ __forceinline__ T group_sum(const Acc<T, COMP>& a) {
   }
 }
 
+// Integer sum over a lane group of G = 1, 2, 4 or 8 (exact, so the pairing
+// does not matter): pairs, then quads, then the two quads of eight lanes.
 template <int G>
 __device__ __forceinline__ int group_sum_int(int v) {
-  if constexpr (G == 1) {
-    return v;
-  } else {
-#pragma unroll
-    for (int m = G / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, kWave);
-    return v;
-  }
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8, "lane groups of 1, 2, 4 or 8");
+  if constexpr (G >= 2) v += dpp_move<kDppQuadXor1>(v);
+  if constexpr (G >= 4) v += dpp_move<kDppQuadXor2>(v);
+  if constexpr (G >= 8) v += dpp_move<kDppRowHalfMirror>(v);
+  return v;
 }
 
 // ---------------------------------------------------------------- pair terms
@@ -575,21 +630,26 @@ __device__ __forceinline__ void for_each_neighbour_listed(const Grid& g, const C
 }
 
 // ---------------------------------------------------------------- reductions
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int m = kWave / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, kWave);
-  return v;
+// Sum or maximum over the 64 lanes of a wavefront, in every lane: DPP moves
+// combine pairs, quads, halves and whole rows of 16, then the four row
+// results are read out and combined in the order 0, 16, 32, 48.  The order is
+// fixed, so the result is bit-reproducible.  Maxima are taken over values
+// >= 0 (a switched-off lane would read as 0).
+template <bool MAX>
+__device__ __forceinline__ double lane_combine(double a, double b) {
+  return MAX ? (a > b ? a : b) : a + b;
 }
-template <typename T>
-__device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-  for (int m = kWave / 2; m > 0; m >>= 1) {
-    T o = __shfl_xor(v, m, kWave);
-    v = v > o ? v : o;
-  }
-  return v;
+template <bool MAX>
+__device__ __forceinline__ double wave_reduce(double v) {
+  v = lane_combine<MAX>(v, dpp_move<kDppQuadXor1>(v));
+  v = lane_combine<MAX>(v, dpp_move<kDppQuadXor2>(v));
+  v = lane_combine<MAX>(v, dpp_move<kDppRowHalfMirror>(v));
+  v = lane_combine<MAX>(v, dpp_move<kDppRowMirror>(v));
+  return lane_combine<MAX>(lane_combine<MAX>(read_lane<0>(v), read_lane<16>(v)),
+                           lane_combine<MAX>(read_lane<32>(v), read_lane<48>(v)));
 }
+__device__ __forceinline__ double wave_sum(double v) { return wave_reduce<false>(v); }
+__device__ __forceinline__ double wave_max(double v) { return wave_reduce<true>(v); }
 
 // Block-wide sum/max of one value per thread (blockDim.x == kBlock); the
 // result is valid in thread 0.  Fixed order, hence deterministic.
@@ -654,23 +714,43 @@ __device__ __forceinline__ void wave_partials(double* __restrict__ p, const int*
 
 // Folds column `col` of the partials (nrows rows) into diag[col], in a fixed
 // order (sum, or maximum for columns 4 and 8): deterministic.  One block per
-// column; must run in a later launch than the writers.
+// column; must run in a later launch than the writers.  Each thread keeps
+// eight accumulators and issues its eight loads of a round together (the row
+// index is clamped so every load is in bounds; rows past the end count as 0),
+// so a round costs one memory latency.
+template <bool MAX>
+__device__ __forceinline__ double fold_rows(const double* __restrict__ c, int nrows) {
+  constexpr int U = 8;
+  double a[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) a[u] = 0.0;
+  for (int r = threadIdx.x; r < nrows; r += U * kBlock) {
+    double x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int rr = r + u * kBlock;
+      x[u] = c[rr < nrows ? rr : nrows - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[u] = lane_combine<MAX>(a[u], r + u * kBlock < nrows ? x[u] : 0.0);
+  }
+#pragma unroll
+  for (int w = U / 2; w > 0; w /= 2) {
+#pragma unroll
+    for (int u = 0; u < w; ++u) a[u] = lane_combine<MAX>(a[u], a[u + w]);
+  }
+  return a[0];
+}
+
 __device__ __forceinline__ void fold_diag_column(const double* __restrict__ partials, int nrows,
                                                  int col, double* __restrict__ diag) {
   __shared__ double red[kBlock / kWave];
-  const bool is_max = (col == 4 || col == 8);
   const double* c = partials + (size_t)col * nrows;
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int r = threadIdx.x; r < nrows; r += 4 * kBlock) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int rr = r + u * kBlock;
-      const double x = rr < nrows ? c[rr] : 0.0;
-      a[u] = is_max ? (x > a[u] ? x : a[u]) : a[u] + x;
-    }
-  }
-  double v = is_max ? fmax(fmax(a[0], a[1]), fmax(a[2], a[3])) : (a[0] + a[1]) + (a[2] + a[3]);
-  v = is_max ? block_reduce<double, true>(v, red) : block_reduce<double, false>(v, red);
+  double v;
+  if (col == 4 || col == 8)
+    v = block_reduce<double, true>(fold_rows<true>(c, nrows), red);
+  else
+    v = block_reduce<double, false>(fold_rows<false>(c, nrows), red);
   if (threadIdx.x == 0) diag[col] = v;
 }
 
