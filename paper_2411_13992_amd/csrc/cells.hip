@@ -233,7 +233,14 @@ void launch_scatter(hipStream_t s, int n, const int* cell, const int* id, const 
 
 // ------------------------------------------------------------------ rank + gather
 // Slot p holds a particle of some cell; its final position is the cell start
-// plus the number of cell members with a smaller id.
+// plus the number of cell members with a smaller id.  The gathered values are
+// loaded first, so their latency overlaps the ranking, and the ranking reads
+// the cell's ids eight at a time with the eight loads issued together (the
+// index is clamped into the cell, which holds at least this particle; reads
+// past its end are not counted): a few memory latencies per thread instead of
+// one per cell member and one per array.
+constexpr int kRankBatch = 8;
+
 template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void rank_gather_kernel(int n, SortTmp tmp,
                                                              PArrays<T> stg, PArrays<T> dst,
@@ -243,21 +250,39 @@ __global__ __launch_bounds__(kBlock) void rank_gather_kernel(int n, SortTmp tmp,
   const int src = tmp.src[p];
   const int idk = tmp.id[p];
   const int2 be = tmp.range[p];
+  const int cell = stg.cell[src];
+  T off[D], vel[D], acc[D];
+  T rho = T(0), mass = T(0), h = T(0);
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    off[d] = stg.off[d * n + src];
+    vel[d] = dst.vel ? stg.vel[d * n + src] : T(0);
+    acc[d] = dst.acc ? stg.acc[d * n + src] : T(0);
+  }
+  if (dst.rho) rho = stg.rho[src];
+  if (dst.mass) mass = stg.mass[src];
+  if (dst.h) h = stg.h[src];
   int rank = 0;
-  for (int q = be.x; q < be.y; ++q) rank += tmp.id[q] < idk ? 1 : 0;
+  for (int q = be.x; q < be.y; q += kRankBatch) {
+    int ids[kRankBatch];
+#pragma unroll
+    for (int u = 0; u < kRankBatch; ++u) ids[u] = tmp.id[min(q + u, be.y - 1)];
+#pragma unroll
+    for (int u = 0; u < kRankBatch; ++u) rank += (q + u < be.y && ids[u] < idk) ? 1 : 0;
+  }
   const int to = be.x + rank;
   if (perm) perm[to] = src;
-  dst.cell[to] = stg.cell[src];
+  dst.cell[to] = cell;
   dst.id[to] = idk;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
-    dst.off[d * n + to] = stg.off[d * n + src];
-    if (dst.vel) dst.vel[d * n + to] = stg.vel[d * n + src];
-    if (dst.acc) dst.acc[d * n + to] = stg.acc[d * n + src];
+    dst.off[d * n + to] = off[d];
+    if (dst.vel) dst.vel[d * n + to] = vel[d];
+    if (dst.acc) dst.acc[d * n + to] = acc[d];
   }
-  if (dst.rho) dst.rho[to] = stg.rho[src];
-  if (dst.mass) dst.mass[to] = stg.mass[src];
-  if (dst.h) dst.h[to] = stg.h[src];
+  if (dst.rho) dst.rho[to] = rho;
+  if (dst.mass) dst.mass[to] = mass;
+  if (dst.h) dst.h[to] = h;
 }
 
 template <typename T>
