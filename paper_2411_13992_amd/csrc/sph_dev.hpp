@@ -192,6 +192,46 @@ __device__ __forceinline__ void for_each_candidate(const Grid& g, const Coeffs<T
   }
 }
 
+// The same walk with the candidates of a cell taken B at a time per lane:
+// load(j) reads what the body needs of candidate j (through buffer resources,
+// so any j is safe: past a component's end a read returns 0), the B loads of
+// a batch are issued together, then body(values, j, shift, live) runs for
+// each in order, live = false for the batch's slots past the cell's end.  The
+// visiting order and the bodies run with live = true are those of
+// for_each_candidate, so sums are bit-identical to it.
+template <int D, int G, int B, typename T, typename Load, typename Body>
+__device__ __forceinline__ void for_each_candidate_batched(const Grid& g, const Coeffs<T>& k,
+                                                           int cell, const int* __restrict__ cs,
+                                                           int sub, Load&& load, Body&& body) {
+  int c[3];
+  decode_cell<D>(g, cell, c);
+  constexpr int zlo = (D == 3) ? -1 : 0;
+  constexpr int zhi = (D == 3) ? 1 : 0;
+#pragma unroll
+  for (int dz = zlo; dz <= zhi; ++dz) {
+    const int z = (D == 3) ? wrap_index(c[2] + dz, g.nc[2]) : 0;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int y = wrap_index(c[1] + dy, g.nc[1]);
+      const int row = g.nc[0] * (y + g.nc[1] * z);
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int cc = row + wrap_index(c[0] + dx, g.nc[0]);
+        const int b = cs[cc];
+        const int e = cs[cc + 1];
+        const T shift[3] = {T(dx) * k.L[0], T(dy) * k.L[1], T(dz) * k.L[2]};
+        for (int j0 = b + sub; j0 < e; j0 += B * G) {
+          decltype(load(0)) v[B];
+#pragma unroll
+          for (int u = 0; u < B; ++u) v[u] = load(j0 + u * G);
+#pragma unroll
+          for (int u = 0; u < B; ++u) body(v[u], j0 + u * G, shift, j0 + u * G < e);
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- lane moves
 // DPP (data-parallel primitive) moves: a lane reads a register of another
 // lane in its row of 16 with one VALU instruction per 32-bit half, instead of

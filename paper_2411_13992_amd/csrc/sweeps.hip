@@ -22,6 +22,13 @@
 namespace sph {
 
 // ------------------------------------------------------------------ density
+// Candidates per lane and batch (their loads issued together): 4 for the
+// FP32 sweeps with many candidates per lane and cell (3-D, or cells sized by
+// the largest h), 1 (the plain walk) otherwise, where the batch's unused
+// slots cost more than the overlap gains.
+template <int D, typename T, bool VAR>
+constexpr int density_batch() { return (sizeof(T) == 4 && (D == 3 || VAR)) ? 4 : 1; }
+
 template <int D, typename T, bool VAR, int G>
 __global__ __launch_bounds__(kBlock) void density_kernel(
     Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
@@ -46,27 +53,39 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
       if constexpr (VAR) acc.init(mass[i] * wendland_alpha<D>(frcp(hi)));
       else acc.init(T(1));
     }
-    for_each_candidate<D, G>(g, k, cell[i], cs, sub, [&](int j, const T* sh) {
-      T r2 = T(0);
+    struct Cand {
+      T o[D], m, h;
+    };
+    auto load = [&](int j) {
+      Cand x;
 #pragma unroll
-      for (int d = 0; d < D; ++d) {
-        T rv = (oi[d] - offc(d, j)) - sh[d];
-        r2 = tfma(rv, rv, r2);
-      }
-      if constexpr (VAR) {
-        const T sup = hi + hc(0, j);
-        if (r2 < sup * sup && j != i) {
-          const T inv = frcp(T(0.5) * sup);
-          acc.add(mc(0, j) * wendland_alpha<D>(inv) * wendland_shape(fsqrt(r2) * inv));
-          ++cnt;
-        }
-      } else {
-        if (r2 < k.sup2 && j != i) {
-          acc.add(wendland_shape(fsqrt(r2) * k.inv_h));
-          ++cnt;
-        }
-      }
-    });
+      for (int d = 0; d < D; ++d) x.o[d] = offc(d, j);
+      x.m = VAR ? mc(0, j) : T(0);
+      x.h = VAR ? hc(0, j) : T(0);
+      return x;
+    };
+    for_each_candidate_batched<D, G, density_batch<D, T, VAR>()>(
+        g, k, cell[i], cs, sub, load, [&](const Cand& cj, int j, const T* sh, bool live) {
+          T r2 = T(0);
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            T rv = (oi[d] - cj.o[d]) - sh[d];
+            r2 = tfma(rv, rv, r2);
+          }
+          if constexpr (VAR) {
+            const T sup = hi + cj.h;
+            if (live && r2 < sup * sup && j != i) {
+              const T inv = frcp(T(0.5) * sup);
+              acc.add(cj.m * wendland_alpha<D>(inv) * wendland_shape(fsqrt(r2) * inv));
+              ++cnt;
+            }
+          } else {
+            if (live && r2 < k.sup2 && j != i) {
+              acc.add(wendland_shape(fsqrt(r2) * k.inv_h));
+              ++cnt;
+            }
+          }
+        });
   }
   const T sum = group_sum<G>(acc);
   cnt = group_sum_int<G>(cnt);
