@@ -199,23 +199,26 @@ __global__ __launch_bounds__(kBlock) void density_vjp_kernel(
     const T hi = VAR ? hh[i] : k.h;
     const T mi = VAR ? mass[i] : k.mass;
     const T pbi = rho_bar[i];
-    for_each_candidate<D, G>(g, k, cell[i], cs, sub, [&](int j, const T* sh) {
-      T r[3];
-      T r2 = T(0);
+    auto load = [&](int j) { return candidate_of<D, T, VAR>(offc, hc, k, j); };
+    for_each_candidate_batched<D, G, candidate_batch<D, T, VAR>()>(
+        g, k, cell[i], cs, sub, load, [&](const Candidate<D, T>& cj, int j, const T* sh,
+                                          bool live) {
+          T r[3];
+          T r2 = T(0);
 #pragma unroll
-      for (int d = 0; d < D; ++d) {
-        r[d] = (oi[d] - offc(d, j)) - sh[d];
-        r2 = tfma(r[d], r[d], r2);
-      }
-      if (j == i) return;
-      PairKernel<D, T> pk;
-      T inv_r;
-      if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? hc(0, j) : k.h, pk, inv_r)) return;
-      const T mj = VAR ? mc(0, j) : k.mass;
-      const T c = (pbi * mj + rbarc(0, j) * mi) * pk.F;
+          for (int d = 0; d < D; ++d) {
+            r[d] = (oi[d] - cj.o[d]) - sh[d];
+            r2 = tfma(r[d], r[d], r2);
+          }
+          if (!live || j == i) return;
+          PairKernel<D, T> pk;
+          T inv_r;
+          if (!pair_kernel<D, T, VAR>(k, r2, hi, cj.h, pk, inv_r)) return;
+          const T mj = VAR ? mc(0, j) : k.mass;
+          const T c = (pbi * mj + rbarc(0, j) * mi) * pk.F;
 #pragma unroll
-      for (int d = 0; d < D; ++d) acc[d].add(c * r[d]);
-    });
+          for (int d = 0; d < D; ++d) acc[d].add(c * r[d]);
+        });
   }
   T sums[3];
 #pragma unroll
@@ -507,33 +510,36 @@ __global__ __launch_bounds__(kBlock) void tv_vjp_kernel(
     mi = VAR ? mass[i] : k.mass;
     rhoi = rho[i];
     const T Vi = mi / rhoi;
-    for_each_candidate<D, G>(g, k, cell[i], cs, sub, [&](int j, const T* sh) {
-      T r[3];
-      T r2 = T(0);
+    auto load = [&](int j) { return candidate_of<D, T, VAR>(offc, hc, k, j); };
+    for_each_candidate_batched<D, G, candidate_batch<D, T, VAR>()>(
+        g, k, cell[i], cs, sub, load, [&](const Candidate<D, T>& cj, int j, const T* sh,
+                                          bool live) {
+          T r[3];
+          T r2 = T(0);
 #pragma unroll
-      for (int d = 0; d < D; ++d) {
-        r[d] = (oi[d] - offc(d, j)) - sh[d];
-        r2 = tfma(r[d], r[d], r2);
-      }
-      if (j == i) return;
-      PairKernel<D, T> pk;
-      T inv_r;
-      if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? hc(0, j) : k.h, pk, inv_r)) return;
-      const T mj = VAR ? mc(0, j) : k.mass;
-      const T Vj = mj * frcp(rhoc(0, j));
-      T u[3], gj[3];
-      T ur = T(0), gjr = T(0);
+          for (int d = 0; d < D; ++d) {
+            r[d] = (oi[d] - cj.o[d]) - sh[d];
+            r2 = tfma(r[d], r[d], r2);
+          }
+          if (!live || j == i) return;
+          PairKernel<D, T> pk;
+          T inv_r;
+          if (!pair_kernel<D, T, VAR>(k, r2, hi, cj.h, pk, inv_r)) return;
+          const T mj = VAR ? mc(0, j) : k.mass;
+          const T Vj = mj * frcp(rhoc(0, j));
+          T u[3], gj[3];
+          T ur = T(0), gjr = T(0);
 #pragma unroll
-      for (int d = 0; d < D; ++d) {
-        gj[d] = ghatc(d, j);
-        u[d] = Vj * gi[d] - Vi * gj[d];
-        ur = tfma(u[d], r[d], ur);
-        gjr = tfma(gj[d], r[d], gjr);
-      }
+          for (int d = 0; d < D; ++d) {
+            gj[d] = ghatc(d, j);
+            u[d] = Vj * gi[d] - Vi * gj[d];
+            ur = tfma(u[d], r[d], ur);
+            gjr = tfma(gj[d], r[d], gjr);
+          }
 #pragma unroll
-      for (int d = 0; d < D; ++d) acc[d].add(pk.F * u[d] + pk.Fpr * ur * r[d]);
-      pb.add(pk.F * gjr);
-    });
+          for (int d = 0; d < D; ++d) acc[d].add(pk.F * u[d] + pk.Fpr * ur * r[d]);
+          pb.add(pk.F * gjr);
+        });
   }
   T sums[3];
 #pragma unroll

@@ -199,6 +199,30 @@ __device__ __forceinline__ void for_each_candidate(const Grid& g, const Coeffs<T
 // each in order, live = false for the batch's slots past the cell's end.  The
 // visiting order and the bodies run with live = true are those of
 // for_each_candidate, so sums are bit-identical to it.
+// What a candidate test reads of j: its offsets and its h (the uniform h
+// without per-particle resolution).
+template <int D, typename T>
+struct Candidate {
+  T o[D], h;
+};
+template <int D, typename T, bool VAR>
+__device__ __forceinline__ Candidate<D, T> candidate_of(const Cols<T, D>& offc,
+                                                        const Cols<T, 1>& hc,
+                                                        const Coeffs<T>& k, int j) {
+  Candidate<D, T> c;
+#pragma unroll
+  for (int d = 0; d < D; ++d) c.o[d] = offc(d, j);
+  c.h = VAR ? hc(0, j) : k.h;
+  return c;
+}
+
+// Candidates per lane and batch for the sweeps with short pair bodies: 4 in
+// FP32 with many candidates per lane and cell (3-D, or cells sized by the
+// largest h), 1 (the plain walk) otherwise, where a batch's unused slots
+// cost more than the overlap gains.
+template <int D, typename T, bool VAR>
+constexpr int candidate_batch() { return (sizeof(T) == 4 && (D == 3 || VAR)) ? 4 : 1; }
+
 template <int D, int G, int B, typename T, typename Load, typename Body>
 __device__ __forceinline__ void for_each_candidate_batched(const Grid& g, const Coeffs<T>& k,
                                                            int cell, const int* __restrict__ cs,

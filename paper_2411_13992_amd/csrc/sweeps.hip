@@ -22,13 +22,6 @@
 namespace sph {
 
 // ------------------------------------------------------------------ density
-// Candidates per lane and batch (their loads issued together): 4 for the
-// FP32 sweeps with many candidates per lane and cell (3-D, or cells sized by
-// the largest h), 1 (the plain walk) otherwise, where the batch's unused
-// slots cost more than the overlap gains.
-template <int D, typename T, bool VAR>
-constexpr int density_batch() { return (sizeof(T) == 4 && (D == 3 || VAR)) ? 4 : 1; }
-
 template <int D, typename T, bool VAR, int G>
 __global__ __launch_bounds__(kBlock) void density_kernel(
     Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
@@ -64,7 +57,7 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
       x.h = VAR ? hc(0, j) : T(0);
       return x;
     };
-    for_each_candidate_batched<D, G, density_batch<D, T, VAR>()>(
+    for_each_candidate_batched<D, G, candidate_batch<D, T, VAR>()>(
         g, k, cell[i], cs, sub, load, [&](const Cand& cj, int j, const T* sh, bool live) {
           T r2 = T(0);
 #pragma unroll
@@ -129,24 +122,27 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
 #pragma unroll
     for (int d = 0; d < D; ++d) oi[d] = off[d * n + i];
     const T hi = VAR ? hh[i] : k.h;
-    for_each_candidate<D, G>(g, k, cell[i], cs, sub, [&](int j, const T* sh) {
-      T rv[3];
-      T r2 = T(0);
+    auto load = [&](int j) { return candidate_of<D, T, VAR>(offc, hc, k, j); };
+    for_each_candidate_batched<D, G, candidate_batch<D, T, VAR>()>(
+        g, k, cell[i], cs, sub, load, [&](const Candidate<D, T>& cj, int j, const T* sh,
+                                          bool live) {
+          T rv[3];
+          T r2 = T(0);
 #pragma unroll
-      for (int d = 0; d < D; ++d) {
-        rv[d] = (oi[d] - offc(d, j)) - sh[d];
-        r2 = tfma(rv[d], rv[d], r2);
-      }
-      if (j == i) return;
-      const PairH<D, T, VAR> ph = pair_h<D, T, VAR>(k, hi, VAR ? hc(0, j) : T(0));
-      if (!(r2 < ph.sup2)) return;
-      const PairGeo<T> pg = pair_geo(r2);
-      const T t = kernel_t(pg.r, ph.inv_h);
-      const T t3 = t * t * t;
-      const T w = tv_weight<D, T, VAR>(ph, t3, frcp(rhoc(0, j)), VAR ? mc(0, j) : k.mass);
+          for (int d = 0; d < D; ++d) {
+            rv[d] = (oi[d] - cj.o[d]) - sh[d];
+            r2 = tfma(rv[d], rv[d], r2);
+          }
+          if (!live || j == i) return;
+          const PairH<D, T, VAR> ph = pair_h<D, T, VAR>(k, hi, cj.h);
+          if (!(r2 < ph.sup2)) return;
+          const PairGeo<T> pg = pair_geo(r2);
+          const T t = kernel_t(pg.r, ph.inv_h);
+          const T t3 = t * t * t;
+          const T w = tv_weight<D, T, VAR>(ph, t3, frcp(rhoc(0, j)), VAR ? mc(0, j) : k.mass);
 #pragma unroll
-      for (int d = 0; d < D; ++d) acc[d].add(w * rv[d]);
-    });
+          for (int d = 0; d < D; ++d) acc[d].add(w * rv[d]);
+        });
   }
   T gi[3], dri[3];
 #pragma unroll
@@ -426,29 +422,33 @@ __global__ __launch_bounds__(kBlock) void wall_state_kernel(
 #pragma unroll
     for (int d = 0; d < D; ++d) oi[d] = off[d * n + i];
     const T hi = VAR ? hh[i] : k.h;
-    for_each_candidate<D, G>(g, k, cell[i], cs, sub, [&](int j, const T* sh) {
-      T r2 = T(0);
+    auto load = [&](int j) { return candidate_of<D, T, VAR>(offc, hc, k, j); };
+    for_each_candidate_batched<D, G, candidate_batch<D, T, VAR>()>(
+        g, k, cell[i], cs, sub, load, [&](const Candidate<D, T>& cj, int j, const T* sh,
+                                          bool live) {
+          T r2 = T(0);
 #pragma unroll
-      for (int d = 0; d < D; ++d) {
-        const T rv = (oi[d] - offc(d, j)) - sh[d];
-        r2 = tfma(rv, rv, r2);
-      }
-      T w;
-      if constexpr (VAR) {
-        const T sup = hi + hc(0, j);
-        if (!(r2 < sup * sup)) return;
-        const T inv = frcp(T(0.5) * sup);
-        w = wendland_alpha<D>(inv) * wendland_shape(fsqrt(r2) * inv);
-      } else {
-        if (!(r2 < k.sup2)) return;
-        w = wendland_shape(fsqrt(r2) * k.inv_h);   // alpha cancels in the ratios
-      }
-      if (is_wall(k, id[j])) return;               // fluid neighbours only
-      sw.add(w);
-      sp.add(k.c0sq * (rhoc(0, j) - k.rho0) * w);
+          for (int d = 0; d < D; ++d) {
+            const T rv = (oi[d] - cj.o[d]) - sh[d];
+            r2 = tfma(rv, rv, r2);
+          }
+          if (!live) return;
+          T w;
+          if constexpr (VAR) {
+            const T sup = hi + cj.h;
+            if (!(r2 < sup * sup)) return;
+            const T inv = frcp(T(0.5) * sup);
+            w = wendland_alpha<D>(inv) * wendland_shape(fsqrt(r2) * inv);
+          } else {
+            if (!(r2 < k.sup2)) return;
+            w = wendland_shape(fsqrt(r2) * k.inv_h);   // alpha cancels in the ratios
+          }
+          if (is_wall(k, id[j])) return;               // fluid neighbours only
+          sw.add(w);
+          sp.add(k.c0sq * (rhoc(0, j) - k.rho0) * w);
 #pragma unroll
-      for (int d = 0; d < D; ++d) sv[d].add(velc(d, j) * w);
-    });
+          for (int d = 0; d < D; ++d) sv[d].add(velc(d, j) * w);
+        });
   }
   const T S = group_sum<G>(sw);
   const T P = group_sum<G>(sp);
