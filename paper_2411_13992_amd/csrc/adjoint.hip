@@ -95,15 +95,15 @@ __global__ __launch_bounds__(kBlock) void force_vjp_kernel(
     const T pi = k.c0sq * (rhoi - k.rho0);
     const T hi = VAR ? hh[i] : k.h;
     const T mi = VAR ? mass[i] : k.mass;
+    // branch-free, so a batch's loads are not moved behind a test
     auto test = [&](int j, const T* v, const T* sh) -> bool {
-      if (j == i) return false;
       T r2 = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         const T rv = (oi[d] - v[d]) - sh[d];
         r2 = tfma(rv, rv, r2);
       }
-      return r2 < pair_h<D, T, VAR>(k, hi, VAR ? v[D] : T(0)).sup2;
+      return (j != i) & (r2 < pair_h<D, T, VAR>(k, hi, VAR ? v[D] : T(0)).sup2);
     };
     auto body = [&](int j, const T* sh) {
       T r[3];
@@ -154,7 +154,8 @@ __global__ __launch_bounds__(kBlock) void force_vjp_kernel(
       }
       pb.add(-Cc * Bw * inv_rhoi - Cc * (T(0.5) * k.c0sq + T(0.25) * br * k.c0 * du) * rw);
     };
-    for_each_neighbour_listed<D, G, T, NS>(g, k, cell[i], cs, sub, st, nl, srct, test, body);
+    // the plain candidate walk: batching costs this long body's occupancy
+    for_each_neighbour_listed<D, G, T, NS, 1>(g, k, cell[i], cs, sub, st, nl, srct, test, body);
   }
   T rbs[3], vbs[3];
 #pragma unroll

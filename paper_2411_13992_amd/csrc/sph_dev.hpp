@@ -613,9 +613,10 @@ __device__ __forceinline__ int staged_delta(const Grid& g, const Stage<D, T, NS,
 // position stage or from src), and appends the hits to this thread's list in
 // LDS; the body phase then runs body(j, shift) over the list alone, so the
 // wavefront executes the body once per neighbour instead of once per
-// candidate.  The list is flushed after each z-plane of cells (once in 2-D)
-// and whenever it fills.  An entry is j in bits 0-27, dx + 1 in bits 28-29
-// and dy + 1 in bits 30-31.  The visiting order is that of
+// candidate (outside the stage, each lane tests B candidates at a time, their
+// loads issued together).  The list is flushed after each z-plane of cells
+// (once in 2-D) and whenever it fills.  An entry is j in bits 0-27, dx + 1 in
+// bits 28-29 and dy + 1 in bits 30-31.  The visiting order is that of
 // for_each_candidate, so sums over the listed pairs are bit-identical to sums
 // over a plain walk.
 constexpr int kListBits = 28;
@@ -626,8 +627,8 @@ struct NeighbourList {
   unsigned slot[CAP][kBlock];   // [entry][thread]: one bank per thread
 };
 
-template <int D, int G, typename T, int NS, int SCAP, int CAP, typename Src, typename Test,
-          typename Body>
+template <int D, int G, typename T, int NS, int B, int SCAP, int CAP, typename Src,
+          typename Test, typename Body>
 __device__ __forceinline__ void for_each_neighbour_listed(const Grid& g, const Coeffs<T>& k,
                                                           int cell, const int* __restrict__ cs,
                                                           int sub,
@@ -678,12 +679,19 @@ __device__ __forceinline__ void for_each_neighbour_listed(const Grid& g, const C
             }
           }
         } else {
-          for (int j = b + sub; j < e; j += G) {
-            T v[NS];
-            src(j, v);
-            if (test(j, v, shift)) {
-              nl.slot[cnt][tid] = (unsigned)j | code;
-              if (++cnt == CAP) flush();
+          // B candidates per lane at a time, their loads issued together
+          for (int j0 = b + sub; j0 < e; j0 += B * G) {
+            T v[B][NS];
+#pragma unroll
+            for (int u = 0; u < B; ++u) src(j0 + u * G, v[u]);
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+              const int j = j0 + u * G;
+              const bool hit = test(j, v[u], shift);
+              if ((j < e) & hit) {
+                nl.slot[cnt][tid] = (unsigned)j | code;
+                if (++cnt == CAP) flush();
+              }
             }
           }
         }

@@ -233,15 +233,15 @@ __device__ __forceinline__ void forces_impl(
     rhoi = rho[i];
     const T pi = k.c0sq * (rhoi - k.rho0);
     const T hi = VAR ? hh[i] : k.h;
+    // branch-free, so a batch's loads are not moved behind a test
     auto test = [&](int j, const T* v, const T* sh) -> bool {
-      if (j == i) return false;
       T r2 = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         const T rv = (oi[d] - v[d]) - sh[d];
         r2 = tfma(rv, rv, r2);
       }
-      return r2 < pair_h<D, T, VAR>(k, hi, VAR ? v[D] : T(0)).sup2;
+      return (j != i) & (r2 < pair_h<D, T, VAR>(k, hi, VAR ? v[D] : T(0)).sup2);
     };
     auto body = [&](int j, const T* sh) {
       T rv[3];
@@ -280,7 +280,8 @@ __device__ __forceinline__ void forces_impl(
       }
     };
     if (!wall)
-      for_each_neighbour_listed<D, G, T, NS>(g, k, celli, cs, sub, st, nl, srct, test, body);
+      for_each_neighbour_listed<D, G, T, NS, candidate_batch<D, T, VAR>()>(g, k, celli, cs, sub,
+                                                                         st, nl, srct, test, body);
   }
   const T s = T(2) / rhoi;
   bool bad = false;
