@@ -606,6 +606,49 @@ __device__ __forceinline__ int staged_delta(const Grid& g, const Stage<D, T, NS,
   }
 }
 
+// The plain candidate walk reading the candidates' test values from the
+// position stage when every lane's cell of the wavefront is staged, through
+// src otherwise: body(j, v, shift) with v the NS values of j.  Same visiting
+// order as for_each_candidate.
+template <int D, int G, typename T, int NS, int SCAP, typename Src, typename Body>
+__device__ __forceinline__ void for_each_candidate_staged(const Grid& g, const Coeffs<T>& k,
+                                                          int cell, const int* __restrict__ cs,
+                                                          int sub,
+                                                          const Stage<D, T, NS, SCAP>& st,
+                                                          Src&& src, Body&& body) {
+  int c[3];
+  decode_cell<D>(g, cell, c);
+  constexpr int zlo = (D == 3) ? -1 : 0;
+  constexpr int zhi = (D == 3) ? 1 : 0;
+#pragma unroll
+  for (int dz = zlo; dz <= zhi; ++dz) {
+    const int z = (D == 3) ? wrap_index(c[2] + dz, g.nc[2]) : 0;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int y = wrap_index(c[1] + dy, g.nc[1]);
+      const int row = g.nc[0] * (y + g.nc[1] * z);
+      const int r = (dy + 1) + 3 * (dz - zlo);
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int cc = row + wrap_index(c[0] + dx, g.nc[0]);
+        const int b = cs[cc];
+        const int e = cs[cc + 1];
+        const int delta = staged_delta<D>(g, st, r, cc, b);
+        const T shift[3] = {T(dx) * k.L[0], T(dy) * k.L[1], T(dz) * k.L[2]};
+        if (__all(delta != kNotStaged)) {
+          for (int j = b + sub; j < e; j += G) body(j, st.rec[j + delta].w, shift);
+        } else {
+          for (int j = b + sub; j < e; j += G) {
+            T v[NS];
+            src(j, v);
+            body(j, v, shift);
+          }
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- compacted walk
 // Neighbour walk in two phases for sweeps whose pair body is expensive.  The
 // scan phase tests every candidate with test(j, v, shift), v the NS staged

@@ -31,6 +31,16 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
   const int n = g.n;
   const Cols<T, D> offc(off, n);
   const Cols<T, 1> hc(hh, n), mc(mass, n);
+  // candidate-test values: offsets, then h (variable resolution); staged in
+  // LDS for the 2-D FP32 sweeps
+  constexpr int NS = D + (VAR ? 1 : 0);
+  auto srct = [&](int j, T* v) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) v[d] = offc(d, j);
+    if constexpr (VAR) v[D] = hc(0, j);
+  };
+  __shared__ Stage<D, T, NS, StageCap<D, T>::value> st;
+  stage_positions<D, G>(g, cell, cs, st, srct);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   const bool valid = i < n;
@@ -46,39 +56,44 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
       if constexpr (VAR) acc.init(mass[i] * wendland_alpha<D>(frcp(hi)));
       else acc.init(T(1));
     }
-    struct Cand {
-      T o[D], m, h;
-    };
-    auto load = [&](int j) {
-      Cand x;
+    // one candidate j with test values v (offsets, then h_j)
+    auto pair = [&](int j, const T* v, const T* sh, bool live) {
+      T r2 = T(0);
 #pragma unroll
-      for (int d = 0; d < D; ++d) x.o[d] = offc(d, j);
-      x.m = VAR ? mc(0, j) : T(0);
-      x.h = VAR ? hc(0, j) : T(0);
-      return x;
+      for (int d = 0; d < D; ++d) {
+        T rv = (oi[d] - v[d]) - sh[d];
+        r2 = tfma(rv, rv, r2);
+      }
+      if constexpr (VAR) {
+        const T sup = hi + v[D];
+        if (live && r2 < sup * sup && j != i) {
+          const T inv = frcp(T(0.5) * sup);
+          acc.add(mc(0, j) * wendland_alpha<D>(inv) * wendland_shape(fsqrt(r2) * inv));
+          ++cnt;
+        }
+      } else {
+        if (live && r2 < k.sup2 && j != i) {
+          acc.add(wendland_shape(fsqrt(r2) * k.inv_h));
+          ++cnt;
+        }
+      }
     };
-    for_each_candidate_batched<D, G, candidate_batch<D, T, VAR>()>(
-        g, k, cell[i], cs, sub, load, [&](const Cand& cj, int j, const T* sh, bool live) {
-          T r2 = T(0);
-#pragma unroll
-          for (int d = 0; d < D; ++d) {
-            T rv = (oi[d] - cj.o[d]) - sh[d];
-            r2 = tfma(rv, rv, r2);
-          }
-          if constexpr (VAR) {
-            const T sup = hi + cj.h;
-            if (live && r2 < sup * sup && j != i) {
-              const T inv = frcp(T(0.5) * sup);
-              acc.add(cj.m * wendland_alpha<D>(inv) * wendland_shape(fsqrt(r2) * inv));
-              ++cnt;
-            }
-          } else {
-            if (live && r2 < k.sup2 && j != i) {
-              acc.add(wendland_shape(fsqrt(r2) * k.inv_h));
-              ++cnt;
-            }
-          }
-        });
+    if constexpr (StageCap<D, T>::value > 0) {
+      for_each_candidate_staged<D, G>(g, k, cell[i], cs, sub, st, srct,
+                                      [&](int j, const T* v, const T* sh) { pair(j, v, sh, true); });
+    } else {
+      struct Cand {
+        T v[NS];
+      };
+      auto load = [&](int j) {
+        Cand x;
+        srct(j, x.v);
+        return x;
+      };
+      for_each_candidate_batched<D, G, candidate_batch<D, T, VAR>()>(
+          g, k, cell[i], cs, sub, load,
+          [&](const Cand& cj, int j, const T* sh, bool live) { pair(j, cj.v, sh, live); });
+    }
   }
   const T sum = group_sum<G>(acc);
   cnt = group_sum_int<G>(cnt);
