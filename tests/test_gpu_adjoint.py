@@ -48,6 +48,13 @@ def _walled(n, dim, seed):
     return case
 
 
+def _wide(case, h_over_dx):
+    """The same case with a wider support: every lane's neighbour list
+    overflows in the force sweep and its VJP."""
+    case.h = np.full(case.n, h_over_dx * case.dx)
+    return case
+
+
 def _init_cases():
     return {
         "tg2d_jit": cases.taylor_green_2d(24, jitter=0.2, seed=12),
@@ -55,6 +62,8 @@ def _init_cases():
         "varres": cases.variable_resolution_2d(dp_min=1.0 / 60, jitter=0.1, seed=14),
         "cavity": _walled(12, 2, 15),
         "cavity3d": _walled(6, 3, 16),
+        "tg2d_wide": _wide(cases.taylor_green_2d(24, jitter=0.2, seed=17), 3.0),
+        "tg3d_wide": _wide(cases.taylor_green_3d(14, jitter=0.2, seed=18), 2.0),
     }
 
 
