@@ -187,6 +187,16 @@ __global__ __launch_bounds__(kBlock) void density_vjp_kernel(
   const int n = g.n;
   const Cols<T, D> offc(off, n);
   const Cols<T, 1> rbarc(rho_bar, n), hc(hh, n), mc(mass, n);
+  // candidate-test values: offsets, then h (variable resolution); staged in
+  // LDS for the 2-D FP32 sweeps
+  constexpr int NS = D + (VAR ? 1 : 0);
+  auto srct = [&](int j, T* v) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) v[d] = offc(d, j);
+    if constexpr (VAR) v[D] = hc(0, j);
+  };
+  __shared__ Stage<D, T, NS, StageCap<D, T>::value> st;
+  stage_positions<D, G>(g, cell, cs, st, srct);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   const bool valid = i < n;
@@ -200,21 +210,19 @@ __global__ __launch_bounds__(kBlock) void density_vjp_kernel(
     const T hi = VAR ? hh[i] : k.h;
     const T mi = VAR ? mass[i] : k.mass;
     const T pbi = rho_bar[i];
-    auto load = [&](int j) { return candidate_of<D, T, VAR>(offc, hc, k, j); };
-    for_each_candidate_batched<D, G, candidate_batch<D, T, VAR>()>(
-        g, k, cell[i], cs, sub, load, [&](const Candidate<D, T>& cj, int j, const T* sh,
-                                          bool live) {
+    for_each_candidate_values<D, G, T, VAR>(
+        g, k, cell[i], cs, sub, st, srct, [&](int j, const T* v, const T* sh, bool live) {
           T r[3];
           T r2 = T(0);
 #pragma unroll
           for (int d = 0; d < D; ++d) {
-            r[d] = (oi[d] - cj.o[d]) - sh[d];
+            r[d] = (oi[d] - v[d]) - sh[d];
             r2 = tfma(r[d], r[d], r2);
           }
           if (!live || j == i) return;
           PairKernel<D, T> pk;
           T inv_r;
-          if (!pair_kernel<D, T, VAR>(k, r2, hi, cj.h, pk, inv_r)) return;
+          if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? v[D] : k.h, pk, inv_r)) return;
           const T mj = VAR ? mc(0, j) : k.mass;
           const T c = (pbi * mj + rbarc(0, j) * mi) * pk.F;
 #pragma unroll
@@ -492,6 +500,16 @@ __global__ __launch_bounds__(kBlock) void tv_vjp_kernel(
   const int n = g.n;
   const Cols<T, D> offc(off, n), ghatc(ghat, n);
   const Cols<T, 1> rhoc(rho, n), hc(hh, n), mc(mass, n);
+  // candidate-test values: offsets, then h (variable resolution); staged in
+  // LDS for the 2-D FP32 sweeps
+  constexpr int NS = D + (VAR ? 1 : 0);
+  auto srct = [&](int j, T* v) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) v[d] = offc(d, j);
+    if constexpr (VAR) v[D] = hc(0, j);
+  };
+  __shared__ Stage<D, T, NS, StageCap<D, T>::value> st;
+  stage_positions<D, G>(g, cell, cs, st, srct);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   const bool valid = i < n;
@@ -511,21 +529,19 @@ __global__ __launch_bounds__(kBlock) void tv_vjp_kernel(
     mi = VAR ? mass[i] : k.mass;
     rhoi = rho[i];
     const T Vi = mi / rhoi;
-    auto load = [&](int j) { return candidate_of<D, T, VAR>(offc, hc, k, j); };
-    for_each_candidate_batched<D, G, candidate_batch<D, T, VAR>()>(
-        g, k, cell[i], cs, sub, load, [&](const Candidate<D, T>& cj, int j, const T* sh,
-                                          bool live) {
+    for_each_candidate_values<D, G, T, VAR>(
+        g, k, cell[i], cs, sub, st, srct, [&](int j, const T* v, const T* sh, bool live) {
           T r[3];
           T r2 = T(0);
 #pragma unroll
           for (int d = 0; d < D; ++d) {
-            r[d] = (oi[d] - cj.o[d]) - sh[d];
+            r[d] = (oi[d] - v[d]) - sh[d];
             r2 = tfma(r[d], r[d], r2);
           }
           if (!live || j == i) return;
           PairKernel<D, T> pk;
           T inv_r;
-          if (!pair_kernel<D, T, VAR>(k, r2, hi, cj.h, pk, inv_r)) return;
+          if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? v[D] : k.h, pk, inv_r)) return;
           const T mj = VAR ? mc(0, j) : k.mass;
           const T Vj = mj * frcp(rhoc(0, j));
           T u[3], gj[3];

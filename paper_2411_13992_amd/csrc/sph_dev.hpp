@@ -649,6 +649,35 @@ __device__ __forceinline__ void for_each_candidate_staged(const Grid& g, const C
   }
 }
 
+// The candidate walk for short pair bodies in the form that suits the
+// configuration: from the position stage when there is one (2-D FP32),
+// candidates in batches of candidate_batch() otherwise.  pair(j, v, shift,
+// live) gets the NS test values v of j (offsets, then h with per-particle
+// resolution) read by src(j, v); live is false for a batch's unused slots.
+template <int D, int G, typename T, bool VAR, int NS, int SCAP, typename Src, typename Pair>
+__device__ __forceinline__ void for_each_candidate_values(const Grid& g, const Coeffs<T>& k,
+                                                          int cell, const int* __restrict__ cs,
+                                                          int sub,
+                                                          const Stage<D, T, NS, SCAP>& st,
+                                                          Src&& src, Pair&& pair) {
+  if constexpr (SCAP > 0) {
+    for_each_candidate_staged<D, G>(g, k, cell, cs, sub, st, src,
+                                    [&](int j, const T* v, const T* sh) { pair(j, v, sh, true); });
+  } else {
+    struct Vals {
+      T v[NS];
+    };
+    auto load = [&](int j) {
+      Vals x;
+      src(j, x.v);
+      return x;
+    };
+    for_each_candidate_batched<D, G, candidate_batch<D, T, VAR>()>(
+        g, k, cell, cs, sub, load,
+        [&](const Vals& x, int j, const T* sh, bool live) { pair(j, x.v, sh, live); });
+  }
+}
+
 // ---------------------------------------------------------------- compacted walk
 // Neighbour walk in two phases for sweeps whose pair body is expensive.  The
 // scan phase tests every candidate with test(j, v, shift), v the NS staged

@@ -78,22 +78,7 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
         }
       }
     };
-    if constexpr (StageCap<D, T>::value > 0) {
-      for_each_candidate_staged<D, G>(g, k, cell[i], cs, sub, st, srct,
-                                      [&](int j, const T* v, const T* sh) { pair(j, v, sh, true); });
-    } else {
-      struct Cand {
-        T v[NS];
-      };
-      auto load = [&](int j) {
-        Cand x;
-        srct(j, x.v);
-        return x;
-      };
-      for_each_candidate_batched<D, G, candidate_batch<D, T, VAR>()>(
-          g, k, cell[i], cs, sub, load,
-          [&](const Cand& cj, int j, const T* sh, bool live) { pair(j, cj.v, sh, live); });
-    }
+    for_each_candidate_values<D, G, T, VAR>(g, k, cell[i], cs, sub, st, srct, pair);
   }
   const T sum = group_sum<G>(acc);
   cnt = group_sum_int<G>(cnt);
