@@ -192,13 +192,6 @@ __device__ __forceinline__ void for_each_candidate(const Grid& g, const Coeffs<T
   }
 }
 
-// The same walk with the candidates of a cell taken B at a time per lane:
-// load(j) reads what the body needs of candidate j (through buffer resources,
-// so any j is safe: past a component's end a read returns 0), the B loads of
-// a batch are issued together, then body(values, j, shift, live) runs for
-// each in order, live = false for the batch's slots past the cell's end.  The
-// visiting order and the bodies run with live = true are those of
-// for_each_candidate, so sums are bit-identical to it.
 // What a candidate test reads of j: its offsets and its h (the uniform h
 // without per-particle resolution).
 template <int D, typename T>
@@ -223,6 +216,13 @@ __device__ __forceinline__ Candidate<D, T> candidate_of(const Cols<T, D>& offc,
 template <int D, typename T, bool VAR>
 constexpr int candidate_batch() { return (sizeof(T) == 4 && (D == 3 || VAR)) ? 4 : 1; }
 
+// The same walk with the candidates of a cell taken B at a time per lane:
+// load(j) reads what the body needs of candidate j (through buffer resources,
+// so any j is safe: past a component's end a read returns 0), the B loads of
+// a batch are issued together, then body(values, j, shift, live) runs for
+// each in order, live = false for the batch's slots past the cell's end.  The
+// visiting order and the bodies run with live = true are those of
+// for_each_candidate, so sums are bit-identical to it.
 template <int D, int G, int B, typename T, typename Load, typename Body>
 __device__ __forceinline__ void for_each_candidate_batched(const Grid& g, const Coeffs<T>& k,
                                                            int cell, const int* __restrict__ cs,
