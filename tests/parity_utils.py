@@ -9,10 +9,9 @@ particles.  Tolerances (stated per field, max-norm):
 * density: / rho0
 * sweep outputs with identical inputs (g, dr, a): / the particle's own sum of
   absolute pair terms (the summation-error scale of the sweep)
-* accelerations after a whole step: / (c0^2 / h), the acceleration a pressure
-  of rho0 c0^2 across one smoothing length produces; this carries the FP32
-  rounding of rho (~1e-7 rho0) through the EOS, which the pair-term scale of
-  a step's own sums does not cover
+* accelerations after a whole step: / the particle's sum of absolute pair
+  terms, with the oracle's forces evaluated at the GPU's own state after the
+  step (step_acc_error), so the EOS does not amplify the density's rounding
 * FP32: 1e-5, FP64: 1e-12.
 """
 from __future__ import annotations
@@ -93,3 +92,23 @@ def min_image(a, b, box):
     d = a - b
     bx = np.asarray(box, dtype=np.float64).reshape(-1, 1)
     return d - bx * np.round(d / bx)
+
+
+def step_acc_error(out, case, mass, h, mask=None):
+    """Acceleration error of a GPU step on the summation-error scale: the
+    oracle's forces (Eq. 2-7) evaluated at the GPU's own state after the step
+    (positions, the density rho^{n+1} and, for the fluid, the half-step
+    velocity v' = v^{n+1} - dt/2 a^{n+1}; walls keep their state velocity),
+    against the GPU's a^{n+1}, per particle / sum_j |pair term|.  Evaluating
+    at the GPU's density keeps the EOS from amplifying the density's own
+    rounding (c0^2 delta rho) into the comparison.  Fluid particles only."""
+    nf = case.n - getattr(case, "n_wall", 0)
+    vhalf = out["vel"].copy()
+    vhalf[:, :nf] -= 0.5 * case.dt * out["acc"][:, :nf]
+    nb = oracle.neighbors(out["pos"], h, case.box)
+    acc, scale = oracle.forces(out["pos"], vhalf, mass, out["rho"], h, case.box, nb,
+                               case.rho0, case.c0, case.eta, case.riemann_eta)
+    err = np.abs(out["acc"][:, :nf] - acc[:, :nf]) / scale[:nf]
+    if mask is not None:
+        err = err[:, mask[:nf]]
+    return float(err.max()) if err.size else 0.0
