@@ -55,21 +55,66 @@ WORKLOADS = {
                     "with FP64 reductions",
 }
 
-# Algorithmic work per interacting pair of the force sweep: the operations of
-# the pair formula (Eq. 2, 3b, 5-7) counted one per add, multiply, min/max,
-# reciprocal or reciprocal square root and two per FMA, without the summation
-# compensation: 50 in 2-D, 62 in 3-D.  Algorithmic bytes per particle: the
-# compulsory reads (offsets D, velocity D, density 1, plus mass and h with
-# per-particle resolution) and writes (acceleration D), once each.
-FORCE_FLOPS_PER_PAIR = {2: 50, 3: 62}
+# Algorithmic work per interacting pair of the force sweep, counted from the
+# oracle's pair formula (Eq. 2, 3b, 5-7), one flop per add, subtract,
+# multiply, divide/reciprocal, square root, min or max (an FMA counts two);
+# uniform resolution, constants folded, no summation compensation, no
+# candidate test (the neighbour search is overhead, not the method's work).
+# Items: pair vector r_ij, r^2, r, q = r/h, 1 - q/2, F = W'/r, p_j (EOS),
+# U_l - U_r (1/r, velocity difference, axis, dot), the dissipation limiter
+# beta (Eq. 6), mean density, P* (Eq. 5), 2 m_j / (rho_i rho_j), and per
+# component the pressure and viscous terms and the accumulation.
+def force_flops_per_pair(dim: int) -> int:
+    d = dim
+    items = [d, 2 * d - 1, 1, 1, 2, 3, 2, 1 + d + d + (2 * d - 1), 4, 2, 6, 3, 4 + 4 * d]
+    return sum(items)
+
+
+FORCE_FLOPS_PER_PAIR = {2: force_flops_per_pair(2), 3: force_flops_per_pair(3)}   # 49, 60
+
+# Compulsory HBM bytes per particle of each kernel of a 2-D FP32 step (each
+# kernel reads its per-particle inputs once and writes its outputs once) and
+# VALU lane-operations per interacting pair (FMA = 1): the step's attainable
+# time is sum_k max(bytes_k N / HBM, ops_k P / VALU).
+STEP_KERNELS_2D_F32 = {
+    #  kernel: (bytes per particle, lane-ops per pair)
+    "cell build (keys, scatter, in-cell order, permute)": (88, 0),
+    "transport correction sweep": (20, 22),
+    "density sweep": (12, 20),
+    "force sweep": (28, 47),
+    "kick + drift + rebin": (56, 0),
+    "kick + FP64 reductions": (32, 0),
+}
+HBM_PEAK = 8e12                       # MI355X HBM3E, bytes/s
+# Published vector FP32 peak of MI355X (packed FP32): 157.3 TFLOP/s.  This
+# library is built without packed FP32 math, so the peak it can attain is
+# half of it: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2 flops per FMA.
+VALU_FP32_PEAK_TFLOPS = 157.3
+VALU_ATTAINABLE_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12       # 78.6
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9                           # 39.3e12 lane-ops/s
 
 
 def force_bytes_per_particle(dim: int, dtype: str, per_particle: bool) -> int:
+    """Compulsory bytes of the force sweep per particle: reads of offsets D,
+    velocity D and density 1 (plus mass and h with per-particle resolution)
+    and the write of the acceleration D, once each."""
     words = 3 * dim + 1 + (2 if per_particle else 0)
     return words * (8 if dtype == "f64" else 4)
-# Non-packed vector FP32 peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
-# x 2 flops per FMA (packed FP32 math is not used).
-VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+
+
+def step_bounds(n: int, pairs: float, t_step: float) -> dict:
+    """Whole-step fractions for the 2-D FP32 step: algorithmic HBM bytes over
+    time against the HBM peak, and the attainable step time (per kernel the
+    larger of its byte and its VALU time, summed) over the measured time."""
+    t_bound = 0.0
+    nbytes = 0
+    for b, ops in STEP_KERNELS_2D_F32.values():
+        nbytes += b * n
+        t_bound += max(b * n / HBM_PEAK, ops * pairs / VALU_LANE_OPS)
+    return {"algorithmic_bytes": nbytes, "hbm_frac": nbytes / t_step / HBM_PEAK,
+            "attainable_us": t_bound * 1e6, "attainable_frac": t_bound / t_step}
+
+
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "forces_kernel_tg2d_400_f32_pmc.md")
 PMC_COPY_BYTES = 64 << 20
 KERNEL_SOURCES = os.path.join(ROOT, "paper_2411_13992_amd", "csrc")
@@ -114,12 +159,14 @@ def time_adjoint(sim, steps, every):
     torch.cuda.synchronize()
     t_fwd = (time.perf_counter() - t0) / steps
     vbar = v0.clone()
+    final_id = sim.id.clone()
     tapes = torch.empty((every, sim.tape_bytes()), dtype=torch.uint8, device=sim.device)
-    backward_run(sim, ckpts, steps, every, vbar, tapes)   # warm
+    backward_run(sim, ckpts, steps, every, vbar, final_id, tapes)   # warm
     ckpts = forward_run(sim, v0, xi, steps, every)
+    final_id = sim.id.clone()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    backward_run(sim, ckpts, steps, every, vbar, tapes)
+    backward_run(sim, ckpts, steps, every, vbar, final_id, tapes)
     torch.cuda.synchronize()
     t_bwd = (time.perf_counter() - t0) / steps
     return t_fwd, t_bwd
@@ -145,10 +192,14 @@ def kernel_roofline(sim, pairs, dtype, reps=200, use_pmc=True):
         "unit": "TFLOP/s",
         "frac": achieved / VALU_FP32_PEAK_TFLOPS,
         "traffic": traffic,
+        "attainable_peak": VALU_ATTAINABLE_TFLOPS,
+        "attainable_frac": achieved / VALU_ATTAINABLE_TFLOPS,
+        "attainable_peak_note": "non-packed FP32: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2",
         "avg_launch_us": t * 1e6,
+        "flops_per_pair": FORCE_FLOPS_PER_PAIR[sim.dim],
         "algorithmic_flops_per_launch": flops,
         "algorithmic_bytes_per_launch": bytes_,
-        "hbm_frac": bytes_ / t / 8e12,
+        "hbm_frac": bytes_ / t / HBM_PEAK,
     }
 
 
@@ -187,25 +238,77 @@ def source_digest():
     return h.hexdigest()
 
 
-def cpu_baseline(case, budget_s=12.0):
-    """The FP64 oracle, as it stands, on the same workload: whole steps until
-    the time budget is used (at least one)."""
+def decay_accuracy(case, nsteps):
+    """FP32 and FP64 runs of nsteps steps from the identical start (the FP32
+    state widened exactly), kinetic energy against the analytic Taylor-Green
+    decay KE(0) exp(-16 pi^2 t / Re) of Eq. (17)."""
+    import copy
+    import math
+    import numpy as np
+    from paper_2411_13992_amd import Simulation
+    s32 = Simulation.from_case(case, dtype="f32")
+    st = s32.export()
+    start = copy.copy(case)
+    start.pos, start.vel = st["pos"], st["vel"]
+    s64 = Simulation.from_case(start, dtype="f64")
+    ke0 = float(0.5 * np.sum(case.mass * np.sum(st["vel"] ** 2, axis=0)))
+    s32.run(nsteps, diag=False)
+    s64.run(nsteps, diag=False)
+    ke32 = s32.diagnostics(fresh=True)["ke"]
+    ke64 = s64.diagnostics(fresh=True)["ke"]
+    t = nsteps * case.dt
+    exact = ke0 * math.exp(-16 * math.pi ** 2 * t / case.extra.get("re", 100.0))
+    return {"steps": nsteps, "t": t, "ke_vs_analytic_f32": ke32 / exact - 1.0,
+            "ke_vs_analytic_f64": ke64 / exact - 1.0, "ke_f32_vs_f64": ke32 / ke64 - 1.0}
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_median_step(case, threads, warm, reps):
+    """Median wall time of `reps` whole oracle steps after `warm` untimed
+    ones, on `threads` OpenMP threads, and the mean ordered pair count."""
     import oracle
-    threads = oracle.get_threads()
+    oracle.set_threads(threads)
     st = oracle.State(case)
-    t0 = time.perf_counter()
-    steps, pairs = 0, 0.0
-    while True:
+    for _ in range(warm):
+        st.step()
+    times, pairs = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
         d = st.step()
-        steps += 1
-        pairs += d["npairs"]
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": threads,
+        times.append(time.perf_counter() - t0)
+        pairs.append(d["npairs"])
+    times.sort()
+    return times[len(times) // 2], sum(pairs) / len(pairs)
+
+
+def cpu_baseline(case):
+    """The FP64 oracle, as it stands, on the same workload: the median time of
+    a whole step after two warm-up steps, once on every host thread (the
+    reported value) and once single-threaded; about 10-20 s in all."""
+    import oracle
+    threads = os.cpu_count() or 1
+    oracle.set_threads(threads)
+    threads = oracle.get_threads()
+    t_all, pairs = _oracle_median_step(case, threads, 2, 20)
+    t_one, _ = _oracle_median_step(case, 1, 2, 5)
+    oracle.set_threads(threads)
+    return {"value": pairs / t_all, "unit": "pair-interactions/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{steps} whole FP64 steps of the {case.n}-particle workload "
-                      f"(neighbour search by cells, {dt:.1f} s)"}
+            "sample": f"median of 20 whole FP64 steps (after 2 warm-up steps) of the "
+                      f"{case.n}-particle workload on {threads} threads, neighbour search by "
+                      f"cells; single-threaded: median of 5 steps",
+            "s_per_step": t_all,
+            "single_thread": {"value": pairs / t_one, "s_per_step": t_one, "cores": 1},
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
 
 
 def main():
@@ -282,6 +385,10 @@ def main():
         "roofline": roof,
         "device_flags": flags32,
     }
+    if case.dim == 2 and not case.n_wall and case.uniform:
+        out["step_roofline"] = step_bounds(case.n, pairs, t32)
+    if args.workload == WORKLOAD:
+        out["accuracy"] = decay_accuracy(case, case.steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
     else:
