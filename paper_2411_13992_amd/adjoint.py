@@ -66,11 +66,16 @@ def forward_run(sim: Simulation, v0: torch.Tensor, xi: float, nsteps: int, every
 
 
 def backward_run(sim: Simulation, ckpts: list, nsteps: int, every: int,
-                 v_bar_final: torch.Tensor, tapes: torch.Tensor | None = None):
-    """Reverse sweep.  v_bar_final is id-ordered; sim holds the final state.
-    Returns (v0_bar id-ordered, r0_bar id-ordered, xi_bar float)."""
+                 v_bar_final: torch.Tensor, final_id: torch.Tensor,
+                 tapes: torch.Tensor | None = None):
+    """Reverse sweep.  v_bar_final is id-ordered; final_id is the sorted id
+    order of the rollout's final state (sim.id right after forward_run), so the
+    simulation may have been stepped or restored since.  The simulation's state
+    is the same on return as on entry.  Returns (v0_bar id-ordered, r0_bar
+    id-ordered, xi_bar float)."""
+    entry = sim.snapshot()
     adj = Adjoint(sim)
-    adj.v.copy_(v_bar_final.to(sim.device, sim.T)[:, sim.id.long()])
+    adj.v.copy_(v_bar_final.to(sim.device, sim.T)[:, final_id.long()])
     xi_bar = torch.zeros(1, dtype=torch.float64, device=sim.device)
     if tapes is None:
         tapes = torch.empty((every, sim.tape_bytes()), dtype=torch.uint8, device=sim.device)
@@ -89,6 +94,7 @@ def backward_run(sim: Simulation, ckpts: list, nsteps: int, every: int,
     v0_bar[:, ids] = adj.v
     r0_bar = torch.empty_like(adj.r)
     r0_bar[:, ids] = adj.r
+    sim.restore(entry)
     return v0_bar, r0_bar, float(xi_bar.item())
 
 
@@ -97,6 +103,7 @@ class _Rollout(torch.autograd.Function):
     def forward(ctx, v0, xi, sim, nsteps, every):
         ckpts = forward_run(sim, v0.detach(), float(xi), nsteps, every)
         ctx.sim, ctx.nsteps, ctx.every, ctx.ckpts = sim, nsteps, every, ckpts
+        ctx.final_id = sim.id.clone()
         ctx.xi = float(xi)
         ctx.v0_dtype, ctx.xi_dtype = v0.dtype, xi.dtype
         return sim.velocity_by_id().to(v0.dtype)
@@ -104,8 +111,11 @@ class _Rollout(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_v):
         sim = ctx.sim
+        xi_now = sim.params.xi
         sim.set_xi(ctx.xi)
-        v0_bar, _, xi_bar = backward_run(sim, ctx.ckpts, ctx.nsteps, ctx.every, grad_v)
+        v0_bar, _, xi_bar = backward_run(sim, ctx.ckpts, ctx.nsteps, ctx.every, grad_v,
+                                         ctx.final_id)
+        sim.set_xi(xi_now)
         xi_grad = torch.tensor(xi_bar, dtype=ctx.xi_dtype, device=grad_v.device)
         return v0_bar.to(ctx.v0_dtype), xi_grad, None, None, None
 

@@ -324,3 +324,39 @@ def test_adjoint_workload_fp32_vs_fp64_fd(jitter):
     print(f"jitter {jitter}: dKE/dxi adjoint {gxi:.6e} fd {fd:.6e}; "
           f"directional {derivs[0]:.6e} fd {fds[0]:.6e}")
     assert abs(gxi - fd) <= 1e-4 * max(abs(fd), 1e-3 * scale)
+
+
+def test_rollout_backward_after_the_simulation_moved_on():
+    """The rollout's backward pass keeps its own record of the final particle
+    order: driving the simulation elsewhere between rollout() and backward()
+    (another rollout from other velocities, then more steps) changes nothing
+    in the gradients, which equal those of an undisturbed rollout bit for bit;
+    a second backward through a retained graph adds the same gradients again;
+    and backward leaves the simulation's state as it found it."""
+    import torch
+    from paper_2411_13992_amd.adjoint import forward_run, kinetic_energy, rollout
+    case = cases.taylor_green_2d(16, jitter=0.15, seed=31, vel_perturb=0.01)
+
+    def grads(disturb):
+        sim = _sim(case, "f32")
+        v0 = torch.tensor(case.vel, dtype=torch.float64, device="cuda", requires_grad=True)
+        xi = torch.tensor(case.xi, dtype=torch.float64, device="cuda", requires_grad=True)
+        loss = kinetic_energy(sim, rollout(sim, v0, xi, 12, every=5))
+        if disturb:
+            forward_run(sim, torch.flip(v0.detach(), dims=[1]), -0.1, 7, None)
+            sim.run(9, diag=False)
+            before = sim.snapshot()
+        loss.backward(retain_graph=disturb)
+        if disturb:
+            for key in sim._STATE:
+                assert torch.equal(getattr(sim, key), before[key]), key
+            assert sim.step_index == before["step_index"]
+            g1 = (v0.grad.clone(), xi.grad.clone())
+            loss.backward()
+            assert torch.equal(v0.grad, 2 * g1[0]) and torch.equal(xi.grad, 2 * g1[1])
+        return v0.grad.clone(), xi.grad.clone()
+
+    clean = grads(False)
+    moved = grads(True)
+    assert torch.equal(moved[0], 2 * clean[0]) and torch.equal(moved[1], 2 * clean[1])
+    assert float(clean[0].abs().max()) > 0.0 and float(clean[1].abs()) > 0.0
