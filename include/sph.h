@@ -25,7 +25,8 @@
  *    the boundary; sph_status_string() names the status;
  *  - every array pointer is a DEVICE pointer owned by the caller; the library
  *    allocates no device memory and keeps no state between calls; scratch
- *    memory is the caller's workspace of sph_workspace_size() bytes;
+ *    memory is the caller's workspace of sph_workspace_size() bytes (the one
+ *    exception, sph_kdk_run_static, takes it from a static device array);
  *  - every call is asynchronous on `stream` (a hipStream_t, NULL = the null
  *    stream) and never synchronises, except sph_get_flags();
  *  - argument errors are detected on the host and returned at once, before
@@ -59,6 +60,13 @@ extern "C" {
                                  fewer than 3 cells on an axis                */
 #define SPH_E_NONFINITE   -5  /* non-finite parameter                         */
 #define SPH_E_UNSUPPORTED -6  /* dimension or dtype not supported             */
+#define SPH_E_TOO_LARGE   -7  /* the run needs more workspace than the static
+                                 scratch of sph_kdk_run_static holds          */
+
+/* Size of the device scratch array behind sph_kdk_run_static (64 MiB per
+ * device): enough for about 570,000 particles in 2-D FP32, 340,000 in 2-D
+ * FP64 and 430,000 in 3-D FP32 (sph_workspace_size bytes per run). */
+#define SPH_STATIC_SCRATCH_BYTES (64u << 20)
 
 /* device flag bits (sph_get_flags) */
 #define SPH_FLAG_NONFINITE  1u  /* a velocity, acceleration or density is NaN/Inf */
@@ -253,6 +261,26 @@ int32_t sph_kdk_run(const sph_params *p, sph_particles *parts, int32_t *cell_sta
                     int64_t step_index, int64_t nsteps, void *ws, size_t ws_bytes,
                     void *tapes, double *diag, void *stream);
 
+/* sph_kdk_run without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same kernels and arithmetic
+ * (bit-identical results), with the run's scratch taken from a static device
+ * array of SPH_STATIC_SCRATCH_BYTES that the library holds on every device it
+ * runs on until the process ends.  The call allocates nothing; the caller
+ * still owns and passes every input and output.  Runs whose
+ * sph_workspace_size exceeds SPH_STATIC_SCRATCH_BYTES return SPH_E_TOO_LARGE
+ * before anything is enqueued.  The array belongs to the device current at
+ * the call (which must be the stream's device) and is shared by every call
+ * on that device: calls that overlap on one device (concurrent streams or
+ * host threads) race and must be serialised by the caller.
+ * flags (optional, device, one uint32_t owned by the caller) is the device
+ * flag word of the run: bits are ORed in, never cleared, and read and clear
+ * with sph_get_flags(flags, stream, &host) / sph_clear_flags(flags, stream);
+ * with flags == NULL the run's flags are not reported. */
+int32_t sph_kdk_run_static(const sph_params *p, sph_particles *parts, int32_t *cell_start,
+                           int64_t step_index, int64_t nsteps, void *tapes, double *diag,
+                           uint32_t *flags, void *stream);
+
 /* Diagnostics of the current state alone (KE, momentum, max|v|, pairs);
  * entries 6-8 are zero. */
 int32_t sph_diagnostics(const sph_params *p, const sph_particles *parts,
@@ -283,7 +311,9 @@ int32_t sph_neighbor_counts(const sph_params *p, const sph_particles *parts,
 
 /* ---- errors --------------------------------------------------------------- */
 
-/* Synchronise `stream`, then read (and clear) the device flag word. */
+/* Synchronise `stream`, then read (and clear) the device flag word: the
+ * first word of a workspace, or the flag word a caller passed to
+ * sph_kdk_run_static. */
 int32_t sph_get_flags(void *ws, void *stream, uint32_t *host_flags);
 
 /* Clear the device flag word (asynchronous). */

@@ -14,6 +14,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsph.so")
 
 SPH_OK = 0
+SPH_E_TOO_LARGE = -7
+STATIC_SCRATCH_BYTES = 64 << 20   # the static scratch of sph_kdk_run_static
 SPH_F32 = 0
 SPH_F64 = 1
 SPH_NDIAG = 9
@@ -35,7 +37,7 @@ EXPORTS = (
     "sph_workspace_size", "sph_tape_size", "sph_lattice_kappa", "sph_bin_positions",
     "sph_build_cells", "sph_density", "sph_forces", "sph_wall_state", "sph_tv_correction",
     "sph_kdk_step",
-    "sph_kdk_run", "sph_diagnostics", "sph_adjoint_step", "sph_adjoint_init", "sph_neighbor_counts",
+    "sph_kdk_run", "sph_kdk_run_static", "sph_diagnostics", "sph_adjoint_step", "sph_adjoint_init", "sph_neighbor_counts",
     "sph_get_flags", "sph_clear_flags", "sph_status_string",
 )
 
@@ -101,6 +103,8 @@ def load():
                          vp],
         "sph_kdk_run": [pp, P(SphParticles), vp, ctypes.c_int64, ctypes.c_int64, vp,
                         ctypes.c_size_t, vp, vp, vp],
+        "sph_kdk_run_static": [pp, P(SphParticles), vp, ctypes.c_int64, ctypes.c_int64, vp, vp,
+                               vp, vp],
         "sph_diagnostics": [pp, P(SphParticles), vp, vp, ctypes.c_size_t, vp, vp],
         "sph_adjoint_step": [pp, vp, P(SphAdjoint), vp, vp, ctypes.c_size_t, vp],
         "sph_adjoint_init": [pp, P(SphParticles), vp, P(SphAdjoint), vp, ctypes.c_size_t, vp],

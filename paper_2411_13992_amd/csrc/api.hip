@@ -3,6 +3,7 @@
 // every function are in include/sph.h.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "sph.h"
 #include "sph_internal.hpp"
@@ -350,14 +351,15 @@ int32_t build_cells_t(const sph_params* p, sph_particles* parts, int32_t* cs, in
 // the density sweep; the state after step s is the state before step s + 1.
 template <typename T>
 int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int64_t step0,
-                    int64_t nsteps, char* ws, char* tapes, double* diag, hipStream_t stream) {
+                    int64_t nsteps, char* ws, char* tapes, double* diag, hipStream_t stream,
+                    unsigned* flag_word = nullptr) {
   const bool var = is_var(p);
   const Sizes sz = sizes_of(p, var);
   const WsLayout w = ws_layout(sz);
   const Grid g = grid_of(p);
   const Coeffs<T> k = coeffs_of<T>(p, g);
   const Launch l = launch_of(p, var, stream);
-  unsigned* flags = (unsigned*)(ws + w.flags);
+  unsigned* flags = flag_word ? flag_word : (unsigned*)(ws + w.flags);
   double* part[2] = {(double*)(ws + w.partials), (double*)(ws + w.partials2)};
   PArrays<T> a = arrays_of<T>(parts);
   PArrays<T> stg = staging_of<T>(ws, w, var);
@@ -575,6 +577,37 @@ int32_t dispatch(const sph_params* p, F&& f) {
 }  // namespace
 }  // namespace sph
 
+// ---------------------------------------------------------------- allocation-free runs
+// Device scratch of sph_kdk_run_static: the workspace of a run, held by every
+// device the library runs on until the process ends.  In host code `scratch`
+// names a host-side stand-in, never a device address: its device address is
+// looked up once per device (hipGetSymbolAddress, with that device current)
+// and only that address is passed to kernels.
+static __device__ __align__(256) char scratch[SPH_STATIC_SCRATCH_BYTES];
+
+namespace sph {
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mutex;
+char* scratch_address[kMaxDevices] = {};
+
+// Device address of the current device's scratch (looked up on its first use).
+int32_t scratch_of_current_device(char** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return SPH_E_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return SPH_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_address[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SPH_E_HIP;
+    scratch_address[dev] = (char*)ptr;
+  }
+  *out = scratch_address[dev];
+  return SPH_OK;
+}
+}  // namespace
+}  // namespace sph
+
 using namespace sph;
 
 extern "C" {
@@ -781,6 +814,41 @@ int32_t sph_kdk_run(const sph_params* p, sph_particles* parts, int32_t* cell_sta
   return kdk_common(p, parts, cell_start, step_index, nsteps, ws, ws_bytes, tapes, diag, stream);
 }
 
+int32_t sph_kdk_run_static(const sph_params* p, sph_particles* parts, int32_t* cell_start,
+                           int64_t step_index, int64_t nsteps, void* tapes, double* diag,
+                           uint32_t* flags, void* stream) {
+  int32_t st = check_params(p);
+  if (st != SPH_OK) return st;
+  st = check_particles(p, parts, true);
+  if (st != SPH_OK) return st;
+  if (!cell_start || step_index < 0 || nsteps < 0) return SPH_E_ARG;
+  size_t need = 0;
+  sph_workspace_size(p, &need);
+  if (need > (size_t)SPH_STATIC_SCRATCH_BYTES) return SPH_E_TOO_LARGE;
+  if (nsteps == 0) return SPH_OK;
+  hipStream_t s = (hipStream_t)stream;
+  if (p->n == 0) {
+    if (diag) launch_zero<double>(s, diag, (long)SPH_NDIAG * nsteps);
+    return hip_status();
+  }
+  char* ws = nullptr;
+  st = scratch_of_current_device(&ws);
+  if (st != SPH_OK) return st;
+  // the scratch keeps the previous call's contents: its own flag word is
+  // cleared here (the run itself clears its histogram, scan state and
+  // diagnostics partials before use, as it does in a caller's workspace)
+  unsigned* flag_word = (unsigned*)flags;
+  if (!flag_word) {
+    flag_word = (unsigned*)ws;
+    launch_fill(s, (int*)flag_word, 1, 0);
+  }
+  return dispatch(p, [&](auto tag) {
+    using T = decltype(tag);
+    return run_steps_t<T>(p, parts, cell_start, step_index, nsteps, ws, (char*)tapes, diag, s,
+                          flag_word);
+  });
+}
+
 int32_t sph_diagnostics(const sph_params* p, const sph_particles* parts, const int32_t* cell_start,
                         void* ws, size_t ws_bytes, double* diag, void* stream) {
   int32_t st = check_params(p);
@@ -879,6 +947,8 @@ const char* sph_status_string(int32_t status) {
     case SPH_E_CELL_RANGE: return "cell grid too fine for the kernel support (need >= 3 cells of edge >= 2 h_max per axis)";
     case SPH_E_NONFINITE: return "non-finite parameter";
     case SPH_E_UNSUPPORTED: return "unsupported dimension, dtype or size";
+    case SPH_E_TOO_LARGE:
+      return "problem needs more workspace than the static scratch of sph_kdk_run_static holds";
     default: return "unknown status";
   }
 }

@@ -156,3 +156,27 @@ def test_automatic_lane_choice():
     assert ws(big, 0) == ws(big, 2)
     cube = cases.taylor_green_3d(128)
     assert ws(cube, 0) == ws(cube, 4)
+
+
+def test_static_run_rejects_oversize_before_launch():
+    """The allocation-free run refuses, on the host and before anything is
+    enqueued, a problem whose workspace exceeds its static scratch, and checks
+    its other arguments like sph_kdk_run."""
+    L = _lib.load()
+    parts = _lib.SphParticles()
+    for name in ("cell", "id", "off", "vel", "acc", "rho"):
+        setattr(parts, name, 4096)       # never dereferenced: the checks fail first
+    small = _params(n=1000)
+    assert _status(small)[1] <= _lib.STATIC_SCRATCH_BYTES
+    big = _params(n=1_000_000, ncell=(400, 400, 1), h_min=1e-3, h_max=1e-3)
+    assert _status(big)[1] > _lib.STATIC_SCRATCH_BYTES
+    st = L.sph_kdk_run_static(ctypes.byref(big), ctypes.byref(parts), 4096, 0, 3, None, None,
+                              None, None)
+    assert st == _lib.SPH_E_TOO_LARGE
+    assert b"static scratch" in L.sph_status_string(st)
+    assert L.sph_kdk_run_static(ctypes.byref(small), ctypes.byref(parts), None, 0, 3, None,
+                                None, None, None) == -1
+    assert L.sph_kdk_run_static(ctypes.byref(small), None, 4096, 0, 3, None, None, None,
+                                None) == -1
+    assert L.sph_kdk_run_static(ctypes.byref(small), ctypes.byref(parts), 4096, -1, 3, None,
+                                None, None, None) == -1
