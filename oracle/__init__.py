@@ -52,6 +52,23 @@ class Params(ctypes.Structure):
     ]
 
 
+class DualParams(ctypes.Structure):
+    """Dual-criteria time stepping (Sec. 2.4): CFL numbers of Eq. 9 and 11,
+    the reference speed and kinematic viscosity of Eq. 10, and an optional
+    cap on the acoustic substeps of one advection step."""
+    _fields_ = [
+        ("cfl_ad", ctypes.c_double), ("cfl_ac", ctypes.c_double), ("u_ref", ctypes.c_double),
+        ("nu", ctypes.c_double), ("max_substeps", ctypes.c_int32),
+        ("refresh_geometry", ctypes.c_int32),
+    ]
+
+
+def dual_params(case, cfl_ad: float = 0.25, cfl_ac: float = 0.6,
+                max_substeps: int = 0, refresh_geometry: bool = False) -> DualParams:
+    return DualParams(cfl_ad=cfl_ad, cfl_ac=cfl_ac, u_ref=case.u_ref, nu=case.eta / case.rho0,
+                      max_substeps=max_substeps, refresh_geometry=int(refresh_geometry))
+
+
 # Transport-velocity formulations
 TV_LIMITED = 0      # h-scaled correction with the limiter, Eq. (16)
 TV_SCALED = 1       # h-scaled correction without limiter, Eq. (14)
@@ -100,6 +117,18 @@ def lib():
                                       ctypes.POINTER(Params), ctypes.c_int64, _D, _D, _D, _D, _D]
         L.oracle_run.argtypes = [ctypes.c_int, ctypes.c_int64, _D, _D, _D, _D, _D, _D, _D,
                                  ctypes.POINTER(Params), ctypes.c_int64, ctypes.c_int64, _D]
+        L.oracle_dt_advection.restype = ctypes.c_double
+        L.oracle_dt_advection.argtypes = [ctypes.c_double, ctypes.c_double,
+                                          ctypes.POINTER(DualParams)]
+        L.oracle_dt_acoustic.restype = ctypes.c_double
+        L.oracle_dt_acoustic.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.POINTER(DualParams)]
+        L.oracle_continuity.argtypes = [ctypes.c_int, ctypes.c_int64, _D, _D, _D, _D, _D, _D,
+                                        _I64, _I32, ctypes.c_double, ctypes.c_double, _D]
+        L.oracle_dual_step.restype = ctypes.c_int64
+        L.oracle_dual_step.argtypes = [ctypes.c_int, ctypes.c_int64, _D, _D, _D, _D, _D, _D,
+                                       ctypes.POINTER(Params), ctypes.POINTER(DualParams),
+                                       _D, _D, _D, _D, _D, _D]
         _lib = L
     return _lib
 
@@ -227,6 +256,27 @@ def forces(pos, vel, mass, rho, h, box, nbr, rho0, c0, eta, riemann_eta=3.0):
     return acc, ascale
 
 
+def dt_advection(vmax, h_min, q: DualParams) -> float:
+    """Eq. 9-10: CFL_ad h_min / max(|v|_max, max(nu / h_min, U_ref))."""
+    return float(lib().oracle_dt_advection(float(vmax), float(h_min), ctypes.byref(q)))
+
+
+def dt_acoustic(vmax, h_min, c0, q: DualParams) -> float:
+    """Eq. 11: CFL_ac h_min / (|v|_max + c0)."""
+    return float(lib().oracle_dt_acoustic(float(vmax), float(h_min), float(c0), ctypes.byref(q)))
+
+
+def continuity(pos, vel, mass, rho, h, box, nbr, rho0, c0):
+    """drho/dt of Eq. 3a with the U* of Eq. 5 at the given state."""
+    pos, vel, mass, rho, h, box = map(_f64, (pos, vel, mass, rho, h, box))
+    dim, n = pos.shape
+    start, lst = nbr
+    out = np.zeros(n)
+    lib().oracle_continuity(dim, n, _p(pos), _p(vel), _p(mass), _p(rho), _p(h), _p(box),
+                            _p(start), _p(lst), float(rho0), float(c0), _p(out))
+    return out
+
+
 class State:
     """FP64 particle state (absolute positions) advanced by the C oracle."""
 
@@ -277,6 +327,31 @@ class State:
                          ctypes.byref(self.prm), self.step_index, nsteps, _p(diag))
         self.step_index += nsteps
         return diag
+
+    def dual_step(self, q: DualParams, want: bool = False):
+        """One advection step of the dual-criteria scheme (density by
+        summation, viscous force and correction at the step's start, acoustic
+        substeps with the continuity equation).  Returns dict: dt_ad,
+        substeps, t (time advanced), dt_sub (substep sizes), the diagnostics
+        of the new state, and with want=True the correction (dr, beta, s)."""
+        d, n = self.dim, self.n
+        cap = q.max_substeps if q.max_substeps > 0 else 64
+        info = np.zeros(3)
+        dt_sub = np.zeros(cap)
+        dr = np.zeros((d, n)) if want else None
+        beta = np.zeros(n) if want else None
+        s = np.zeros(n) if want else None
+        diag = np.zeros(NDIAG)
+        nsub = lib().oracle_dual_step(d, n, _p(self.pos), _p(self.vel), _p(self.rho),
+                                      _p(self.mass), _p(self.h), _p(self.box),
+                                      ctypes.byref(self.prm), ctypes.byref(q), _p(info),
+                                      _p(dt_sub), _p(dr), _p(beta), _p(s), _p(diag))
+        self.step_index += 1
+        out = dict(zip(DIAG_NAMES, diag))
+        out.update(dt_ad=info[0], substeps=int(nsub), t=info[2], dt_sub=dt_sub[:min(nsub, cap)])
+        if want:
+            out.update(dr=dr, beta=beta, s=s)
+        return out
 
     def kinetic_energy(self) -> float:
         return float(0.5 * np.sum(self.mass * np.sum(self.vel * self.vel, axis=0)))

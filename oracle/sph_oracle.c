@@ -658,3 +658,306 @@ void oracle_run(int dim, int64_t n, double *pos, double *vel, double *acc, doubl
         oracle_kdk_step(dim, n, pos, vel, acc, rho, mass, h, box, p, step0 + s,
                         NULL, NULL, NULL, NULL, diag ? diag + ORACLE_NDIAG * s : NULL);
 }
+
+/* ================================================================== */
+/* Dual-criteria time stepping (Sec. 2.4, Eq. 9-11) with the          */
+/* continuity equation (Eq. 3a) and the Riemann solver (Eq. 5-6).     */
+/*                                                                    */
+/* One advection step of size dt_ad:                                  */
+/*  1. dt_ad = CFL_ad h_min / |v|_ad, |v|_ad = max(|v|_max,           */
+/*     max(nu / h_min, U_ref))                           (Eq. 9-10)   */
+/*  2. topology at the current positions r0: the neighbour sets and   */
+/*     the pair geometry (r_ij, F_ij = W'(r_ij)/r_ij) are fixed for   */
+/*     the whole advection step (the advection criterion updates the  */
+/*     topology, the acoustic one pressure and density)               */
+/*  3. density reinitialised by summation                  (Eq. 8)    */
+/*  4. viscous acceleration (Eq. 7), held over the step               */
+/*  5. transport-velocity correction at r0 (Eq. 14 or 16), applied    */
+/*     once to the positions                                          */
+/*  6. acoustic substeps until the step is covered, each of size      */
+/*     dt = min(CFL_ac h_min / (|v|_max + c0), dt_ad - t)  (Eq. 11)   */
+/*     in a Verlet (half density, full velocity, half density) form:  */
+/*       rho' = rho + dt/2 drho/dt                                    */
+/*       v^+  = v + dt (a^p(rho', v) + a^visc)        (Eq. 3b, 5-6)   */
+/*       r   += dt (v + v^+) / 2                                      */
+/*       drho/dt = continuity at (rho', v^+)          (Eq. 3a, 5)     */
+/*       rho^+ = rho' + dt/2 drho/dt                                  */
+/*     with drho/dt before the first substep evaluated at the          */
+/*     reinitialised density and the step's initial velocity.         */
+/* Continuity with U* of Eq. 5 (e_ij from i to j, U_l - U_r > 0 when   */
+/* approaching):                                                      */
+/*   drho_i/dt = 2 rho_i sum_j V_j (U*_ij - v_i.e_ij) W'_ij           */
+/*             = rho_i sum_j V_j F_ij [ v_ij.r_ij                     */
+/*                                      + (p_i - p_j) r_ij / (rhobar c0) ] */
+/* ================================================================== */
+typedef struct {
+    double cfl_ad;          /* 0.25 (Eq. 9)                                   */
+    double cfl_ac;          /* 0.6 (Eq. 11)                                   */
+    double u_ref;           /* reference speed U_ref (Eq. 10)                 */
+    double nu;              /* kinematic viscosity eta / rho0 (Eq. 10)        */
+    int32_t max_substeps;   /* > 0: end the advection step after this many
+                               substeps even if dt_ad is not covered          */
+    int32_t refresh_geometry; /* 1: pair geometry follows the particles through
+                               the substeps (neighbour sets still fixed)      */
+} oracle_dual_params;
+
+/* Eq. 9-10 */
+double oracle_dt_advection(double vmax, double h_min, const oracle_dual_params *q)
+{
+    double vad = fmax(vmax, fmax(q->nu / h_min, q->u_ref));
+    return q->cfl_ad * h_min / vad;
+}
+
+/* Eq. 11 */
+double oracle_dt_acoustic(double vmax, double h_min, double c0, const oracle_dual_params *q)
+{
+    return q->cfl_ac * h_min / (vmax + c0);
+}
+
+/* pair geometry of CSR neighbour lists at fixed positions */
+typedef struct {
+    double *rij;   /* [3][P]  r_i - r_j (minimum image)           */
+    double *r;     /* [P]     |r_ij|                              */
+    double *f;     /* [P]     F = W'(r)/r with h_ij               */
+} pair_geometry;
+
+static void make_geometry(int dim, int64_t n, const double *pos, const double *h,
+                          const double *box, const int64_t *start, const int32_t *list,
+                          pair_geometry *pg)
+{
+    int64_t np = start[n];
+    size_t m = (size_t)(np > 0 ? np : 1);
+    pg->rij = (double *)malloc(3 * m * sizeof(double));
+    pg->r = (double *)malloc(m * sizeof(double));
+    pg->f = (double *)malloc(m * sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t e = start[i]; e < start[i + 1]; ++e) {
+            int64_t j = list[e];
+            double d[3] = {0.0, 0.0, 0.0};
+            double r = displacement(dim, n, pos, box, i, j, d);
+            for (int k = 0; k < 3; ++k) pg->rij[(size_t)k * m + e] = d[k];
+            pg->r[e] = r;
+            pg->f[e] = oracle_kernel_f(dim, r, 0.5 * (h[i] + h[j]));
+        }
+}
+
+static void free_geometry(pair_geometry *pg)
+{
+    free(pg->rij);
+    free(pg->r);
+    free(pg->f);
+}
+
+#define GEO_R(pg, np, k, e) ((pg)->rij[(size_t)(k) * (size_t)((np) > 0 ? (np) : 1) + (e)])
+
+/* drho/dt of Eq. 3a with U* of Eq. 5 on fixed pair geometry */
+static void continuity_geo(int dim, int64_t n, const int64_t *start, const int32_t *list,
+                           const pair_geometry *pg, const double *vel, const double *mass,
+                           const double *rho, double rho0, double c0, double *drho)
+{
+    int64_t np = start[n];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double sum = 0.0;
+        double pi_ = c0 * c0 * (rho[i] - rho0);
+        for (int64_t e = start[i]; e < start[i + 1]; ++e) {
+            int64_t j = list[e];
+            double vr = 0.0;
+            for (int k = 0; k < dim; ++k)
+                vr += (vel[k * n + i] - vel[k * n + j]) * GEO_R(pg, np, k, e);
+            double pj = c0 * c0 * (rho[j] - rho0);
+            double rhobar = 0.5 * (rho[i] + rho[j]);
+            double term = vr + (pi_ - pj) * pg->r[e] / (rhobar * c0);
+            sum += mass[j] / rho[j] * pg->f[e] * term;
+        }
+        drho[i] = rho[i] * sum;
+    }
+}
+
+/* pressure acceleration of Eq. 3b with P* of Eq. 5-6 on fixed geometry */
+static void pressure_geo(int dim, int64_t n, const int64_t *start, const int32_t *list,
+                         const pair_geometry *pg, const double *vel, const double *mass,
+                         const double *rho, double rho0, double c0, double riemann_eta,
+                         double *acc)
+{
+    int64_t np = start[n];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double ai[3] = {0.0, 0.0, 0.0};
+        double pi_ = c0 * c0 * (rho[i] - rho0);
+        for (int64_t e = start[i]; e < start[i + 1]; ++e) {
+            int64_t j = list[e];
+            double r = pg->r[e];
+            double du = 0.0;
+            if (r > 0.0)
+                for (int k = 0; k < dim; ++k)
+                    du += (vel[k * n + i] - vel[k * n + j]) * (-GEO_R(pg, np, k, e) / r);
+            double beta_r = fmin(riemann_eta * fmax(du / c0, 0.0), 1.0);
+            double pj = c0 * c0 * (rho[j] - rho0);
+            double rhobar = 0.5 * (rho[i] + rho[j]);
+            double pstar = 0.5 * (pi_ + pj) + 0.5 * beta_r * rhobar * c0 * du;
+            double coef = 2.0 * mass[j] / (rho[i] * rho[j]);
+            for (int k = 0; k < dim; ++k) ai[k] += -coef * pstar * pg->f[e] * GEO_R(pg, np, k, e);
+        }
+        for (int k = 0; k < dim; ++k) acc[k * n + i] = ai[k];
+    }
+}
+
+/* viscous acceleration of Eq. 7 on fixed geometry */
+static void viscous_geo(int dim, int64_t n, const int64_t *start, const int32_t *list,
+                        const pair_geometry *pg, const double *vel, const double *mass,
+                        const double *rho, double eta, double *acc)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double ai[3] = {0.0, 0.0, 0.0};
+        for (int64_t e = start[i]; e < start[i + 1]; ++e) {
+            int64_t j = list[e];
+            double coef = 2.0 * mass[j] * eta / (rho[i] * rho[j]) * pg->f[e];
+            for (int k = 0; k < dim; ++k) ai[k] += coef * (vel[k * n + i] - vel[k * n + j]);
+        }
+        for (int k = 0; k < dim; ++k) acc[k * n + i] = ai[k];
+    }
+}
+
+/* Eq. 3a with U* of Eq. 5 at the given positions (for checks) */
+void oracle_continuity(int dim, int64_t n, const double *pos, const double *vel,
+                       const double *mass, const double *rho, const double *h,
+                       const double *box, const int64_t *start, const int32_t *list,
+                       double rho0, double c0, double *drho)
+{
+    pair_geometry pg;
+    make_geometry(dim, n, pos, h, box, start, list, &pg);
+    continuity_geo(dim, n, start, list, &pg, vel, mass, rho, rho0, c0, drho);
+    free_geometry(&pg);
+}
+
+static double max_speed(int dim, int64_t n, const double *vel)
+{
+    double vmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double v2 = 0.0;
+        for (int k = 0; k < dim; ++k) v2 += vel[k * n + i] * vel[k * n + i];
+        if (sqrt(v2) > vmax) vmax = sqrt(v2);
+    }
+    return vmax;
+}
+
+static void wrap_positions(int dim, int64_t n, double *pos, const double *box)
+{
+    for (int k = 0; k < dim; ++k)
+        for (int64_t i = 0; i < n; ++i) {
+            size_t a = (size_t)k * n + i;
+            double x = pos[a] - box[k] * floor(pos[a] / box[k]);
+            if (x >= box[k]) x -= box[k];
+            pos[a] = x;
+        }
+}
+
+/* One advection step (steps 1-6 above) of a wall-free state.  pos and vel
+ * hold the state on entry and after the step on return; rho receives the
+ * density after the last substep.  info (optional, 3 doubles): dt_ad, the
+ * number of substeps, the time advanced.  dt_sub (optional, max_substeps or
+ * 64 doubles): the substep sizes.  dr_out / beta_out / s_out (optional): the
+ * correction at r0.  diag (optional): the 9 diagnostics of the new state (KE,
+ * momentum, max|v|, the pairs of the step's topology, the limiter counts and
+ * max |dr| / dt_ad).  Returns the number of substeps. */
+int64_t oracle_dual_step(int dim, int64_t n, double *pos, double *vel, double *rho,
+                         const double *mass, const double *h, const double *box,
+                         const oracle_params *p, const oracle_dual_params *q, double *info,
+                         double *dt_sub, double *dr_out, double *beta_out, double *s_out,
+                         double *diag)
+{
+    size_t dn = (size_t)dim * (size_t)n;
+    double *visc = (double *)calloc(dn > 0 ? dn : 1, sizeof(double));
+    double *ap = (double *)calloc(dn > 0 ? dn : 1, sizeof(double));
+    double *vnew = (double *)calloc(dn > 0 ? dn : 1, sizeof(double));
+    double *dr = (double *)calloc(dn > 0 ? dn : 1, sizeof(double));
+    double *g = (double *)calloc(dn > 0 ? dn : 1, sizeof(double));
+    double *beta = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    double *s = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    double *drho = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    double *rhoh = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+
+    /* 1. advection step size */
+    double dt_ad = oracle_dt_advection(max_speed(dim, n, vel), p->h_min, q);
+
+    /* 2. topology at r0, 3. density by summation */
+    nbr_lists nl;
+    make_lists(dim, n, pos, h, box, p->use_grid, &nl);
+    pair_geometry pg;
+    make_geometry(dim, n, pos, h, box, nl.start, nl.list, &pg);
+    oracle_density(dim, n, pos, mass, h, box, nl.start, nl.list, p->kappa, rho);
+
+    /* 4. viscous acceleration, held */
+    viscous_geo(dim, n, nl.start, nl.list, &pg, vel, mass, rho, p->eta, visc);
+
+    /* 5. correction at r0 (limited Eq. 16 or unlimited Eq. 14), applied once */
+    oracle_tv(dim, n, pos, mass, rho, h, box, nl.start, nl.list, p->h_min, p->xi, p->lim_c,
+              p->lim_s0, p->tv_mode, 0.0, g, s, beta, dr, NULL);
+    for (size_t a = 0; a < dn; ++a) pos[a] += dr[a];
+    wrap_positions(dim, n, pos, box);
+
+    /* 6. acoustic substeps */
+    continuity_geo(dim, n, nl.start, nl.list, &pg, vel, mass, rho, p->rho0, p->c0, drho);
+    double t = 0.0;
+    int64_t nsub = 0;
+    while (t < dt_ad && (q->max_substeps <= 0 || nsub < q->max_substeps)) {
+        double dt = fmin(oracle_dt_acoustic(max_speed(dim, n, vel), p->h_min, p->c0, q),
+                         dt_ad - t);
+        if (dt_sub && nsub < (q->max_substeps > 0 ? q->max_substeps : 64)) dt_sub[nsub] = dt;
+        for (int64_t i = 0; i < n; ++i) rhoh[i] = rho[i] + 0.5 * dt * drho[i];
+        if (q->refresh_geometry) {
+            /* pressure at r + dt/2 v */
+            double *ph = (double *)malloc((dn > 0 ? dn : 1) * sizeof(double));
+            for (size_t a = 0; a < dn; ++a) ph[a] = pos[a] + 0.5 * dt * vel[a];
+            free_geometry(&pg);
+            make_geometry(dim, n, ph, h, box, nl.start, nl.list, &pg);
+            free(ph);
+        }
+        pressure_geo(dim, n, nl.start, nl.list, &pg, vel, mass, rhoh, p->rho0, p->c0,
+                     p->riemann_eta, ap);
+        for (size_t a = 0; a < dn; ++a) {
+            vnew[a] = vel[a] + dt * (ap[a] + visc[a]);
+            pos[a] += 0.5 * dt * (vel[a] + vnew[a]);
+        }
+        memcpy(vel, vnew, dn * sizeof(double));
+        if (q->refresh_geometry) {
+            free_geometry(&pg);
+            make_geometry(dim, n, pos, h, box, nl.start, nl.list, &pg);
+        }
+        continuity_geo(dim, n, nl.start, nl.list, &pg, vel, mass, rhoh, p->rho0, p->c0, drho);
+        for (int64_t i = 0; i < n; ++i) rho[i] = rhoh[i] + 0.5 * dt * drho[i];
+        t += dt;
+        nsub++;
+    }
+    wrap_positions(dim, n, pos, box);
+
+    if (info) {
+        info[0] = dt_ad;
+        info[1] = (double)nsub;
+        info[2] = t;
+    }
+    if (diag) {
+        oracle_params pd = *p;
+        pd.dt = dt_ad;        /* transport speed |dr| / dt_ad */
+        pd.n_wall = 0;
+        diagnostics(dim, n, vel, mass, nl.npairs, beta, s, dr, &pd, diag);
+    }
+    if (dr_out) memcpy(dr_out, dr, dn * sizeof(double));
+    if (beta_out) memcpy(beta_out, beta, (size_t)n * sizeof(double));
+    if (s_out) memcpy(s_out, s, (size_t)n * sizeof(double));
+    free_geometry(&pg);
+    free_lists(&nl);
+    free(visc);
+    free(ap);
+    free(vnew);
+    free(dr);
+    free(g);
+    free(beta);
+    free(s);
+    free(drho);
+    free(rhoh);
+    return nsub;
+}
