@@ -281,6 +281,58 @@ int32_t sph_kdk_run_static(const sph_params *p, sph_particles *parts, int32_t *c
                            int64_t step_index, int64_t nsteps, void *tapes, double *diag,
                            uint32_t *flags, void *stream);
 
+/* Dual-criteria time stepping (Sec. 2.4): CFL numbers of the advection and
+ * acoustic criteria (Eq. 9 and 11: 0.25 and 0.6), the reference speed U_ref
+ * and the kinematic viscosity nu of Eq. 10, and an optional cap on the
+ * acoustic substeps of one advection step. */
+typedef struct {
+    double cfl_ad, cfl_ac;
+    double u_ref;           /* > 0                                              */
+    double nu;              /* eta / rho0, >= 0                                 */
+    int32_t max_substeps;   /* 0: as many as the advection step needs (up to a
+                               bound, see sph_dual_run); 1..64: end each
+                               advection step after this many substeps even if
+                               they do not cover it                            */
+} sph_dual_params;
+
+/* nsteps advection steps of the dual-criteria scheme (Sec. 2.3-2.4, Sec. 3)
+ * on a sorted state with cell_start built (rho and acc on entry are not
+ * used).  Each advection step:
+ *   1. dt_ad = CFL_ad h_min / max(|v|_max, nu / h_min, U_ref)   (Eq. 9-10)
+ *   2. the topology (cells, cell-local offsets and hence the neighbour pairs
+ *      and their kernel values) of the step's start is kept through the step
+ *   3. density by summation (Eq. 8)
+ *   4. viscous acceleration (Eq. 7), held for the step
+ *   5. the correction of Eq. 16 (SPH_TV_LIMITED) or Eq. 14 (SPH_TV_SCALED)
+ *      at the step's start, added once to the displacement
+ *   6. acoustic substeps of dt = min(CFL_ac h_min / (|v|_max + c0), dt_ad - t)
+ *      (Eq. 11) until dt_ad is covered, each
+ *        rho' = rho + dt/2 drho/dt,  v+ = v + dt (a^p + a^visc) with the
+ *        Riemann pressure term of Eq. 3b, 5-6 at (rho', v),
+ *        displacement += dt (v + v+)/2,
+ *        drho/dt of Eq. 3a with U* of Eq. 5 at (rho', v+),
+ *        rho+ = rho' + dt/2 drho/dt
+ *      (the first substep's drho/dt is evaluated at the step's start)
+ *   7. positions += displacement, rebinning, cell build.
+ * The step sizes are computed on the device (FP64 maxima of |v|), so a run
+ * never synchronises; the substeps are launched a fixed number of times per
+ * step (the even number above max_substeps, or above the bound
+ * ceil(CFL_ad / CFL_ac (2 + c0 / U_ref)) + 1, which covers every step whose
+ * largest speed stays below twice max(|v|_max at its start, U_ref)); a
+ * launch past the covering substeps does nothing.  A step the automatic
+ * bound does not cover sets SPH_FLAG_CFL.  params.dt and tv_every are not
+ * used; xi = 0 turns the correction off.  On return the particle arrays hold
+ * the state after the last step in (cell, id) order: rho the density of the
+ * last substep (not re-summed), acc overwritten.  diag (optional, device)
+ * receives one row of SPH_NDIAG per step (KE, momentum, max|v| after it; the
+ * pairs of its topology; limiter counts and max |dr| / dt_ad of its
+ * correction); steps (optional, device, 3 doubles per step) dt_ad, the
+ * substeps taken and the time they covered.  Walls and SPH_TV_BACKGROUND:
+ * SPH_E_UNSUPPORTED. */
+int32_t sph_dual_run(const sph_params *p, const sph_dual_params *q, sph_particles *parts,
+                     int32_t *cell_start, int64_t nsteps, void *ws, size_t ws_bytes,
+                     double *diag, double *steps, void *stream);
+
 /* Diagnostics of the current state alone (KE, momentum, max|v|, pairs);
  * entries 6-8 are zero. */
 int32_t sph_diagnostics(const sph_params *p, const sph_particles *parts,

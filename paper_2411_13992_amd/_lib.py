@@ -37,7 +37,7 @@ EXPORTS = (
     "sph_workspace_size", "sph_tape_size", "sph_lattice_kappa", "sph_bin_positions",
     "sph_build_cells", "sph_density", "sph_forces", "sph_wall_state", "sph_tv_correction",
     "sph_kdk_step",
-    "sph_kdk_run", "sph_kdk_run_static", "sph_diagnostics", "sph_adjoint_step", "sph_adjoint_init", "sph_neighbor_counts",
+    "sph_kdk_run", "sph_kdk_run_static", "sph_dual_run", "sph_diagnostics", "sph_adjoint_step", "sph_adjoint_init", "sph_neighbor_counts",
     "sph_get_flags", "sph_clear_flags", "sph_status_string",
 )
 
@@ -55,6 +55,12 @@ class SphParams(ctypes.Structure):
         ("riemann_eta", ctypes.c_double), ("band_tol", ctypes.c_double),
         ("n_wall", ctypes.c_int64), ("lanes", ctypes.c_int32),
     ]
+
+
+class SphDualParams(ctypes.Structure):
+    _fields_ = [("cfl_ad", ctypes.c_double), ("cfl_ac", ctypes.c_double),
+                ("u_ref", ctypes.c_double), ("nu", ctypes.c_double),
+                ("max_substeps", ctypes.c_int32)]
 
 
 class SphParticles(ctypes.Structure):
@@ -105,6 +111,8 @@ def load():
                         ctypes.c_size_t, vp, vp, vp],
         "sph_kdk_run_static": [pp, P(SphParticles), vp, ctypes.c_int64, ctypes.c_int64, vp, vp,
                                vp, vp],
+        "sph_dual_run": [pp, P(SphDualParams), P(SphParticles), vp, ctypes.c_int64, vp,
+                         ctypes.c_size_t, vp, vp, vp],
         "sph_diagnostics": [pp, P(SphParticles), vp, vp, ctypes.c_size_t, vp, vp],
         "sph_adjoint_step": [pp, vp, P(SphAdjoint), vp, vp, ctypes.c_size_t, vp],
         "sph_adjoint_init": [pp, P(SphParticles), vp, P(SphAdjoint), vp, ctypes.c_size_t, vp],

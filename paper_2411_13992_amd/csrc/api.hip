@@ -27,6 +27,7 @@ struct WsLayout {
   size_t dr, partials, partials2;
   size_t adj_r, adj_v, adj_rho, adj_g, adj_r2;
   size_t wall_cells;   // cells holding a wall particle (reverse of the wall state)
+  size_t dual_clock;   // two clocks of the dual-criteria steps
   size_t total;
 };
 
@@ -122,6 +123,7 @@ WsLayout ws_layout(const Sizes& s) {
   w.adj_g = c.take(t * dn);
   w.adj_r2 = c.take(t * dn);
   w.wall_cells = c.take(s.nwall > 0 ? sizeof(int) * (size_t)s.ncells : 0);
+  w.dual_clock = c.take(2 * sizeof(DualSlot) * (kMaxDualSubsteps + 1));
   w.total = c.o;
   return w;
 }
@@ -471,6 +473,75 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
       launch_kick<T>(l, k, sz.n, a.vel, a.acc, a.mass, a.id, cur, true, flags);
       if (diag) launch_diag_fold(stream, DiagFold{cur, sz.nblk * kWavesPerBlock, diag + (size_t)SPH_NDIAG * s});
     }
+  }
+  return hip_status();
+}
+
+// ---------------------------------------------------------------- dual-criteria steps
+// nsteps advection steps of the dual-criteria scheme (dual.hip).  Per step:
+// density summation, prologue sweep, K pressure + continuity substep
+// sweeps, move, and the cell build (scan, scatter, rank + gather).  The
+// substeps reuse workspace regions the kick-drift-kick run and the adjoint
+// use for other things: the correction buffer holds the displacement
+// accumulator, the adjoint buffers the viscous acceleration, the second
+// velocity and density buffers and both density-rate buffers.  Diagnostics
+// partials alternate between the two partials buffers and are folded by the
+// next step's scan (the last step's by an extra fold).
+template <typename T>
+int32_t dual_steps_t(const sph_params* p, const DualCoeffs& q, sph_particles* parts, int32_t* cs,
+                     int64_t nsteps, char* ws, double* diag, double* record,
+                     hipStream_t stream) {
+  const bool var = is_var(p);
+  const Sizes sz = sizes_of(p, var);
+  const WsLayout w = ws_layout(sz);
+  const Grid g = grid_of(p);
+  const Coeffs<T> k = coeffs_of<T>(p, g);
+  const Launch l = launch_of(p, var, stream);
+  unsigned* flags = (unsigned*)(ws + w.flags);
+  double* part[2] = {(double*)(ws + w.partials), (double*)(ws + w.partials2)};
+  PArrays<T> a = arrays_of<T>(parts);
+  PArrays<T> stg = staging_of<T>(ws, w, var);
+  const CellBuf cb = cellbuf_of(ws, w.cellbuf, sz.ncells);
+  int* counts = cb.counts;
+  int* slot = (int*)(ws + w.slot);
+  const SortTmp st{(int*)(ws + w.tmp), (int*)(ws + w.tmp_id), (int2*)(ws + w.tmp_range)};
+  int* perm = (int*)(ws + w.perm);
+  const size_t n = (size_t)sz.n;
+  T* delta = (T*)(ws + w.dr);
+  T* visc = (T*)(ws + w.adj_r);
+  T* vel_buf[2] = {a.vel, (T*)(ws + w.adj_v)};
+  T* rho_buf[2] = {a.rho, (T*)(ws + w.adj_rho)};
+  T* drho_buf[2] = {(T*)(ws + w.adj_g), (T*)(ws + w.adj_g) + n};
+  DualSlot* clock[2] = {(DualSlot*)(ws + w.dual_clock),
+                        (DualSlot*)(ws + w.dual_clock) + (kMaxDualSubsteps + 1)};
+  launch_fill(stream, (int*)clock[0],
+              (long)(2 * sizeof(DualSlot) * (kMaxDualSubsteps + 1) / sizeof(int)), 0);
+  launch_fill(stream, counts, cb.fill_ints, 0);
+  launch_dual_start<T>(stream, sz.n, sz.dim, a.vel, clock[0]);
+  PArrays<T> src = stg;
+  src.acc = nullptr;
+  PArrays<T> dst = a;
+  dst.acc = nullptr;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    double* cur = diag ? part[s & 1] : nullptr;
+    DualSlot* clk = clock[s & 1];
+    DualSlot* nxt = clock[(s + 1) & 1];
+    launch_density<T>(l, g, k, a, cs, a.rho, cur, nullptr, flags);
+    launch_dual_prologue<T>(l, g, k, q, a, cs, visc, delta, drho_buf[0], clk, nxt, cur, flags);
+    for (int sk = 0; sk < q.K; ++sk) {
+      const int b = sk & 1;
+      launch_dual_pressure<T>(l, g, k, q, sk, a, cs, vel_buf[b], rho_buf[b], drho_buf[b], visc,
+                              vel_buf[b ^ 1], delta, clk, flags);
+      launch_dual_continuity<T>(l, g, k, q, sk, a, cs, vel_buf[b ^ 1], rho_buf[b], drho_buf[b],
+                                rho_buf[b ^ 1], drho_buf[b ^ 1], clk, flags);
+    }
+    launch_dual_move<T>(l, g, k, q, a, delta, stg, counts, slot, clk, nxt, cur,
+                        record ? record + 3 * s : nullptr, flags);
+    DiagFold fold{};
+    if (diag) fold = DiagFold{cur, sz.nblk * kWavesPerBlock, diag + (size_t)SPH_NDIAG * s};
+    launch_scan(stream, sz.ncells, counts, cb.scan, (unsigned)s, cs, flags, fold);
+    launch_scatter(stream, sz.n, stg.cell, stg.id, slot, cs, st);
+    launch_rank_gather<T>(l, sz.n, st, src, dst, perm);
   }
   return hip_status();
 }
@@ -846,6 +917,55 @@ int32_t sph_kdk_run_static(const sph_params* p, sph_particles* parts, int32_t* c
     using T = decltype(tag);
     return run_steps_t<T>(p, parts, cell_start, step_index, nsteps, ws, (char*)tapes, diag, s,
                           flag_word);
+  });
+}
+
+int32_t sph_dual_run(const sph_params* p, const sph_dual_params* q, sph_particles* parts,
+                     int32_t* cell_start, int64_t nsteps, void* ws, size_t ws_bytes, double* diag,
+                     double* steps, void* stream) {
+  int32_t st = check_params(p);
+  if (st != SPH_OK) return st;
+  st = check_particles(p, parts, true);
+  if (st != SPH_OK) return st;
+  if (!q || !cell_start || !ws || nsteps < 0) return SPH_E_ARG;
+  if (p->n_wall > 0 || p->tv_mode == SPH_TV_BACKGROUND) return SPH_E_UNSUPPORTED;
+  const double vals[] = {q->cfl_ad, q->cfl_ac, q->u_ref, q->nu};
+  for (double v : vals)
+    if (!std::isfinite(v)) return SPH_E_NONFINITE;
+  if (q->cfl_ad <= 0.0 || q->cfl_ac <= 0.0 || q->u_ref <= 0.0 || q->nu < 0.0) return SPH_E_ARG;
+  if (q->max_substeps < 0 || q->max_substeps > kMaxDualSubsteps) return SPH_E_ARG;
+  DualCoeffs dq;
+  dq.cfl_ad = q->cfl_ad;
+  dq.cfl_ac = q->cfl_ac;
+  dq.u_ref = q->u_ref;
+  dq.nu = q->nu;
+  dq.h_min = p->h_min;
+  dq.c0 = p->c0;
+  dq.capped = q->max_substeps > 0 ? 1 : 0;
+  if (dq.capped) {
+    dq.cap = q->max_substeps;
+  } else {
+    // the substeps of Eq. 11 needed to cover Eq. 9-10 while the largest
+    // speed stays below twice max(|v|_max at the step's start, U_ref)
+    const double bound = std::ceil(q->cfl_ad / q->cfl_ac * (2.0 + p->c0 / q->u_ref)) + 1.0;
+    if (!(bound <= kMaxDualSubsteps)) return SPH_E_UNSUPPORTED;
+    dq.cap = (int)bound;
+  }
+  dq.K = dq.cap + (dq.cap & 1);    // even: the substeps end in the state's own buffers
+  if (dq.K > kMaxDualSubsteps) return SPH_E_UNSUPPORTED;
+  size_t need = 0;
+  sph_workspace_size(p, &need);
+  if (ws_bytes < need) return SPH_E_WORKSPACE;
+  if (nsteps == 0) return SPH_OK;
+  hipStream_t s = (hipStream_t)stream;
+  if (p->n == 0) {
+    if (diag) launch_zero<double>(s, diag, (long)SPH_NDIAG * nsteps);
+    if (steps) launch_zero<double>(s, steps, 3L * nsteps);
+    return hip_status();
+  }
+  return dispatch(p, [&](auto tag) {
+    using T = decltype(tag);
+    return dual_steps_t<T>(p, dq, parts, cell_start, nsteps, (char*)ws, diag, steps, s);
   });
 }
 

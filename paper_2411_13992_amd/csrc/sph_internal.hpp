@@ -89,6 +89,44 @@ template <typename T>
 void launch_wall_state(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                        const int* cs, const T* wall_vel, int n_wall, T* wsum_out, T* wavg_out);
 
+// ---- dual-criteria time stepping (dual.hip)
+// One clock slot per acoustic substep of an advection step: the substep's
+// start time and the largest speed at its start (bits of a non-negative
+// double, gathered with integer atomic maxima).
+struct DualSlot {
+  double t;
+  unsigned long long vmax_bits;
+};
+struct DualCoeffs {
+  double cfl_ad, cfl_ac, u_ref, nu, h_min, c0;
+  int K;        // substep launches per advection step (even, <= kMaxDualSubsteps)
+  int cap;      // substeps allowed to run (K when not capped)
+  int capped;   // 1: the caller capped the substeps (an uncovered step is not an error)
+};
+constexpr int kMaxDualSubsteps = 64;
+template <typename T>
+void launch_dual_start(hipStream_t s, int n, int dim, const T* vel, DualSlot* clk);
+template <typename T>
+void launch_dual_prologue(const Launch& l, const Grid& g, const Coeffs<T>& k, const DualCoeffs& q,
+                          const PArrays<T>& p, const int* cs, T* visc, T* delta, T* drho,
+                          const DualSlot* clk, DualSlot* clk_next, double* partials,
+                          unsigned* flags);
+template <typename T>
+void launch_dual_pressure(const Launch& l, const Grid& g, const Coeffs<T>& k,
+                          const DualCoeffs& q, int sk, const PArrays<T>& p, const int* cs,
+                          const T* vel, const T* rho, const T* drho, const T* visc, T* vel_out,
+                          T* delta, DualSlot* clk, unsigned* flags);
+template <typename T>
+void launch_dual_continuity(const Launch& l, const Grid& g, const Coeffs<T>& k,
+                            const DualCoeffs& q, int sk, const PArrays<T>& p, const int* cs,
+                            const T* vel, const T* rho, const T* drho, T* rho_out, T* drho_out,
+                            DualSlot* clk, unsigned* flags);
+template <typename T>
+void launch_dual_move(const Launch& l, const Grid& g, const Coeffs<T>& k, const DualCoeffs& q,
+                      const PArrays<T>& p, const T* delta, const PArrays<T>& stg, int* counts,
+                      int* slot, const DualSlot* clk, DualSlot* clk_next, double* partials,
+                      double* record, unsigned* flags);
+
 // ---- cells (cells.hip)
 template <typename T>
 void launch_bin(const Launch& l, const Grid& g, const Coeffs<T>& k, const double* pos,

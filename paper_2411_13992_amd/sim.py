@@ -47,6 +47,7 @@ class Config:
     h_over_dx: float = 1.3    # Sec. 4: h = 1.3 dp, fixes the reference kernel sum
     ncell: tuple | None = None
     lanes: int = 0            # lanes per particle in the sweeps (0: chosen by size)
+    u_ref: float = 1.0        # reference speed of Eq. 10 (dual-criteria stepping)
 
     def cells(self):
         if self.ncell is not None:
@@ -58,7 +59,7 @@ def config_from_case(case, **overrides) -> Config:
     cfg = Config(dim=case.dim, box=tuple(case.box), rho0=case.rho0, c0=case.c0, eta=case.eta,
                  dt=case.dt, h_min=case.h_min, h_max=case.h_max, mass=float(case.mass[0]),
                  xi=case.xi, lim_c=case.lim_c, lim_s0=case.lim_s0,
-                 riemann_eta=case.riemann_eta)
+                 riemann_eta=case.riemann_eta, u_ref=case.u_ref)
     for k, v in overrides.items():
         setattr(cfg, k, v)
     return cfg
@@ -260,6 +261,26 @@ class Simulation:
             self.diag.copy_(d[-1])
         self.step_index += nsteps
         return d
+
+    def dual_run(self, nsteps: int, cfl_ad: float = 0.25, cfl_ac: float = 0.6,
+                 max_substeps: int = 0, diag: bool = True):
+        """nsteps advection steps of the dual-criteria scheme (sph_dual_run):
+        the correction once per advection step, acoustic substeps with the
+        continuity equation, step sizes of Eq. 9-11 chosen on the device.
+        Returns (diagnostics rows (nsteps, 9), step records (nsteps, 3):
+        dt_ad, substeps, time covered), FP64 device tensors."""
+        q = _lib.SphDualParams(cfl_ad=cfl_ad, cfl_ac=cfl_ac, u_ref=self.cfg.u_ref,
+                               nu=self.cfg.eta / self.cfg.rho0, max_substeps=max_substeps)
+        d = (torch.empty((nsteps, _lib.SPH_NDIAG), dtype=torch.float64, device=self.device)
+             if diag else None)
+        rec = torch.empty((nsteps, 3), dtype=torch.float64, device=self.device)
+        _lib.call("sph_dual_run", ctypes.byref(self.params), ctypes.byref(q),
+                  ctypes.byref(self.parts()), _vp(self.cs), nsteps, _vp(self.ws), self.ws_bytes,
+                  _vp(d), _vp(rec), _stream())
+        if d is not None and nsteps > 0:
+            self.diag.copy_(d[-1])
+        self.step_index += nsteps
+        return d, rec
 
     def diag_rows(self, nsteps: int) -> torch.Tensor:
         """Device buffer for the per-step diagnostics of a run."""

@@ -5,10 +5,11 @@ formulation, recording the largest fluid speed, the largest transport
 KE(t) = KE(0) exp(-16 pi^2 t / Re).
 
     python -m paper_2411_13992_amd.tg_study [--n 200] [--t-end 5] [--dtype f32]
-        [--modes limited scaled background] [--json out.json]
+        [--modes limited scaled background] [--jitter 0.05] [--dual] [--json out.json]
 
-Every step runs through sph_kdk_run; the per-step FP64 diagnostics stay on the
-device until the end of each chunk.
+Every step runs through sph_kdk_run (or, with --dual, every advection step
+through sph_dual_run); the per-step FP64 diagnostics stay on the device until
+the end of each chunk.
 """
 from __future__ import annotations
 
@@ -67,6 +68,58 @@ def run_mode(n: int, t_end: float, mode: str, dtype: str = "f32", jitter: float 
     }
 
 
+def run_dual(n: int, t_end: float, mode: str, dtype: str = "f32", jitter: float = 0.0,
+             chunk: int = 200, samples: int = 50) -> dict:
+    """The same study with the dual-criteria scheme (sph_dual_run): the
+    correction once per advection step, acoustic substeps with the continuity
+    equation, step sizes of Eq. 9-11; the transport speed is |dr| / dt_ad."""
+    import numpy as np
+    import torch
+
+    import cases
+    from .sim import Simulation
+
+    case = cases.taylor_green_2d(n, jitter=jitter, seed=1)
+    sim = Simulation.from_case(case, dtype=dtype, tv_mode=mode)
+    ke0 = float(sim.diagnostics(fresh=True)["ke"])
+    rows, recs = [], []
+    t_done = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while t_done < t_end:
+        d, rec = sim.dual_run(chunk)
+        rows.append(d.cpu().numpy())
+        recs.append(rec.cpu().numpy())
+        t_done += float(recs[-1][:, 2].sum())
+    wall = time.perf_counter() - t0
+    d = np.concatenate(rows)
+    rec = np.concatenate(recs)
+    t = np.cumsum(rec[:, 2])
+    keep = np.nonzero(t <= t_end * (1 + 1e-12))[0]
+    last = keep[-1] if keep.size else 0
+    d, rec, t = d[:last + 1], rec[:last + 1], t[:last + 1]
+    rate = -16.0 * math.pi ** 2 / case.extra["re"]
+    ke = d[:, 0] / ke0
+    ana = np.exp(rate * t)
+    vmax, tmax = d[:, 4], d[:, 8]
+    over = tmax > vmax
+    pick = np.unique(np.linspace(0, len(t) - 1, samples).astype(int))
+    k1 = int(np.searchsorted(t, 1.0)) if t[-1] >= 1.0 else len(t) - 1
+    k1 = min(k1, len(t) - 1)
+    return {
+        "mode": mode, "n": n, "particles": case.n, "dtype": dtype, "scheme": "dual",
+        "jitter": jitter, "advection_steps": len(t),
+        "substeps": int(rec[:, 1].sum()), "wall_s": wall, "flags": sim.flags(),
+        "t": t[pick].tolist(), "ke_over_ke0": ke[pick].tolist(),
+        "ke_analytic": ana[pick].tolist(), "vmax": vmax[pick].tolist(),
+        "transport_vmax": tmax[pick].tolist(),
+        "first_overcorrection_t": float(t[over][0]) if over.any() else None,
+        "overcorrected_fraction": float(over.mean()),
+        "ke_ratio_end": float(ke[-1] / ana[-1]),
+        "ke_ratio_t1": float(ke[k1] / ana[k1]),
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--n", type=int, default=200, help="particles per side (dp = 1/n)")
@@ -77,10 +130,24 @@ def main(argv=None):
     ap.add_argument("--tv-every", type=int, default=1,
                     help="apply the correction every k-th step (5 ~ once per advection "
                          "step of the dual-criteria scheme at these parameters)")
+    ap.add_argument("--dual", action="store_true",
+                    help="dual-criteria time stepping (sph_dual_run) instead of kick-drift-kick")
     ap.add_argument("--json", default=None, help="write the full series here")
     args = ap.parse_args(argv)
     out = []
     for mode in args.modes:
+        if args.dual:
+            if mode == "background":
+                continue
+            r = run_dual(args.n, args.t_end, mode, args.dtype, args.jitter)
+            out.append(r)
+            print(f"{mode:10s} n {args.n} dual: {r['advection_steps']} advection steps, "
+                  f"{r['substeps']} substeps ({r['wall_s']:.2f} s)  KE/analytic at t = 1: "
+                  f"{r['ke_ratio_t1']:.4f}, at t_end: {r['ke_ratio_end']:.4f}; transport speed "
+                  f"above fluid speed from t = {r['first_overcorrection_t']} "
+                  f"({100 * r['overcorrected_fraction']:.1f}% of steps); flags {r['flags']}",
+                  flush=True)
+            continue
         r = run_mode(args.n, args.t_end, mode, args.dtype, args.jitter, args.tv_every)
         out.append(r)
         print(f"{mode:10s} n {args.n} tv_every {args.tv_every} steps {r['steps']} ({r['wall_s']:.2f} s)  KE/analytic at t = 1: "
