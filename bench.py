@@ -238,6 +238,30 @@ def source_digest():
     return h.hexdigest()
 
 
+def time_dual(case, nsteps=60, warmup=5):
+    """The dual-criteria scheme (sph_dual_run) on the same workload, FP32:
+    time per advection step and per acoustic substep (a substep is one
+    pressure and one continuity sweep; an advection step adds the density,
+    prologue and move sweeps and the cell build)."""
+    import torch
+    from paper_2411_13992_amd import Simulation
+    sim = Simulation.from_case(case, dtype="f32")
+    sim.dual_run(warmup)
+    torch.cuda.synchronize()
+    box = {}
+    t = _events_time(lambda: box.update(r=sim.dual_run(nsteps)), 1)
+    d, rec = box["r"]
+    rec = rec.cpu().numpy()
+    sub = float(rec[:, 1].mean())
+    pairs = float(d[:, 5].mean().item())
+    return {"ms_per_advection_step": t / nsteps * 1e3, "substeps_per_step": sub,
+            "us_per_substep_amortised": t / nsteps / sub * 1e6,
+            "dt_ad": float(rec[:, 0].mean()),
+            "pair_interactions_per_s": pairs * (2 + 2 * sub) / (t / nsteps),
+            "note": "pairs counted once per neighbour sweep: density, prologue, and a "
+                    "pressure and a continuity sweep per substep"}
+
+
 def decay_accuracy(case, nsteps):
     """FP32 and FP64 runs of nsteps steps from the identical start (the FP32
     state widened exactly), kinetic energy against the analytic Taylor-Green
@@ -336,16 +360,26 @@ def main():
     default = args.workload == WORKLOAD
     sim = Simulation.from_case(case, dtype="f32")
     if args.pmc:
-        sim.run(args.warmup)
-        out = torch.empty_like(sim.acc)
-        for _ in range(20):
-            sim.forces(out=out)
+        # 20 launches each of the standalone force and density sweeps, FP32
+        # then FP64, on the benchmark state after the warm-up steps, then one
+        # copy of known size to calibrate the byte counters
+        for dt in ("f32", "f64"):
+            s = sim if dt == "f32" else Simulation.from_case(case, dtype="f64")
+            s.run(args.warmup)
+            out = torch.empty_like(s.acc)
+            rho = torch.empty_like(s.rho)
+            for _ in range(20):
+                s.forces(out=out)
+            for _ in range(20):
+                s.density(out=rho)
+            torch.cuda.synchronize()
         src = torch.ones(PMC_COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"pmc_run": True, "force_launches": 20, "copy_bytes": PMC_COPY_BYTES}))
+        print(json.dumps({"pmc_run": True, "force_launches": 20, "density_launches": 20,
+                          "copy_bytes": PMC_COPY_BYTES}))
         return
     steps, warmup = args.steps, args.warmup
     if case.n > 500_000:     # 10-30x the work per step: keep the timed region short
@@ -389,6 +423,7 @@ def main():
         out["step_roofline"] = step_bounds(case.n, pairs, t32)
     if args.workload == WORKLOAD:
         out["accuracy"] = decay_accuracy(case, case.steps)
+        out["dual_criteria"] = time_dual(case)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case)
     else:

@@ -483,8 +483,17 @@ __device__ __forceinline__ Limited limit_correction(const Coeffs<T>& k, const T*
 // of consecutive lanes with the same cell (particles arrive sorted by their
 // previous cell and move by at most one, so runs are long); the first lane of
 // each run adds the run length to the cell's counter, all runs of the wave in
-// one atomic instruction, and the run's lanes take consecutive slots.
-__device__ __forceinline__ int wave_claim_slot(bool valid, int c, int* __restrict__ counts) {
+// one atomic instruction, and the run's lanes take consecutive slots.  In two
+// halves: slot_claim_issue issues the atomic, slot_claim_finish reads its
+// result, so a caller can put independent work between them and overlap the
+// atomic's round trip (device-scope atomics are served far from the CU).
+struct SlotClaim {
+  int base;    // the run's first slot (valid in the run's first lane)
+  int start;   // lane holding the run's base
+  int lane;
+};
+
+__device__ __forceinline__ SlotClaim slot_claim_issue(bool valid, int c, int* __restrict__ counts) {
   const int lane = threadIdx.x % kWave;
   const int key = valid ? c : -1 - lane;             // invalid lanes form their own runs
   const int prev = __shfl_up(key, 1, kWave);
@@ -496,8 +505,15 @@ __device__ __forceinline__ int wave_claim_slot(bool valid, int c, int* __restric
   const int next = after ? lane + __ffsll((long long)after) : kWave;
   int base = 0;
   if (lead && valid) base = atomicAdd(&counts[c], next - lane);
-  base = __shfl(base, start, kWave);
-  return base + (lane - start);
+  return SlotClaim{base, start, lane};
+}
+
+__device__ __forceinline__ int slot_claim_finish(const SlotClaim& sc) {
+  return __shfl(sc.base, sc.start, kWave) + (sc.lane - sc.start);
+}
+
+__device__ __forceinline__ int wave_claim_slot(bool valid, int c, int* __restrict__ counts) {
+  return slot_claim_finish(slot_claim_issue(valid, c, counts));
 }
 
 // ---------------------------------------------------------------- position staging

@@ -361,14 +361,16 @@ __device__ __forceinline__ void forces_impl(
       }
       if (f) atomicOr(flags, f);
     }
-    const int slot = wave_claim_slot(lead, lin, fo.counts);
-    if (lead) fo.slot[i] = slot;
+    // the slot claim's atomic overlaps the diagnostics reductions
+    const SlotClaim sc = slot_claim_issue(lead, lin, fo.counts);
     if (fo.part_cur) {
       const int cur_cols[5] = {0, 1, 2, 3, 4};
       wave_partials<5>(fo.part_cur, cur_cols, v, 1u << 4);
       const int next_cols[3] = {6, 7, 8};
       wave_partials<3>(fo.part_next, next_cols, v + 5, 1u << 2);
     }
+    const int slot = slot_claim_finish(sc);
+    if (lead) fo.slot[i] = slot;
   }
 }
 

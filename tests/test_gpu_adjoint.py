@@ -360,3 +360,37 @@ def test_rollout_backward_after_the_simulation_moved_on():
     moved = grads(True)
     assert torch.equal(moved[0], 2 * clean[0]) and torch.equal(moved[1], 2 * clean[1])
     assert float(clean[0].abs().max()) > 0.0 and float(clean[1].abs()) > 0.0
+
+
+@pytest.mark.timeout(900)
+def test_adjoint_workload_vs_oracle_fd():
+    """The differentiation workload (200x200 Taylor-Green, 40k particles,
+    +-1% velocity perturbation, jittered +-0.05 dx, 200 FP32 steps,
+    checkpoints every 20) against central differences of the FP64 oracle run
+    from the same particles: two random directions of v^0 and xi, to 1e-4."""
+    import torch
+    from paper_2411_13992_amd.adjoint import rollout, kinetic_energy
+    case = cases.taylor_green_2d(200, jitter=0.05, vel_perturb=0.01, seed=1, steps=200)
+    nsteps, every = case.steps, 20
+    sim = _sim(case, "f32")
+    pos0 = sim.positions_fp64(sim.initial["cell"], sim.initial["off"])
+    ids0 = sim.initial["id"].cpu().numpy()
+    pos_by_id = np.empty_like(pos0)
+    pos_by_id[:, ids0] = pos0
+    v0 = torch.tensor(case.vel, dtype=torch.float64, device="cuda", requires_grad=True)
+    xi = torch.tensor(case.xi, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = kinetic_energy(sim, rollout(sim, v0, xi, nsteps, every))
+    loss.backward()
+    gv = v0.grad.cpu().numpy()
+    gxi = xi.grad.item()
+    rng = np.random.default_rng(17)
+    for k in range(2):
+        u = rng.normal(size=case.vel.shape)
+        print(f"oracle fd direction {k}", flush=True)
+        fd = central_fd(lambda e: _oracle_ke(case, pos_by_id, case.vel + e * u, case.xi,
+                                             nsteps), 1e-6)
+        assert abs(np.sum(gv * u) - fd) <= 1e-4 * abs(fd), (k, np.sum(gv * u), fd)
+    print("oracle fd xi", flush=True)
+    fd = central_fd(lambda e: _oracle_ke(case, pos_by_id, case.vel, case.xi + e, nsteps), 1e-6)
+    print(f"workload vs oracle: dKE/dxi adjoint {gxi:.6e} oracle fd {fd:.6e}")
+    assert fd != 0.0 and abs(gxi - fd) <= 1e-4 * abs(fd), (gxi, fd)
