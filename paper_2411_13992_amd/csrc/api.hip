@@ -15,7 +15,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Sizes {
-  int dim, n, ncells, nblk, nwall;
+  int dim, n, ncells, nblk, nwall, G;
   size_t tsz;     // bytes per float element
   bool var;
 };
@@ -27,9 +27,15 @@ struct WsLayout {
   size_t dr, partials, partials2;
   size_t adj_r, adj_v, adj_rho, adj_g, adj_r2;
   size_t wall_cells;   // cells holding a wall particle (reverse of the wall state)
+  size_t cs2;          // second cell_start of a run (the rebuild reads one, writes the other)
   size_t dual_clock;   // two clocks of the dual-criteria steps
+  size_t base_total;   // every region above: the least a run can work with
+  size_t nlist, ncount;   // stored neighbour lists of a run (0 bytes when not usable)
   size_t total;
 };
+
+// Whether the stored neighbour lists can index every particle (list_jbits).
+bool lists_usable(const Sizes& s) { return (long)s.n < (1L << (s.dim == 3 ? 27 : 28)); }
 
 // One step's tape: the sorted state before the step (order n), the raw
 // correction sum and limiter value at step n, the permutation from order
@@ -46,8 +52,13 @@ struct TapeLayout {
 // One region holds everything the cell build and the diagnostics fold keep
 // between launches, so a single fill zeroes it: counts[ncells], a spare word,
 // the diagnostics ticket, two scan tickets, then 8-byte look-back tile states.
+// The tile words serve the scan (scan_blocks tiles) or the one-launch rebuild
+// (at most one tile per cell), never both in one run.
 size_t cellbuf_head(int ncells) { return ((sizeof(int) * ((size_t)ncells + 4)) + 7) / 8 * 8; }
-size_t cellbuf_bytes(int ncells) { return cellbuf_head(ncells) + 8 * (size_t)scan_blocks(ncells); }
+size_t cellbuf_bytes(int ncells) {
+  const int words = scan_blocks(ncells) > ncells ? scan_blocks(ncells) : ncells;
+  return cellbuf_head(ncells) + 8 * (size_t)words;
+}
 
 struct CellBuf {
   int* counts;
@@ -86,7 +97,8 @@ Sizes sizes_of(const sph_params* p, bool var) {
   s.dim = p->dim;
   s.n = (int)p->n;
   s.ncells = p->ncell[0] * p->ncell[1] * (p->dim == 3 ? p->ncell[2] : 1);
-  s.nblk = blocks_for((long)s.n * lanes_of(p));
+  s.G = lanes_of(p);
+  s.nblk = blocks_for((long)s.n * s.G);
   s.nwall = (int)p->n_wall;
   s.tsz = p->dtype == SPH_F64 ? 8 : 4;
   s.var = var;
@@ -124,6 +136,12 @@ WsLayout ws_layout(const Sizes& s) {
   w.adj_r2 = c.take(t * dn);
   w.wall_cells = c.take(s.nwall > 0 ? sizeof(int) * (size_t)s.ncells : 0);
   w.dual_clock = c.take(2 * sizeof(DualSlot) * (kMaxDualSubsteps + 1));
+  w.cs2 = c.take(sizeof(int) * ((size_t)s.ncells + 1));
+  w.base_total = c.o;
+  const size_t lanes = (size_t)(s.nblk > 0 ? s.nblk : 1) * kBlock;
+  const bool lists = lists_usable(s);
+  w.nlist = c.take(lists ? sizeof(unsigned) * lanes * list_cap(s.dim, s.G) : 0);
+  w.ncount = c.take(lists ? sizeof(int) * lanes : 0);
   w.total = c.o;
   return w;
 }
@@ -345,16 +363,21 @@ int32_t build_cells_t(const sph_params* p, sph_particles* parts, int32_t* cs, in
 // evaluates the correction with the standalone sweep and drifts with the
 // standalone kernel; every later step takes both from the fused force sweep of
 // the step before.  The last step finishes with the standalone kick.  Per step:
-// scan, scatter, rank + gather, density, forces (fused except the last).
+// the one-launch cell build (rebuild_kernel), density, forces (fused except
+// the last).  The cell build reads the previous order's cell starts and
+// writes the new ones into the other of two buffers (the caller's and the
+// workspace's), arranged so that the last step writes the caller's.
 // With tapes (nsteps consecutive tapes of tape_layout size), step s records
 // its state before the step, its correction sum and limiter value (from the
 // standalone sweep for the first step, from the fused force sweep of the
 // step before for the others), the cell-build permutation and its state after
 // the density sweep; the state after step s is the state before step s + 1.
+// With `lists`, each step's density sweep records the neighbour lists its
+// force sweep then reads (the workspace holds the list regions).
 template <typename T>
-int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int64_t step0,
+int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs_caller, int64_t step0,
                     int64_t nsteps, char* ws, char* tapes, double* diag, hipStream_t stream,
-                    unsigned* flag_word = nullptr) {
+                    bool lists, unsigned* flag_word = nullptr) {
   const bool var = is_var(p);
   const Sizes sz = sizes_of(p, var);
   const WsLayout w = ws_layout(sz);
@@ -366,12 +389,22 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
   PArrays<T> a = arrays_of<T>(parts);
   PArrays<T> stg = staging_of<T>(ws, w, var);
   const CellBuf cb = cellbuf_of(ws, w.cellbuf, sz.ncells);
-  int* counts = cb.counts;
-  int* slot = (int*)(ws + w.slot);
-  const SortTmp st{(int*)(ws + w.tmp), (int*)(ws + w.tmp_id), (int2*)(ws + w.tmp_range)};
   int* perm = (int*)(ws + w.perm);
+  StoredList sl{};
+  if (lists && lists_usable(sz))
+    sl = StoredList{(unsigned*)(ws + w.nlist), (int*)(ws + w.ncount), sz.nblk * kBlock};
   const size_t n = (size_t)sz.n, dn = (size_t)sz.dim * n, t = sz.tsz;
   const size_t csb = sizeof(int) * ((size_t)sz.ncells + 1);
+  // the two cell_start buffers; step s reads csbuf[cur] and writes
+  // csbuf[cur ^ 1].  With an odd number of steps the run starts from the
+  // workspace copy, so the last step writes the caller's buffer.
+  int* csbuf[2] = {cs_caller, (int*)(ws + w.cs2)};
+  int cur = 0;
+  if (nsteps & 1) {
+    if (copy_d2d(csbuf[1], cs_caller, csb, stream) != hipSuccess) return SPH_E_HIP;
+    cur = 1;
+  }
+  int* cs = csbuf[cur];
   auto applies = [&](int64_t s) { return p->tv_every > 0 && (s % p->tv_every) == 0; };
   const TapeLayout tl = tape_layout(sz);
   auto tape_of = [&](int64_t s) { return tapes + (size_t)s * tl.total; };
@@ -402,7 +435,7 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
     return e;
   };
   if (tapes && record_pre(tape_of(0)) != hipSuccess) return SPH_E_HIP;
-  launch_fill(stream, counts, cb.fill_ints, 0);
+  launch_fill(stream, cb.counts, cb.fill_ints, 0);
   if (diag) launch_zero_partials(stream, sz.nblk, part[0]);
 
   // first step: 1. correction at r^n (Eq. 14-16), 2. half kick + drift + rebin
@@ -416,26 +449,37 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
     launch_zero<T>(stream, (T*)(tapes + tl.g), (long)dn);
     launch_zero<T>(stream, (T*)(tapes + tl.beta), (long)n);
   }
-  launch_drift<T>(l, g, k, a, dr, stg, counts, slot, flags);
+  launch_drift<T>(l, g, k, a, dr, stg, nullptr, nullptr, flags);
 
-  PArrays<T> src = stg;
-  src.acc = nullptr;
-  src.rho = nullptr;
   PArrays<T> dst = a;
   dst.acc = nullptr;
   dst.rho = nullptr;
+  RebuildArgs rb{};
+  rb.ncells = sz.ncells;
+  rb.tile_cells = rebuild_tile_cells(sz.dim, p->ncell, (long)n, var);
+  rb.tiles_per_row = (p->ncell[0] + rb.tile_cells - 1) / rb.tile_cells;
+  rb.ntiles = rebuild_tiles(sz.dim, p->ncell, (long)n, var);
+  rb.st = cb.scan;
+  rb.perm = tapes ? perm : nullptr;
+  rb.flags = flags;
   for (int64_t s = 0; s < nsteps; ++s) {
-    double* cur = diag ? part[s & 1] : nullptr;
+    double* cur_part = diag ? part[s & 1] : nullptr;
     double* nxt = diag ? part[(s + 1) & 1] : nullptr;
-    // the previous step's diagnostics are folded by the scan of this step
-    DiagFold fold{};
-    if (diag && s > 0) fold = DiagFold{part[(s - 1) & 1], sz.nblk * kWavesPerBlock, diag + (size_t)SPH_NDIAG * (s - 1)};
-    // 3. cell build
-    launch_scan(stream, sz.ncells, counts, cb.scan, (unsigned)s, cs, flags, fold);
-    launch_scatter(stream, sz.n, stg.cell, stg.id, slot, cs, st);
-    launch_rank_gather<T>(l, sz.n, st, src, dst, perm);
-    // 4. density summation (Eq. 8); wall particles from the fluid
-    launch_density<T>(l, g, k, a, cs, a.rho, cur, nullptr, flags);
+    // 3. cell build, folding the previous step's diagnostics in its extra blocks
+    rb.fold = DiagFold{};
+    if (diag && s > 0)
+      rb.fold = DiagFold{part[(s - 1) & 1], sz.nblk * kWavesPerBlock,
+                         diag + (size_t)SPH_NDIAG * (s - 1)};
+    rb.cs_old = csbuf[cur];
+    rb.cs_new = csbuf[cur ^ 1];
+    rb.epoch = (unsigned)s;
+    launch_rebuild<T>(l, g, rb, stg, dst);
+    cur ^= 1;
+    cs = csbuf[cur];
+    // 4. density summation (Eq. 8), recording the neighbours for the fused
+    // force sweep; wall particles from the fluid
+    const StoredList step_sl = s + 1 < nsteps ? sl : StoredList{};
+    launch_density<T>(l, g, k, a, cs, a.rho, cur_part, nullptr, flags, step_sl);
     launch_wall_state<T>(l, g, k, a, cs, (const T*)parts->wall_vel, (int)p->n_wall,
                          tapes ? (T*)(tape_of(s) + tl.wsum) : nullptr,
                          tapes ? (T*)(tape_of(s) + tl.wavg) : nullptr);
@@ -450,9 +494,9 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
       FusedOut<T> fo;
       fo.apply_next = applies(step0 + s + 1) ? 1 : 0;
       fo.stg = stg;
-      fo.counts = counts;
-      fo.slot = slot;
-      fo.part_cur = cur;
+      fo.counts = nullptr;
+      fo.slot = nullptr;
+      fo.part_cur = cur_part;
       fo.part_next = nxt;
       fo.g_next = nullptr;
       fo.beta_next = nullptr;
@@ -466,12 +510,12 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs, int6
           launch_zero<T>(stream, (T*)(tn + tl.beta), (long)n);
         }
       }
-      launch_forces_fused<T>(l, g, k, a, cs, fo, flags);
+      launch_forces_fused<T>(l, g, k, a, cs, fo, flags, step_sl);
     } else {
       // 5-6. accelerations at (r^{n+1}, v', rho^{n+1}), 7. second half kick
       launch_forces<T>(l, g, k, a, cs, a.vel, a.acc, flags);
-      launch_kick<T>(l, k, sz.n, a.vel, a.acc, a.mass, a.id, cur, true, flags);
-      if (diag) launch_diag_fold(stream, DiagFold{cur, sz.nblk * kWavesPerBlock, diag + (size_t)SPH_NDIAG * s});
+      launch_kick<T>(l, k, sz.n, a.vel, a.acc, a.mass, a.id, cur_part, true, flags);
+      if (diag) launch_diag_fold(stream, DiagFold{cur_part, sz.nblk * kWavesPerBlock, diag + (size_t)SPH_NDIAG * s});
     }
   }
   return hip_status();
@@ -869,7 +913,7 @@ static int32_t kdk_common(const sph_params* p, sph_particles* parts, int32_t* ce
   return dispatch(p, [&](auto tag) {
     using T = decltype(tag);
     return run_steps_t<T>(p, parts, cell_start, step_index, nsteps, (char*)ws, (char*)tape, diag,
-                          (hipStream_t)stream);
+                          (hipStream_t)stream, true);
   });
 }
 
@@ -893,9 +937,11 @@ int32_t sph_kdk_run_static(const sph_params* p, sph_particles* parts, int32_t* c
   st = check_particles(p, parts, true);
   if (st != SPH_OK) return st;
   if (!cell_start || step_index < 0 || nsteps < 0) return SPH_E_ARG;
-  size_t need = 0;
-  sph_workspace_size(p, &need);
-  if (need > (size_t)SPH_STATIC_SCRATCH_BYTES) return SPH_E_TOO_LARGE;
+  // the run needs the workspace without its stored neighbour lists, and
+  // records lists when they fit too
+  const WsLayout wl = ws_layout(sizes_of(p, true));
+  if (wl.base_total > (size_t)SPH_STATIC_SCRATCH_BYTES) return SPH_E_TOO_LARGE;
+  const bool lists = wl.total <= (size_t)SPH_STATIC_SCRATCH_BYTES;
   if (nsteps == 0) return SPH_OK;
   hipStream_t s = (hipStream_t)stream;
   if (p->n == 0) {
@@ -916,7 +962,7 @@ int32_t sph_kdk_run_static(const sph_params* p, sph_particles* parts, int32_t* c
   return dispatch(p, [&](auto tag) {
     using T = decltype(tag);
     return run_steps_t<T>(p, parts, cell_start, step_index, nsteps, ws, (char*)tapes, diag, s,
-                          flag_word);
+                          lists, flag_word);
   });
 }
 

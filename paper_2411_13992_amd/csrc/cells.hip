@@ -297,7 +297,390 @@ void launch_rank_gather(const Launch& l, int n, SortTmp tmp, const PArrays<T>& s
                        n, tmp, stg, dst, perm);
 }
 
+// ------------------------------------------------------------------ rebuild
+// One launch that puts particles back into (cell, id) order after a drift
+// that moved each of them by at most one cell per axis (the drift flags and
+// clamps anything else).  The previous order is sorted by the previous
+// cells, with cell_start cs_old; the staging arrays hold every particle's new
+// cell and values in that order.  Block b takes tile b: up to T consecutive
+// cells of one x-row (tiles numbered in cell order).  The tile's particles were previous occupants
+// of the cells within one cell of it — 3 row segments in 2-D, 9 in 3-D, each
+// one or two runs of the previous order — so the block reads those runs'
+// new cells, counts the tile's particles per cell in LDS, gets the number of
+// particles in all earlier tiles by a decoupled look-back over the tiles'
+// totals (the same scheme as scan_lookback_kernel), ranks each particle by id
+// among its cell's particles and writes them, its cells' starts and the
+// permutation.  The order is a function of (cell, id) only.  A tile with more
+// than kRebuildCap particles ranks them from global memory instead (slow,
+// exact).  Extra blocks past the tiles fold diagnostics partials, as the
+// scan's do.
+constexpr int kRebuildCap = 2048;        // tile particles ranked in LDS
+constexpr int kRebuildMaxCells = 512;    // cells per tile (host: T <= this)
+constexpr int kRebuildBlock = 1024;     // threads per block
+
+int rebuild_tile_cells(int dim, const int nc[3], long n, bool var) {
+  const int ncells = nc[0] * nc[1] * (dim == 3 ? nc[2] : 1);
+  const double occ = ncells > 0 ? (double)n / ncells : 0.0;
+  // room for 1.5 times the mean occupancy per cell, 3 times with per-particle
+  // resolution (cells sized by the largest h hold several times the mean
+  // where h is smallest)
+  const double room = var ? 3.0 : 1.5;
+  int t = occ > 0.0 ? (int)(kRebuildCap / (room * occ)) : kRebuildMaxCells;
+  t = t < 1 ? 1 : (t > kRebuildMaxCells ? kRebuildMaxCells : t);
+  return t < nc[0] ? t : nc[0];
+}
+
+int rebuild_tiles(int dim, const int nc[3], long n, bool var) {
+  const int t = rebuild_tile_cells(dim, nc, n, var);
+  const int per_row = (nc[0] + t - 1) / t;
+  return per_row * nc[1] * (dim == 3 ? nc[2] : 1);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildArgs a,
+                                                                PArrays<T> stg, PArrays<T> dst) {
+  constexpr int NB = kRebuildBlock;
+  constexpr int NR = D == 3 ? 9 : 3;             // rows of cells around the tile's row
+  constexpr int NP = 2 * NR;                     // runs: one or two per row (x seam)
+  __shared__ int s_off[kRebuildMaxCells + 1];   // counts, then exclusive offsets
+  __shared__ int s_cur[kRebuildMaxCells];
+  __shared__ int s_j[kRebuildCap];              // member: previous index
+  __shared__ int s_c[kRebuildCap];              // member: cell within the tile
+  __shared__ int s_id[kRebuildCap];             // member: particle id
+  __shared__ int s_bucket[kRebuildCap];         // members grouped by cell
+  __shared__ int s_bid[kRebuildCap];            // ids in grouped order
+  __shared__ int s_order[kRebuildCap];          // previous index by destination
+  __shared__ int s_ocell[kRebuildCap];          // new cell by destination
+  __shared__ int s_pa[NP], s_pstart[NP + 1];
+  __shared__ int s_nmem, s_prefix;
+  __shared__ int s_red[NB / kWave];
+  __shared__ double s_fold[kBlock / kWave];
+  const int tid = threadIdx.x;
+  const int lane = tid % kWave;
+  if (a.fold.partials && (int)blockIdx.x >= a.ntiles) {
+    // one diagnostics column, by the first kBlock threads in the order of
+    // fold_diag_column (so the row equals a diag_fold_kernel fold bit for bit)
+    const int col = blockIdx.x - a.ntiles;
+    const bool mx = col == 4 || col == 8;
+    const double* c = a.fold.partials + (size_t)col * a.fold.nrows;
+    double v = 0.0;
+    if (tid < kBlock)
+      v = mx ? wave_max(fold_rows<true>(c, a.fold.nrows)) : wave_sum(fold_rows<false>(c, a.fold.nrows));
+    if (tid < kBlock && lane == 0) s_fold[tid / kWave] = v;
+    __syncthreads();
+    if (tid == 0) {
+      double r = s_fold[0];
+      for (int w = 1; w < kBlock / kWave; ++w) r = mx ? (r > s_fold[w] ? r : s_fold[w]) : r + s_fold[w];
+      a.fold.diag[col] = r;
+    }
+    return;
+  }
+  const int n = g.n;
+  const int nx = g.nc[0], ny = g.nc[1], nz = D == 3 ? g.nc[2] : 1;
+  // tile = block index: blocks start in index order on each XCD, so every
+  // tile a block waits on belongs to a block that started before it and
+  // publishes its total without waiting (and the wait is bounded anyway)
+  const int tile = blockIdx.x;
+  const int row = tile / a.tiles_per_row;
+  const int x0 = (tile - row * a.tiles_per_row) * a.tile_cells;
+  const int tc = min(a.tile_cells, nx - x0);
+  const int tile0 = row * nx + x0;
+  const int y = row % ny, z = row / ny;
+  if (tid == 0) s_nmem = 0;
+  // the runs of the previous order that hold the tile's particles: for each
+  // row of cells next to the tile's, the cells [x0 - 1, x0 + tc] (the whole
+  // row when that covers it), one or two runs across the x seam; clamped into
+  // [0, n], so a cell_start that does not describe the previous order can
+  // lose particles (flagged below) but not fault
+  if (tid < NR) {
+    const int dy = tid % 3 - 1, dz = D == 3 ? tid / 3 - 1 : 0;
+    const int base = (wrap_index(y + dy, ny) + ny * wrap_index(z + dz, nz)) * nx;
+    int pa0, pb0, pa1 = 0, pb1 = 0;
+    if (tc + 2 >= nx) {
+      pa0 = a.cs_old[base];
+      pb0 = a.cs_old[base + nx];
+    } else {
+      const int xs = x0 - 1, xe = x0 + tc + 1;   // [xs, xe), may cross the x seam once
+      if (xs < 0) {
+        pa0 = a.cs_old[base + nx - 1];
+        pb0 = a.cs_old[base + nx];
+        pa1 = a.cs_old[base];
+        pb1 = a.cs_old[base + xe];
+      } else if (xe > nx) {
+        pa0 = a.cs_old[base + xs];
+        pb0 = a.cs_old[base + nx];
+        pa1 = a.cs_old[base];
+        pb1 = a.cs_old[base + xe - nx];
+      } else {
+        pa0 = a.cs_old[base + xs];
+        pb0 = a.cs_old[base + xe];
+      }
+    }
+    pa0 = min(max(pa0, 0), n);
+    pb0 = min(max(pb0, pa0), n);
+    pa1 = min(max(pa1, 0), n);
+    pb1 = min(max(pb1, pa1), n);
+    s_pa[2 * tid] = pa0;
+    s_pa[2 * tid + 1] = pa1;
+    s_pstart[2 * tid + 1] = pb0 - pa0;     // lengths for now
+    s_pstart[2 * tid + 2] = pb1 - pa1;
+  }
+  for (int c = tid; c < tc; c += NB) s_off[c] = 0;
+  __syncthreads();
+  // run starts in the concatenated index range, held in registers: a
+  // candidate's run is found by compares, not by LDS reads
+  int pst[NP + 1], ppa[NP];
+  pst[0] = 0;
+#pragma unroll
+  for (int r = 0; r < NP; ++r) {
+    pst[r + 1] = pst[r] + s_pstart[r + 1];
+    ppa[r] = s_pa[r];
+  }
+  const int total = pst[NP];
+  // pass A: the tile's particles among the candidates, U per thread with
+  // their loads issued together; the wavefront's members of a batch take
+  // consecutive member slots (one LDS atomic per wavefront and batch)
+  constexpr int U = 4;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int b0 = 0; b0 < total; b0 += U * NB) {
+    int cq[U], iq[U], qq[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int f = min(b0 + u * NB + tid, total - 1);
+      int q = ppa[0] + f;
+#pragma unroll
+      for (int r = 1; r < NP; ++r) q = f >= pst[r] ? ppa[r] + (f - pst[r]) : q;
+      qq[u] = q;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      cq[u] = stg.cell[qq[u]];
+      iq[u] = stg.id[qq[u]];
+    }
+    unsigned long long mm[U];
+    int wave_total = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int lc = cq[u] - tile0;
+      const bool mem = b0 + u * NB + tid < total && lc >= 0 && lc < tc;
+      mm[u] = __ballot(mem);
+      wave_total += __popcll(mm[u]);
+      if (mem) atomicAdd(&s_off[lc], 1);
+    }
+    int base = 0;
+    if (lane == 0 && wave_total > 0) base = atomicAdd(&s_nmem, wave_total);
+    base = __shfl(base, 0, kWave);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if ((mm[u] >> lane) & 1ull) {
+        const int m = base + __popcll(mm[u] & below);
+        if (m < kRebuildCap) {
+          s_j[m] = qq[u];
+          s_c[m] = cq[u] - tile0;
+          s_id[m] = iq[u];
+        }
+      }
+      base += __popcll(mm[u]);
+    }
+  }
+  __syncthreads();
+  const int nmem = s_nmem;
+  // publish the tile's total at once, so later tiles can use it
+  if (tid == 0)
+    __hip_atomic_store(&a.st.tile_state[tile],
+                       tile_word(tile == 0 ? kTileInc : kTileAgg, a.epoch, (unsigned)nmem),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // exclusive scan of the per-cell counts, one cell per thread
+  {
+    static_assert(kRebuildMaxCells <= NB, "one cell per thread");
+    const int v = tid < tc ? s_off[tid] : 0;
+    int tot;
+    const int run = block_exclusive_scan<NB>(v, s_red, &tot);
+    if (tid < tc) {
+      s_off[tid] = run;
+      s_cur[tid] = run;
+    }
+    if (tid == 0) s_off[tc] = tot;
+  }
+  // the particles of all earlier tiles: the first wavefront reads the tile
+  // words of up to 64 earlier tiles at once, nearest first, and adds the
+  // totals up to the nearest one that carries its inclusive prefix; tiles
+  // before the first tile read as inclusive zeros
+  if (tid < kWave) {
+    const unsigned ep = a.epoch & 0x3fffffffu;
+    int prefix = 0;
+    int p = tile - 1;
+    long spins = 0;
+    while (p >= 0) {
+      const int idx = p - lane;
+      const unsigned long long w =
+          idx >= 0 ? __hip_atomic_load(&a.st.tile_state[idx], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT)
+                   : tile_word(kTileInc, a.epoch, 0u);
+      const unsigned long long f = w & kTileFlags;
+      const bool ready = f != 0 && (unsigned)((w >> 32) & 0x3fffffffull) == ep;
+      const unsigned long long incm = __ballot(ready && f == kTileInc);
+      const unsigned long long notr = __ballot(!ready);
+      const int lim = incm ? __ffsll((long long)incm) - 1 : kWave - 1;
+      const unsigned long long need = lim == kWave - 1 ? ~0ull : ((2ull << lim) - 1);
+      if (notr & need) {
+        if (++spins > kSpinLimit) {
+          if (lane == 0) atomicOr(a.flags, kFlagInternal);
+          break;
+        }
+        continue;
+      }
+      int v = lane <= lim ? (int)(w & 0xffffffffull) : 0;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) v += __shfl_xor(v, o, kWave);
+      prefix += v;
+      if (incm) break;
+      p -= kWave;
+    }
+    if (lane == 0) {
+      if (tile > 0)
+        __hip_atomic_store(&a.st.tile_state[tile],
+                           tile_word(kTileInc, a.epoch, (unsigned)(prefix + nmem)),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_prefix = prefix;
+    }
+  }
+  __syncthreads();
+  const int prefix = s_prefix;
+  for (int c = tid; c < tc; c += NB) a.cs_new[tile0 + c] = prefix + s_off[c];
+  if (tile == a.ntiles - 1 && tid == 0) {
+    a.cs_new[a.ncells] = prefix + nmem;
+    if (prefix + nmem != n) atomicOr(a.flags, kFlagInternal);   // not a one-cell move
+  }
+  auto move = [&](int j, int to, int c) {
+    if (to >= n) return;
+    dst.cell[to] = c;
+    dst.id[to] = stg.id[j];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      dst.off[d * n + to] = stg.off[d * n + j];
+      if (dst.vel) dst.vel[d * n + to] = stg.vel[d * n + j];
+    }
+    if (dst.mass) dst.mass[to] = stg.mass[j];
+    if (dst.h) dst.h[to] = stg.h[j];
+    if (a.perm) a.perm[to] = j;
+  };
+  if (nmem <= kRebuildCap) {
+    // group the members by cell (their ids beside them), rank each by id
+    // within its cell, then move them in destination order (consecutive
+    // threads, consecutive slots)
+    for (int m = tid; m < nmem; m += NB) {
+      const int pos = atomicAdd(&s_cur[s_c[m]], 1);
+      s_bucket[pos] = m;
+      s_bid[pos] = s_id[m];
+    }
+    __syncthreads();
+    for (int p = tid; p < nmem; p += NB) {
+      const int m = s_bucket[p];
+      const int lc = s_c[m], idm = s_bid[p];
+      const int b = s_off[lc], e = s_off[lc + 1];
+      // ties (equal ids, never in a valid state) by grouping position, so the
+      // ranks are always a permutation of [b, e); eight ids read at a time
+      int rank = 0;
+      for (int r0 = b; r0 < e; r0 += 8) {
+        int idr[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) idr[u] = s_bid[min(r0 + u, e - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int r = r0 + u;
+          rank += (r < e && (idr[u] < idm || (idr[u] == idm && r < p))) ? 1 : 0;
+        }
+      }
+      s_order[b + rank] = s_j[m];
+      s_ocell[b + rank] = tile0 + lc;
+    }
+    __syncthreads();
+    // two particles per thread at a time, every load issued before the stores
+    for (int u0 = tid; u0 < nmem; u0 += 2 * NB) {
+      int jj[2], cc[2], ii[2];
+      T oo[2][D], vv[2][D], ms[2], hs[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int uu = min(u0 + u * NB, nmem - 1);
+        jj[u] = s_order[uu];
+        cc[u] = s_ocell[uu];
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int j = jj[u];
+        ii[u] = stg.id[j];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          oo[u][d] = stg.off[d * n + j];
+          vv[u][d] = dst.vel ? stg.vel[d * n + j] : T(0);
+        }
+        ms[u] = dst.mass ? stg.mass[j] : T(0);
+        hs[u] = dst.h ? stg.h[j] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int to = prefix + u0 + u * NB;
+        if (u0 + u * NB >= nmem || to >= n) continue;
+        dst.cell[to] = cc[u];
+        dst.id[to] = ii[u];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          dst.off[d * n + to] = oo[u][d];
+          if (dst.vel) dst.vel[d * n + to] = vv[u][d];
+        }
+        if (dst.mass) dst.mass[to] = ms[u];
+        if (dst.h) dst.h[to] = hs[u];
+        if (a.perm) a.perm[to] = jj[u];
+      }
+    }
+  } else {
+    // too many for LDS: rank each member by id among the particles of its
+    // new cell, found in the previous occupants of the cells around it
+    for (int f = tid; f < total; f += NB) {
+      int q = ppa[0] + f;
+#pragma unroll
+      for (int r = 1; r < NP; ++r) q = f >= pst[r] ? ppa[r] + (f - pst[r]) : q;
+      const int c = stg.cell[q];
+      const int lc = c - tile0;
+      if (lc < 0 || lc >= tc) continue;
+      const int idq = stg.id[q];
+      int cc[3];
+      decode_cell<D>(g, c, cc);
+      int rank = 0;
+      for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int oc = wrap_index(cc[0] + dx, nx) +
+                           nx * (wrap_index(cc[1] + dy, ny) + ny * wrap_index(cc[2] + dz, nz));
+            const int rb = min(max(a.cs_old[oc], 0), n);
+            const int re = min(max(a.cs_old[oc + 1], rb), n);
+            for (int r = rb; r < re; ++r) {
+              const int idr = stg.id[r];
+              rank += (stg.cell[r] == c && (idr < idq || (idr == idq && r < q))) ? 1 : 0;
+            }
+          }
+      move(q, prefix + s_off[lc] + rank, c);
+    }
+  }
+}
+
+template <typename T>
+void launch_rebuild(const Launch& l, const Grid& g, const RebuildArgs& a, const PArrays<T>& stg,
+                    const PArrays<T>& dst) {
+  if (g.n == 0) return;
+  const int nb = a.ntiles + (a.fold.partials ? kNumPartials : 0);
+  if (l.dim == 2)
+    hipLaunchKernelGGL((rebuild_kernel<2, T>), dim3(nb), dim3(kRebuildBlock), 0, l.stream, g, a,
+                       stg, dst);
+  else
+    hipLaunchKernelGGL((rebuild_kernel<3, T>), dim3(nb), dim3(kRebuildBlock), 0, l.stream, g, a,
+                       stg, dst);
+}
+
 #define SPH_INST(T)                                                                          \
+  template void launch_rebuild<T>(const Launch&, const Grid&, const RebuildArgs&,            \
+                                  const PArrays<T>&, const PArrays<T>&);                     \
   template void launch_bin<T>(const Launch&, const Grid&, const Coeffs<T>&, const double*,   \
                               int*, T*, unsigned*);                                          \
   template void launch_rank_gather<T>(const Launch&, int, SortTmp, const PArrays<T>&,        \

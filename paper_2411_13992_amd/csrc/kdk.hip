@@ -49,7 +49,8 @@ void launch_stage_copy(const Launch& l, int n, const PArrays<T>& src, const PArr
 
 // ------------------------------------------------------------------ kick + drift + rebin
 // v' = v + dt/2 a; o' = o + dt v' + dr, rebinned (drift_rebin); the moved
-// particle goes to the staging buffers and claims a slot in its new cell.
+// particle goes to the staging buffers and, with counts given, claims a slot
+// in its new cell (for the scan-and-scatter cell build).
 template <int D, typename T, bool VAR>
 __global__ __launch_bounds__(kBlock) void drift_kernel(Grid g, Coeffs<T> k, PArrays<T> p,
                                                        const T* __restrict__ dr, PArrays<T> stg,
@@ -85,8 +86,10 @@ __global__ __launch_bounds__(kBlock) void drift_kernel(Grid g, Coeffs<T> k, PArr
     }
     if (f) atomicOr(flags, f);
   }
-  const int sl = wave_claim_slot(valid, lin, counts);
-  if (valid) slot[i] = sl;
+  if (counts) {
+    const int sl = wave_claim_slot(valid, lin, counts);
+    if (valid) slot[i] = sl;
+  }
 }
 
 template <typename T>

@@ -60,7 +60,7 @@ template <typename T>
 struct FusedOut {
   int apply_next;      // correction applied at the next step
   PArrays<T> stg;
-  int* counts;         // zeroed histogram for the next cell build
+  int* counts;         // zeroed histogram for the next cell build (null: no slot claims)
   int* slot;
   double* part_cur;    // null: no diagnostics
   double* part_next;
@@ -69,18 +69,22 @@ struct FusedOut {
 };
 
 // ---- sweeps (sweeps.hip)
+// with sl.entry set, also records every lane's neighbours for the force sweep
 template <typename T>
 void launch_density(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
-                    const int* cs, T* rho_out, double* partials, int* counts, unsigned* flags);
+                    const int* cs, T* rho_out, double* partials, int* counts, unsigned* flags,
+                    const StoredList& sl = StoredList{});
 template <typename T>
 void launch_tv(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                const int* cs, T* dr, T* beta, double* s_out, T* g_out, double* partials);
 template <typename T>
 void launch_forces(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                    const int* cs, const T* vel, T* acc_out, unsigned* flags);
+// with sl.entry set, over the stored lists of the density sweep just before
 template <typename T>
 void launch_forces_fused(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
-                         const int* cs, const FusedOut<T>& fo, unsigned* flags);
+                         const int* cs, const FusedOut<T>& fo, unsigned* flags,
+                         const StoredList& sl = StoredList{});
 // wall particles' density and mirror velocity from their fluid neighbours
 // (p.rho, p.vel of walls written; wall_vel [D][n_wall] by id - nfluid); with
 // wsum_out / wavg_out ([n_wall], [D][n_wall] by id - nfluid) also the kernel
@@ -163,6 +167,28 @@ void launch_scatter(hipStream_t s, int n, const int* cell, const int* id, const 
 template <typename T>
 void launch_rank_gather(const Launch& l, int n, SortTmp tmp, const PArrays<T>& stg,
                         const PArrays<T>& dst, int* perm);
+
+// One-launch cell build after a drift of at most one cell per axis (cells.hip:
+// rebuild_kernel): from the staging arrays in the previous (cell, id) order
+// with its cell starts cs_old into dst in the new order, cs_new, and perm
+// (optional: perm[new index] = previous index).  Tiles of tile_cells cells of
+// one x-row, ntiles of them (block b takes tile b), look-back words in
+// st.tile_state tagged with epoch `epoch` (as launch_scan); fold as launch_scan.
+struct RebuildArgs {
+  int ncells, ntiles, tile_cells, tiles_per_row;
+  const int* cs_old;
+  int* cs_new;
+  ScanState st;
+  unsigned epoch;
+  int* perm;
+  unsigned* flags;
+  DiagFold fold;
+};
+int rebuild_tile_cells(int dim, const int nc[3], long n, bool var);
+int rebuild_tiles(int dim, const int nc[3], long n, bool var);
+template <typename T>
+void launch_rebuild(const Launch& l, const Grid& g, const RebuildArgs& a, const PArrays<T>& stg,
+                    const PArrays<T>& dst);
 
 // ---- integration (kdk.hip)
 template <typename T>

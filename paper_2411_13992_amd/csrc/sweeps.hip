@@ -22,12 +22,17 @@
 namespace sph {
 
 // ------------------------------------------------------------------ density
-template <int D, typename T, bool VAR, int G>
-__global__ __launch_bounds__(kBlock) void density_kernel(
-    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+// Entries of the stored neighbour list each density thread holds in LDS
+template <int D, int G>
+constexpr int kDensityListCap = list_cap(D, G);
+
+// LIST: also record each lane's neighbours into the stored list sl
+template <int D, typename T, bool VAR, int G, bool LIST>
+__device__ __forceinline__ void density_impl(
+    const Grid& g, const Coeffs<T>& k, const int* __restrict__ cell, const int* __restrict__ cs,
     const T* __restrict__ off, const T* __restrict__ mass, const T* __restrict__ hh,
     T* __restrict__ rho, double* __restrict__ partials, int* __restrict__ counts,
-    unsigned* __restrict__ flags) {
+    unsigned* __restrict__ flags, const StoredList& sl) {
   const int n = g.n;
   const Cols<T, D> offc(off, n);
   const Cols<T, 1> hc(hh, n), mc(mass, n);
@@ -40,6 +45,7 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
     if constexpr (VAR) v[D] = hc(0, j);
   };
   __shared__ Stage<D, T, NS, StageCap<D, T>::value> st;
+  __shared__ NeighbourList<LIST ? kDensityListCap<D, G> : 1> nl;
   stage_positions<D, G>(g, cell, cs, st, srct);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
@@ -56,8 +62,15 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
       if constexpr (VAR) acc.init(mass[i] * wendland_alpha<D>(frcp(hi)));
       else acc.init(T(1));
     }
+    // lane L's neighbours go to the stored list (for the force sweep), first
+    // into this thread's column of the LDS list
+    auto record = [&](int j, unsigned code) {
+      if (LIST && cnt < kDensityListCap<D, G>)
+        nl.slot[cnt][threadIdx.x] = (unsigned)j | (code << list_jbits<D>());
+      ++cnt;
+    };
     // one candidate j with test values v (offsets, then h_j)
-    auto pair = [&](int j, const T* v, const T* sh, bool live) {
+    auto pair = [&](int j, const T* v, const T* sh, bool live, unsigned code) {
       T r2 = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
@@ -69,16 +82,29 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
         if (live && r2 < sup * sup && j != i) {
           const T inv = frcp(T(0.5) * sup);
           acc.add(mc(0, j) * wendland_alpha<D>(inv) * wendland_shape(fsqrt(r2) * inv));
-          ++cnt;
+          record(j, code);
         }
       } else {
         if (live && r2 < k.sup2 && j != i) {
           acc.add(wendland_shape(fsqrt(r2) * k.inv_h));
-          ++cnt;
+          record(j, code);
         }
       }
     };
     for_each_candidate_values<D, G, T, VAR>(g, k, cell[i], cs, sub, st, srct, pair);
+  }
+  if constexpr (LIST) {
+    // the LDS list out to the stored list, row by row: a row's stores cover
+    // consecutive lanes (coalesced); rows past a lane's count are not written
+    const int L = blockIdx.x * kBlock + threadIdx.x;
+    sl.count[L] = cnt;
+    const int rows = min(cnt, (int)kDensityListCap<D, G>);
+    int wave_rows = rows;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) wave_rows = max(wave_rows, __shfl_xor(wave_rows, o, kWave));
+    unsigned* __restrict__ col = sl.entry + L;
+    for (int q = 0; q < wave_rows; ++q)
+      if (q < rows) col[(size_t)q * sl.stride] = nl.slot[q][threadIdx.x];
   }
   const T sum = group_sum<G>(acc);
   cnt = group_sum_int<G>(cnt);
@@ -95,6 +121,26 @@ __global__ __launch_bounds__(kBlock) void density_kernel(
     double v[1] = {lead ? (double)cnt : 0.0};
     wave_partials<1>(partials, cols, v, 0u);
   }
+}
+
+template <int D, typename T, bool VAR, int G>
+__global__ __launch_bounds__(kBlock) void density_kernel(
+    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+    const T* __restrict__ off, const T* __restrict__ mass, const T* __restrict__ hh,
+    T* __restrict__ rho, double* __restrict__ partials, int* __restrict__ counts,
+    unsigned* __restrict__ flags) {
+  density_impl<D, T, VAR, G, false>(g, k, cell, cs, off, mass, hh, rho, partials, counts, flags,
+                                    StoredList{});
+}
+
+template <int D, typename T, bool VAR, int G>
+__global__ __launch_bounds__(kBlock) void density_list_kernel(
+    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+    const T* __restrict__ off, const T* __restrict__ mass, const T* __restrict__ hh,
+    T* __restrict__ rho, double* __restrict__ partials, int* __restrict__ counts,
+    unsigned* __restrict__ flags, StoredList sl) {
+  density_impl<D, T, VAR, G, true>(g, k, cell, cs, off, mass, hh, rho, partials, counts, flags,
+                                   sl);
 }
 
 // ------------------------------------------------------------------ transport velocity
@@ -188,13 +234,16 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
 template <int G>
 struct ForceCap { static constexpr int value = G == 2 ? 24 : (G == 4 ? 16 : 8); };
 
-template <int D, typename T, bool VAR, bool FUSED, int G>
+// LIST: the neighbours come from the stored list of the step's density sweep
+// (no candidate tests, no LDS), else from the compacted walk.
+template <int D, typename T, bool VAR, bool FUSED, int G, bool LIST>
 __device__ __forceinline__ void forces_impl(
     const Grid& g, const Coeffs<T>& k, const int* __restrict__ cell, const int* __restrict__ cs,
     const T* __restrict__ off, const T* __restrict__ vel, const T* __restrict__ rho,
     const T* __restrict__ mass, const T* __restrict__ hh, const int* __restrict__ id,
-    T* __restrict__ acc_out, unsigned* __restrict__ flags, const FusedOut<T>& fo) {
-  __shared__ NeighbourList<ForceCap<G>::value> nl;
+    T* __restrict__ acc_out, unsigned* __restrict__ flags, const FusedOut<T>& fo,
+    const StoredList& sl) {
+  __shared__ NeighbourList<LIST ? 1 : ForceCap<G>::value> nl;
   const int n = g.n;
   const Cols<T, D> offc(off, n), velc(vel, n);
   const Cols<T, 1> rhoc(rho, n), hc(hh, n), mc(mass, n);
@@ -205,7 +254,7 @@ __device__ __forceinline__ void forces_impl(
     for (int d = 0; d < D; ++d) v[d] = offc(d, j);
     if constexpr (VAR) v[D] = hc(0, j);
   };
-  __shared__ Stage<D, T, NS, StageCap<D, T>::value> st;
+  __shared__ Stage<D, T, NS, LIST ? 0 : StageCap<D, T>::value> st;
   stage_positions<D, G>(g, cell, cs, st, srct);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
@@ -243,15 +292,30 @@ __device__ __forceinline__ void forces_impl(
       }
       return (j != i) & (r2 < pair_h<D, T, VAR>(k, hi, VAR ? v[D] : T(0)).sup2);
     };
-    auto body = [&](int j, const T* sh) {
+    // the pair body in two parts: fetch reads what it needs of neighbour j,
+    // compute adds the pair's terms (the stored-list walk issues several
+    // neighbours' fetches before their computes)
+    auto fetch = [&](int j) {
+      PairIn<D, T> nb;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        nb.o[d] = offc(d, j);
+        nb.v[d] = velc(d, j);
+      }
+      nb.rho = rhoc(0, j);
+      nb.m = VAR ? mc(0, j) : k.mass;
+      nb.h = VAR ? hc(0, j) : T(0);
+      return nb;
+    };
+    auto compute = [&](const PairIn<D, T>& nb, const T* sh) {
       T rv[3];
       T r2 = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        rv[d] = (oi[d] - offc(d, j)) - sh[d];
+        rv[d] = (oi[d] - nb.o[d]) - sh[d];
         r2 = tfma(rv[d], rv[d], r2);
       }
-      const PairH<D, T, VAR> ph = pair_h<D, T, VAR>(k, hi, VAR ? hc(0, j) : T(0));
+      const PairH<D, T, VAR> ph = pair_h<D, T, VAR>(k, hi, nb.h);
       const PairGeo<T> pg = pair_geo(r2);
       const T t = kernel_t(pg.r, ph.inv_h);
       const T t3 = t * t * t;
@@ -260,16 +324,16 @@ __device__ __forceinline__ void forces_impl(
       T vr = T(0);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        vij[d] = vi[d] - velc(d, j);
+        vij[d] = vi[d] - nb.v[d];
         vr = tfma(vij[d], rv[d], vr);
       }
       const T du = -vr * pg.inv_r;
       const T br = tmin(k.riemann_eta * tmax(du * k.inv_c0, T(0)), T(1));
-      const T rhoj = rhoc(0, j);
+      const T rhoj = nb.rho;
       const T rinv = frcp(rhoj);
       const T pj = k.c0sq * (rhoj - k.rho0);
       const T pstar = tfma(T(0.25) * br * (rhoi + rhoj) * k.c0, du, T(0.5) * (pi + pj));
-      const T mj = VAR ? mc(0, j) : k.mass;
+      const T mj = nb.m;
       const T coef = mj * F * rinv;
 #pragma unroll
       for (int d = 0; d < D; ++d) acc[d].add(coef * tfma(-pstar, rv[d], k.eta * vij[d]));
@@ -279,9 +343,15 @@ __device__ __forceinline__ void forces_impl(
         for (int d = 0; d < D; ++d) tv[d].add(w * rv[d]);
       }
     };
-    if (!wall)
-      for_each_neighbour_listed<D, G, T, NS, candidate_batch<D, T, VAR>()>(g, k, celli, cs, sub,
-                                                                         st, nl, srct, test, body);
+    auto body = [&](int j, const T* sh) { compute(fetch(j), sh); };
+    if (!wall) {
+      if constexpr (LIST)
+        for_each_neighbour_stored<D, G, T, NS>(g, k, celli, cs, sub, sl, srct, test, fetch,
+                                               compute);
+      else
+        for_each_neighbour_listed<D, G, T, NS, candidate_batch<D, T, VAR>()>(
+            g, k, celli, cs, sub, st, nl, srct, test, body);
+    }
   }
   const T s = T(2) / rhoi;
   bool bad = false;
@@ -361,16 +431,20 @@ __device__ __forceinline__ void forces_impl(
       }
       if (f) atomicOr(flags, f);
     }
-    // the slot claim's atomic overlaps the diagnostics reductions
-    const SlotClaim sc = slot_claim_issue(lead, lin, fo.counts);
+    // with counts given, the slot claim's atomic overlaps the diagnostics
+    // reductions (the one-launch rebuild needs no slots)
+    SlotClaim sc{};
+    if (fo.counts) sc = slot_claim_issue(lead, lin, fo.counts);
     if (fo.part_cur) {
       const int cur_cols[5] = {0, 1, 2, 3, 4};
       wave_partials<5>(fo.part_cur, cur_cols, v, 1u << 4);
       const int next_cols[3] = {6, 7, 8};
       wave_partials<3>(fo.part_next, next_cols, v + 5, 1u << 2);
     }
-    const int slot = slot_claim_finish(sc);
-    if (lead) fo.slot[i] = slot;
+    if (fo.counts) {
+      const int slot = slot_claim_finish(sc);
+      if (lead) fo.slot[i] = slot;
+    }
   }
 }
 
@@ -380,8 +454,8 @@ __global__ __launch_bounds__(kBlock) void forces_kernel(
     const T* __restrict__ off, const T* __restrict__ vel, const T* __restrict__ rho,
     const T* __restrict__ mass, const T* __restrict__ hh, const int* __restrict__ id,
     T* __restrict__ acc_out, unsigned* __restrict__ flags, FusedOut<T> fo) {
-  forces_impl<D, T, VAR, false, G>(g, k, cell, cs, off, vel, rho, mass, hh, id, acc_out, flags,
-                                   fo);
+  forces_impl<D, T, VAR, false, G, false>(g, k, cell, cs, off, vel, rho, mass, hh, id, acc_out,
+                                          flags, fo, StoredList{});
 }
 
 template <int D, typename T, bool VAR, int G>
@@ -390,8 +464,19 @@ __global__ __launch_bounds__(kBlock) void forces_fused_kernel(
     const T* __restrict__ off, const T* __restrict__ vel, const T* __restrict__ rho,
     const T* __restrict__ mass, const T* __restrict__ hh, const int* __restrict__ id,
     T* __restrict__ acc_out, unsigned* __restrict__ flags, FusedOut<T> fo) {
-  forces_impl<D, T, VAR, true, G>(g, k, cell, cs, off, vel, rho, mass, hh, id, acc_out, flags,
-                                  fo);
+  forces_impl<D, T, VAR, true, G, false>(g, k, cell, cs, off, vel, rho, mass, hh, id, acc_out,
+                                         flags, fo, StoredList{});
+}
+
+// the fused sweep over the density sweep's stored lists
+template <int D, typename T, bool VAR, int G>
+__global__ __launch_bounds__(kBlock) void forces_fused_list_kernel(
+    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+    const T* __restrict__ off, const T* __restrict__ vel, const T* __restrict__ rho,
+    const T* __restrict__ mass, const T* __restrict__ hh, const int* __restrict__ id,
+    T* __restrict__ acc_out, unsigned* __restrict__ flags, FusedOut<T> fo, StoredList sl) {
+  forces_impl<D, T, VAR, true, G, true>(g, k, cell, cs, off, vel, rho, mass, hh, id, acc_out,
+                                        flags, fo, sl);
 }
 
 // ------------------------------------------------------------------ wall state
@@ -482,10 +567,15 @@ __global__ __launch_bounds__(kBlock) void wall_state_kernel(
 
 template <typename T>
 void launch_density(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
-                    const int* cs, T* rho_out, double* partials, int* counts, unsigned* flags) {
+                    const int* cs, T* rho_out, double* partials, int* counts, unsigned* flags,
+                    const StoredList& sl) {
   if (g.n == 0) return;
-  SPH_SWEEP(density_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.mass, p.h, rho_out, partials,
-                                     counts, flags));
+  if (sl.entry)
+    SPH_SWEEP(density_list_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.mass, p.h, rho_out,
+                                            partials, counts, flags, sl));
+  else
+    SPH_SWEEP(density_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.mass, p.h, rho_out, partials,
+                                       counts, flags));
 }
 
 template <typename T>
@@ -507,10 +597,15 @@ void launch_forces(const Launch& l, const Grid& g, const Coeffs<T>& k, const PAr
 
 template <typename T>
 void launch_forces_fused(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
-                         const int* cs, const FusedOut<T>& fo, unsigned* flags) {
+                         const int* cs, const FusedOut<T>& fo, unsigned* flags,
+                         const StoredList& sl) {
   if (g.n == 0) return;
-  SPH_SWEEP(forces_fused_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.vel, p.rho, p.mass, p.h, p.id,
-                                          p.acc, flags, fo));
+  if (sl.entry)
+    SPH_SWEEP(forces_fused_list_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.vel, p.rho, p.mass,
+                                                 p.h, p.id, p.acc, flags, fo, sl));
+  else
+    SPH_SWEEP(forces_fused_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.vel, p.rho, p.mass, p.h,
+                                            p.id, p.acc, flags, fo));
 }
 
 template <typename T>
@@ -526,14 +621,14 @@ void launch_wall_state(const Launch& l, const Grid& g, const Coeffs<T>& k, const
                                      const PArrays<T>&, const int*, const T*, int, T*, T*);  \
   template void launch_density<T>(const Launch&, const Grid&, const Coeffs<T>&,              \
                                   const PArrays<T>&, const int*, T*, double*, int*,          \
-                                  unsigned*);                                                \
+                                  unsigned*, const StoredList&);                             \
   template void launch_tv<T>(const Launch&, const Grid&, const Coeffs<T>&, const PArrays<T>&,\
                              const int*, T*, T*, double*, T*, double*);                      \
   template void launch_forces<T>(const Launch&, const Grid&, const Coeffs<T>&,               \
                                  const PArrays<T>&, const int*, const T*, T*, unsigned*);    \
   template void launch_forces_fused<T>(const Launch&, const Grid&, const Coeffs<T>&,         \
                                        const PArrays<T>&, const int*, const FusedOut<T>&,    \
-                                       unsigned*);
+                                       unsigned*, const StoredList&);
 SPH_INST(float)
 SPH_INST(double)
 #undef SPH_INST
