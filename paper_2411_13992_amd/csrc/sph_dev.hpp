@@ -592,6 +592,35 @@ struct Stage {
   int cspan[R];    // (last cell - first cell) mod ncells
 };
 
+// The run of stencil range r for this block: its first particle ps and
+// length len (0 when longer than cap or when the cell range wraps onto
+// itself), its first cell lo and cell span.
+struct StageRun {
+  int ps, len, lo, span;
+};
+template <int D, int G>
+__device__ __forceinline__ StageRun stage_run(const Grid& g, const int* __restrict__ cell,
+                                              const int* __restrict__ cs, int r, int cap) {
+  const int n = g.n, nc = g.ncells;
+  const int p0 = blockIdx.x * (kBlock / G);
+  const int p1 = min(p0 + kBlock / G, n);
+  StageRun run{0, 0, 0, 0};
+  if (p0 < n) {
+    const int dy = r % 3 - 1, dz = (D == 3) ? r / 3 - 1 : 0;
+    const int o = dy * g.nc[0] + dz * g.nc[0] * g.nc[1];
+    const int cf = cell[p0], cl = cell[p1 - 1];
+    run.lo = ((cf + o - 1) % nc + nc) % nc;
+    const int hi = ((cl + o + 1) % nc + nc) % nc;
+    run.span = hi - run.lo + (hi < run.lo ? nc : 0);
+    if (run.span + 1 < nc) {
+      run.ps = cs[run.lo];
+      const int cnt = cs[hi + 1] - run.ps + (hi < run.lo ? n : 0);
+      if (cnt <= cap) run.len = cnt;
+    }
+  }
+  return run;
+}
+
 // Fills st for this block; every thread of the block calls it (it
 // synchronises the block when CAP > 0).  src(j, v) reads particle j's NS values.
 template <int D, int G, typename T, int NS, int CAP, typename Src>
@@ -600,29 +629,14 @@ __device__ __forceinline__ void stage_positions(const Grid& g, const int* __rest
                                                 Stage<D, T, NS, CAP>& st, Src&& src) {
   if constexpr (CAP > 0) {
     constexpr int R = Stage<D, T, NS, CAP>::R;
-    const int n = g.n, nc = g.ncells;
-    const int p0 = blockIdx.x * (kBlock / G);
-    const int p1 = min(p0 + kBlock / G, n);
+    const int n = g.n;
     if (threadIdx.x < R) {
       const int r = threadIdx.x;
-      int ps = 0, len = 0, lo = 0, span = 0;
-      if (p0 < n) {
-        const int dy = r % 3 - 1, dz = (D == 3) ? r / 3 - 1 : 0;
-        const int o = dy * g.nc[0] + dz * g.nc[0] * g.nc[1];
-        const int cf = cell[p0], cl = cell[p1 - 1];
-        lo = ((cf + o - 1) % nc + nc) % nc;
-        const int hi = ((cl + o + 1) % nc + nc) % nc;
-        span = hi - lo + (hi < lo ? nc : 0);
-        if (span + 1 < nc) {
-          ps = cs[lo];
-          const int cnt = cs[hi + 1] - ps + (hi < lo ? n : 0);
-          if (cnt <= CAP) len = cnt;
-        }
-      }
-      st.pstart[r] = ps;
-      st.plen[r] = len;
-      st.clo[r] = lo;
-      st.cspan[r] = span;
+      const StageRun run = stage_run<D, G>(g, cell, cs, r, CAP);
+      st.pstart[r] = run.ps;
+      st.plen[r] = run.len;
+      st.clo[r] = run.lo;
+      st.cspan[r] = run.span;
     }
     __syncthreads();
 #pragma unroll
@@ -662,6 +676,54 @@ __device__ __forceinline__ int staged_delta(const Grid& g, const Stage<D, T, NS,
     off += off < 0 ? g.n : 0;
     return r * CAP + off - b;
   }
+}
+
+// Stage of everything the force body reads of a neighbour in 2-D: for each
+// stencil range of the block (the runs of stage_positions), offsets and
+// velocity as one 4-vector and the density beside it.  A stored-list entry j
+// of row r (its cell code's dy) is read from the stage when j lies in that
+// row's run, from global memory otherwise (across the periodic seams, or a
+// run longer than CAP): the values are the same either way.
+template <typename T, int CAP>
+struct BodyStage {
+  static constexpr int R = 3;
+  struct alignas(4 * sizeof(T)) V4 {
+    T ox, oy, vx, vy;
+  };
+  V4 ov[R * CAP];
+  T rho[R * CAP];
+  int pstart[R];
+  int plen[R];
+};
+
+template <int G, typename T, int CAP>
+__device__ __forceinline__ void stage_bodies(const Grid& g, const int* __restrict__ cell,
+                                             const int* __restrict__ cs,
+                                             const T* __restrict__ off, const T* __restrict__ vel,
+                                             const T* __restrict__ rho, BodyStage<T, CAP>& st) {
+  const int n = g.n;
+  if (threadIdx.x < 3) {
+    const StageRun run = stage_run<2, G>(g, cell, cs, threadIdx.x, CAP);
+    st.pstart[threadIdx.x] = run.ps;
+    st.plen[threadIdx.x] = run.len;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int len = st.plen[r], ps = st.pstart[r];
+    for (int t = threadIdx.x; t < len; t += kBlock) {
+      int j = ps + t;
+      j -= (j >= n) ? n : 0;
+      typename BodyStage<T, CAP>::V4 v;
+      v.ox = off[j];
+      v.oy = off[n + j];
+      v.vx = vel[j];
+      v.vy = vel[n + j];
+      st.ov[r * CAP + t] = v;
+      st.rho[r * CAP + t] = rho[j];
+    }
+  }
+  __syncthreads();
 }
 
 // The plain candidate walk reading the candidates' test values from the
@@ -876,12 +938,12 @@ struct PairIn {
 };
 
 // Runs the pair body over lane L's stored list in batches of four: the four
-// entries are read together, then fetch(j) for the four neighbours (their
+// entries are read together, then fetch(e) for the four entries (their
 // loads issued together; past the list's end the last entry is fetched
 // again and not used), then compute(values, shift) for each in order.  A
 // lane whose list is incomplete walks its candidates instead, with
-// test(j, v, shift) on the NS values v read by src(j, v).  Same order as the
-// walk that wrote the list.
+// test(j, v, shift) on the NS values v read by src(j, v) and fetch(j) (an
+// index without cell code).  Same order as the walk that wrote the list.
 template <int D, int G, typename T, int NS, typename Src, typename Test, typename Fetch,
           typename Compute>
 __device__ __forceinline__ void for_each_neighbour_stored(const Grid& g, const Coeffs<T>& k,
@@ -901,9 +963,9 @@ __device__ __forceinline__ void for_each_neighbour_stored(const Grid& g, const C
       unsigned e[B];
 #pragma unroll
       for (int u = 0; u < B; ++u) e[u] = col[(size_t)min(q0 + u, cnt - 1) * sl.stride];
-      decltype(fetch(0)) nb[B];
+      decltype(fetch(0u)) nb[B];
 #pragma unroll
-      for (int u = 0; u < B; ++u) nb[u] = fetch((int)(e[u] & JMASK));
+      for (int u = 0; u < B; ++u) nb[u] = fetch(e[u]);
 #pragma unroll
       for (int u = 0; u < B; ++u) {
         if (q0 + u < cnt) {
@@ -917,7 +979,7 @@ __device__ __forceinline__ void for_each_neighbour_stored(const Grid& g, const C
     for_each_candidate<D, G>(g, k, cell, cs, sub, [&](int j, const T* sh) {
       T v[NS];
       src(j, v);
-      if (test(j, v, sh)) compute(fetch(j), sh);
+      if (test(j, v, sh)) compute(fetch((unsigned)j), sh);
     });
   }
 }

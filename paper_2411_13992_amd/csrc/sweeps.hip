@@ -256,6 +256,12 @@ __device__ __forceinline__ void forces_impl(
   };
   __shared__ Stage<D, T, NS, LIST ? 0 : StageCap<D, T>::value> st;
   stage_positions<D, G>(g, cell, cs, st, srct);
+  // with stored lists in uniform 2-D FP32, the neighbours' body values in LDS
+  // (in FP64 the twice larger stage costs more occupancy than it saves)
+  constexpr bool BSTAGE = LIST && D == 2 && !VAR && sizeof(T) == 4;
+  constexpr int BCAP = BSTAGE ? 256 : 1;
+  __shared__ BodyStage<T, BCAP> bst;
+  if constexpr (BSTAGE) stage_bodies<G>(g, cell, cs, off, vel, rho, bst);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   const bool valid = i < n;
@@ -344,9 +350,34 @@ __device__ __forceinline__ void forces_impl(
       }
     };
     auto body = [&](int j, const T* sh) { compute(fetch(j), sh); };
+    // a stored-list entry's values: from the body stage when its row's run
+    // holds it (2-D), else through fetch; an entry without code bits (the
+    // overflow walk) has row code 0 and is found in row 0's run or fetched
+    auto fetch_entry = [&](unsigned e) {
+      constexpr unsigned JM = (1u << list_jbits<D>()) - 1u;
+      const int j = (int)(e & JM);
+      if constexpr (BSTAGE) {
+        const int r = (int)(e >> (list_jbits<D>() + 2));
+        int o = j - bst.pstart[r];
+        o += o < 0 ? n : 0;
+        if (o < bst.plen[r]) {
+          PairIn<D, T> nb;
+          const auto v = bst.ov[r * BCAP + o];
+          nb.o[0] = v.ox;
+          nb.o[1] = v.oy;
+          nb.v[0] = v.vx;
+          nb.v[1] = v.vy;
+          nb.rho = bst.rho[r * BCAP + o];
+          nb.m = k.mass;
+          nb.h = T(0);
+          return nb;
+        }
+      }
+      return fetch(j);
+    };
     if (!wall) {
       if constexpr (LIST)
-        for_each_neighbour_stored<D, G, T, NS>(g, k, celli, cs, sub, sl, srct, test, fetch,
+        for_each_neighbour_stored<D, G, T, NS>(g, k, celli, cs, sub, sl, srct, test, fetch_entry,
                                                compute);
       else
         for_each_neighbour_listed<D, G, T, NS, candidate_batch<D, T, VAR>()>(
