@@ -34,8 +34,13 @@ struct WsLayout {
   size_t total;
 };
 
-// Whether the stored neighbour lists can index every particle (list_jbits).
-bool lists_usable(const Sizes& s) { return (long)s.n < (1L << (s.dim == 3 ? 27 : 28)); }
+// Whether the stored neighbour lists can index every particle (list_jbits),
+// and their rows stay within 2^31 bytes.
+bool lists_usable(const Sizes& s) {
+  const long lanes = (long)(s.nblk > 0 ? s.nblk : 1) * kBlock;
+  return (long)s.n < (1L << (s.dim == 3 ? 27 : 28)) &&
+         lanes * list_cap(s.dim, s.G) * (long)sizeof(unsigned) < (1L << 31);
+}
 
 // One step's tape: the sorted state before the step (order n), the raw
 // correction sum and limiter value at step n, the permutation from order

@@ -168,6 +168,12 @@ __device__ __forceinline__ void decode_cell(const Grid& g, int cell, int c[3]) {
 template <int D>
 constexpr int list_jbits() { return D == 3 ? 27 : 28; }
 
+// Whether the force sweep over stored lists stages its neighbours' body values
+// in LDS: uniform 2-D FP32 (in FP64 the twice larger stage costs more
+// occupancy than it saves).
+template <int D, typename T, bool VAR>
+constexpr bool body_stage_on() { return D == 2 && !VAR && sizeof(T) == 4; }
+
 template <int D>
 constexpr unsigned cell_code(int dx, int dy, int dz) {
   return D == 3 ? (unsigned)((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1))
@@ -937,8 +943,8 @@ struct PairIn {
   T o[D], v[D], rho, m, h;
 };
 
-// Runs the pair body over lane L's stored list in batches of four: the four
-// entries are read together, then fetch(e) for the four entries (their
+// Runs the pair body over lane L's stored list in batches of two: the two
+// entries are read together, then fetch(e) for both entries (their
 // loads issued together; past the list's end the last entry is fetched
 // again and not used), then compute(values, shift) for each in order.  A
 // lane whose list is incomplete walks its candidates instead, with
@@ -953,16 +959,16 @@ __device__ __forceinline__ void for_each_neighbour_stored(const Grid& g, const C
                                                           Compute&& compute) {
   constexpr int CAP = list_cap(D, G);
   constexpr int JB = list_jbits<D>();
-  constexpr unsigned JMASK = (1u << JB) - 1u;
   const int L = blockIdx.x * kBlock + threadIdx.x;
   const int cnt = sl.count[L];
   if (cnt <= CAP) {
-    const unsigned* __restrict__ col = sl.entry + L;
-    constexpr int B = 4;
+    constexpr int B = 2;
     for (int q0 = 0; q0 < cnt; q0 += B) {
+      // rows q0 .. q0 + B - 1 (clamped to the list's rows: the same for every lane,
+      // so the row address is scalar); entries past a lane's count are not used
       unsigned e[B];
 #pragma unroll
-      for (int u = 0; u < B; ++u) e[u] = col[(size_t)min(q0 + u, cnt - 1) * sl.stride];
+      for (int u = 0; u < B; ++u) e[u] = (sl.entry + (size_t)min(q0 + u, CAP - 1) * sl.stride)[L];
       decltype(fetch(0u)) nb[B];
 #pragma unroll
       for (int u = 0; u < B; ++u) nb[u] = fetch(e[u]);
@@ -979,7 +985,7 @@ __device__ __forceinline__ void for_each_neighbour_stored(const Grid& g, const C
     for_each_candidate<D, G>(g, k, cell, cs, sub, [&](int j, const T* sh) {
       T v[NS];
       src(j, v);
-      if (test(j, v, sh)) compute(fetch((unsigned)j), sh);
+      if (test(j, v, sh)) compute(fetch((unsigned)j), sh);   // no code, not staged
     });
   }
 }

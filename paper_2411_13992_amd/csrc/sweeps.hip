@@ -258,7 +258,7 @@ __device__ __forceinline__ void forces_impl(
   stage_positions<D, G>(g, cell, cs, st, srct);
   // with stored lists in uniform 2-D FP32, the neighbours' body values in LDS
   // (in FP64 the twice larger stage costs more occupancy than it saves)
-  constexpr bool BSTAGE = LIST && D == 2 && !VAR && sizeof(T) == 4;
+  constexpr bool BSTAGE = LIST && body_stage_on<D, T, VAR>();
   constexpr int BCAP = BSTAGE ? 256 : 1;
   __shared__ BodyStage<T, BCAP> bst;
   if constexpr (BSTAGE) stage_bodies<G>(g, cell, cs, off, vel, rho, bst);
