@@ -15,8 +15,9 @@ Prints one JSON line.  The default workload is the benchmark; the others
 print the same line format.  `value` is FP32 pair interactions per second (ordered
 neighbour pairs j != i with r < 2h, counted by the step itself, divided by the
 step time).  Extra fields: the FP64 rate, the adjoint / forward time ratio,
-the roofline of the dominant kernel (the force sweep, timed live with HIP
-events on its stream) and the FP64 CPU oracle's rate on a bounded sample.
+the roofline of the dominant kernel (the force sweep over stored neighbour
+lists, timed live with HIP events on its stream) and the FP64 CPU oracle's
+rate on a bounded sample.
 """
 from __future__ import annotations
 
@@ -115,7 +116,7 @@ def step_bounds(n: int, pairs: float, t_step: float) -> dict:
             "attainable_us": t_bound * 1e6, "attainable_frac": t_bound / t_step}
 
 
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "forces_kernel_tg2d_400_f32_pmc.md")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "forces_list_kernel_tg2d_400_f32_pmc.md")
 PMC_COPY_BYTES = 64 << 20
 KERNEL_SOURCES = os.path.join(ROOT, "paper_2411_13992_amd", "csrc")
 
@@ -173,19 +174,26 @@ def time_adjoint(sim, steps, every):
 
 
 def kernel_roofline(sim, pairs, dtype, reps=200, use_pmc=True):
-    """Average duration of the force sweep launch (sph_forces on the benchmark
-    state, same kernel and launch shape as inside the step), by HIP events on
-    the stream it runs on."""
+    """Average duration of the force sweep over stored neighbour lists
+    (sph_forces_lists after sph_density_lists on the benchmark state: the
+    step's force sweep without its fused correction sum and kick-drift
+    epilogue, same lists, stage and launch shape), by HIP events on the
+    stream it runs on; the density sweep that records the lists (the step's
+    own kernel) is timed the same way."""
     import torch
+    lists = sim.neighbor_lists()
+    rho = torch.empty_like(sim.rho)
     out = torch.empty_like(sim.acc)
-    sim.forces(out=out)
-    t = _events_time(lambda: sim.forces(out=out), reps)
+    sim.density_lists(lists, out=rho)
+    sim.forces_lists(lists, out=out)
+    t = _events_time(lambda: sim.forces_lists(lists, out=out), reps)
+    t_density = _events_time(lambda: sim.density_lists(lists, out=rho), reps)
     flops = FORCE_FLOPS_PER_PAIR[sim.dim] * pairs
     bytes_ = force_bytes_per_particle(sim.dim, dtype, sim.var) * sim.n
     achieved = flops / t / 1e12
     traffic = _pmc_traffic() if use_pmc else None
     return {
-        "kernel": "forces_kernel",
+        "kernel": "forces_list_kernel",
         "bound": "alu",
         "achieved": achieved,
         "peak": VALU_FP32_PEAK_TFLOPS,
@@ -200,6 +208,7 @@ def kernel_roofline(sim, pairs, dtype, reps=200, use_pmc=True):
         "algorithmic_flops_per_launch": flops,
         "algorithmic_bytes_per_launch": bytes_,
         "hbm_frac": bytes_ / t / HBM_PEAK,
+        "density_list_kernel_us": t_density * 1e6,
     }
 
 
@@ -360,18 +369,20 @@ def main():
     default = args.workload == WORKLOAD
     sim = Simulation.from_case(case, dtype="f32")
     if args.pmc:
-        # 20 launches each of the standalone force and density sweeps, FP32
-        # then FP64, on the benchmark state after the warm-up steps, then one
-        # copy of known size to calibrate the byte counters
+        # 20 launches each of the list sweeps (density recording the lists,
+        # forces over them), FP32 then FP64, on the benchmark state after the
+        # warm-up steps, then one copy of known size to calibrate the byte
+        # counters
         for dt in ("f32", "f64"):
             s = sim if dt == "f32" else Simulation.from_case(case, dtype="f64")
             s.run(args.warmup)
+            lists = s.neighbor_lists()
             out = torch.empty_like(s.acc)
             rho = torch.empty_like(s.rho)
             for _ in range(20):
-                s.forces(out=out)
+                s.density_lists(lists, out=rho)
             for _ in range(20):
-                s.density(out=rho)
+                s.forces_lists(lists, out=out)
             torch.cuda.synchronize()
         src = torch.ones(PMC_COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -203,6 +203,29 @@ int32_t sph_density(const sph_params *p, const sph_particles *parts,
 int32_t sph_forces(const sph_params *p, const sph_particles *parts,
                    const int32_t *cell_start, const void *vel, void *acc_out, void *stream);
 
+/* Bytes of the stored neighbour lists of sph_density_lists and
+ * sph_forces_lists for these parameters; 0 when the lists cannot index this
+ * many particles (2^28 in 2-D, 2^27 in 3-D) or would pass 2^31 bytes, and
+ * the two calls then return SPH_E_UNSUPPORTED. */
+int32_t sph_list_size(const sph_params *p, size_t *bytes);
+
+/* sph_density (Eq. 8) that also records every particle's neighbours, in the
+ * sweep's own visiting order, into lists (device, caller-owned, list_bytes
+ * >= sph_list_size; an opaque layout) for sph_forces_lists at the same
+ * positions.  rho_out equals sph_density's bit for bit.  The kick-drift-kick
+ * runs do the same inside every step. */
+int32_t sph_density_lists(const sph_params *p, const sph_particles *parts,
+                          const int32_t *cell_start, void *rho_out, void *lists,
+                          size_t list_bytes, void *stream);
+
+/* sph_forces (Eq. 2, 3b, 5-7) over the lists sph_density_lists recorded for
+ * the same sorted positions, cell_start and params: the sweep tests no
+ * candidates.  acc_out equals sph_forces' bit for bit.  Lists of another
+ * state give wrong accelerations (they are not checked). */
+int32_t sph_forces_lists(const sph_params *p, const sph_particles *parts,
+                         const int32_t *cell_start, const void *vel, void *acc_out,
+                         const void *lists, size_t list_bytes, void *stream);
+
 /* Wall particles (the lid-driven cavity of Sec. 4.2; the paper names no wall
  * treatment, this is the library's): params.n_wall > 0 marks the particles
  * with id >= n - n_wall as walls.  They stay where they are, take part in

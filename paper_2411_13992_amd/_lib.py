@@ -35,7 +35,8 @@ DIAG_NAMES = ("ke", "px", "py", "pz", "vmax", "npairs", "nbeta", "nband", "trans
 # entry points declared in include/sph.h, in declaration order
 EXPORTS = (
     "sph_workspace_size", "sph_tape_size", "sph_lattice_kappa", "sph_bin_positions",
-    "sph_build_cells", "sph_density", "sph_forces", "sph_wall_state", "sph_tv_correction",
+    "sph_build_cells", "sph_density", "sph_forces", "sph_list_size", "sph_density_lists",
+    "sph_forces_lists", "sph_wall_state", "sph_tv_correction",
     "sph_kdk_step",
     "sph_kdk_run", "sph_kdk_run_static", "sph_dual_run", "sph_diagnostics", "sph_adjoint_step", "sph_adjoint_init", "sph_neighbor_counts",
     "sph_get_flags", "sph_clear_flags", "sph_status_string",
@@ -103,6 +104,9 @@ def load():
         "sph_build_cells": [pp, P(SphParticles), vp, vp, vp, ctypes.c_size_t, vp],
         "sph_density": [pp, P(SphParticles), vp, vp, vp],
         "sph_forces": [pp, P(SphParticles), vp, vp, vp, vp],
+        "sph_list_size": [pp, P(ctypes.c_size_t)],
+        "sph_density_lists": [pp, P(SphParticles), vp, vp, vp, ctypes.c_size_t, vp],
+        "sph_forces_lists": [pp, P(SphParticles), vp, vp, vp, vp, ctypes.c_size_t, vp],
         "sph_wall_state": [pp, P(SphParticles), vp, vp],
         "sph_tv_correction": [pp, P(SphParticles), vp, vp, vp, vp, vp, vp],
         "sph_kdk_step": [pp, P(SphParticles), vp, ctypes.c_int64, vp, ctypes.c_size_t, vp, vp,
@@ -143,6 +147,12 @@ def call(fn: str, *args) -> None:
 def workspace_size(params: SphParams) -> int:
     out = ctypes.c_size_t(0)
     call("sph_workspace_size", ctypes.byref(params), ctypes.byref(out))
+    return int(out.value)
+
+
+def list_size(params: SphParams) -> int:
+    out = ctypes.c_size_t(0)
+    call("sph_list_size", ctypes.byref(params), ctypes.byref(out))
     return int(out.value)
 
 

@@ -437,30 +437,36 @@ __global__ __launch_bounds__(kBlock) void zero_walls_kernel(Coeffs<T> k, int n, 
 }
 
 // ------------------------------------------------------------------ correction^T, pass 1
+// The cell build's permutation reversed, and the first pass of the
+// correction's VJP, in one pass over the new order q: i = perm[q] is q's
+// index in order n; r_n[i] and vh_n[i] take r_bar[q] and v_bar[q], and
 // ghat_i = d(dr_i)/dg_i ^T rbar_i for the chosen formulation (beta_i from the
 // tape is 0 on steps without correction, which zeroes every term):
 //   limited:    xi h^2 (beta_i rbar_i + 2 C h^2 (g_i . rbar_i) g_i [ramp branch only])
 //   scaled:     xi h^2 beta_i rbar_i
 //   background: -(rho0 c0^2 dt^2 / rho_i) beta_i rbar_i
-// and per-wavefront partials of the xi derivative sum_i h^2 beta_i g_i . rbar_i
-// (none for the background formulation, which has no xi).
+// with per-wavefront partials (q order) of the xi derivative
+// sum_i h^2 beta_i g_i . rbar_i (none for the background formulation, which
+// has no xi).
 template <int D, typename T>
-__global__ __launch_bounds__(kBlock) void tv_ghat_kernel(Coeffs<T> k, int n,
-                                                         const T* __restrict__ gsum,
-                                                         const T* __restrict__ beta,
-                                                         const T* __restrict__ rho,
-                                                         const T* __restrict__ r_bar,
-                                                         T* __restrict__ ghat,
-                                                         double* __restrict__ partials) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void unpermute_ghat_kernel(
+    Coeffs<T> k, int n, const int* __restrict__ perm, const T* __restrict__ r_bar,
+    const T* __restrict__ v_bar, const T* __restrict__ gsum, const T* __restrict__ beta,
+    const T* __restrict__ rho, T* __restrict__ r_n, T* __restrict__ vh_n, T* __restrict__ ghat,
+    double* __restrict__ partials) {
+  const int q = blockIdx.x * kBlock + threadIdx.x;
   double xi_part = 0.0;
-  if (i < n) {
+  if (q < n) {
+    const int i = perm[q];
     double gg = 0.0, gr = 0.0;
     double gi[3], ri[3];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
+      const T rq = r_bar[d * n + q];
+      r_n[d * n + i] = rq;
+      vh_n[d * n + i] = v_bar[d * n + q];
       gi[d] = (double)gsum[d * n + i];
-      ri[d] = (double)r_bar[d * n + i];
+      ri[d] = (double)rq;
       gg += gi[d] * gi[d];
       gr += gi[d] * ri[d];
     }
@@ -496,7 +502,14 @@ __global__ __launch_bounds__(kBlock) void tv_vjp_kernel(
     const T* __restrict__ off, const T* __restrict__ rho, const T* __restrict__ mass,
     const T* __restrict__ hh, const T* __restrict__ ghat, const T* __restrict__ gsum,
     const T* __restrict__ beta, const T* __restrict__ r_in, T* __restrict__ r_out,
-    T* __restrict__ rho_out) {
+    T* __restrict__ rho_out, AdjFinish<T> fin) {
+  if (fin.xi_bar && (int)blockIdx.x == (int)gridDim.x - 1) {
+    // the extra last block folds the xi partials of the ghat pass (fixed order)
+    __shared__ double red[kBlock / kWave];
+    const double t = block_reduce<double, false>(fold_rows<false>(fin.xi_partials, fin.xi_rows), red);
+    if (threadIdx.x == 0) fin.xi_bar[0] += t;
+    return;
+  }
   const int n = g.n;
   const Cols<T, D> offc(off, n), ghatc(ghat, n);
   const Cols<T, 1> rhoc(rho, n), hc(hh, n), mc(mass, n);
@@ -574,20 +587,20 @@ __global__ __launch_bounds__(kBlock) void tv_vjp_kernel(
     if (k.tv_mode == kTvBackground)
       rb = (T)((double)rb + k.bg * (double)beta[i] / ((double)rhoi * (double)rhoi) * direct);
     rho_out[i] = rb;
+    // 2^T: v' = v^n + dt/2 a^n (fluid): v_bar^n = v'_bar, a_bar^n = dt/2 v'_bar
+    if (fin.v_bar) {
+      const bool wall = fin.id && fin.id[i] >= k.nfluid;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const T v = wall ? T(0) : fin.vh_bar[d * n + i];
+        fin.v_bar[d * n + i] = v;
+        fin.a_bar[d * n + i] = k.half_dt * v;
+      }
+    }
   }
 }
 
 // ------------------------------------------------------------------ elementwise
-template <typename T>
-__global__ __launch_bounds__(kBlock) void unpermute_kernel(int n, int ncomp, const int* __restrict__ perm,
-                                                           const T* __restrict__ src,
-                                                           T* __restrict__ dst) {
-  const int q = blockIdx.x * kBlock + threadIdx.x;
-  if (q >= n) return;
-  const int p = perm[q];
-  for (int d = 0; d < ncomp; ++d) dst[d * n + p] = src[d * n + q];
-}
-
 // Wall particles (told by id when id is given) are not kicked: their
 // velocity cotangent is that of the wall state, not of a kick, and their
 // acceleration is not an output (its cotangent is cleared).
@@ -600,28 +613,6 @@ __global__ __launch_bounds__(kBlock) void adj_kick_kernel(long dn, int n, T half
   if (i >= dn) return;
   if (id && id[i % n] >= nfluid) a_bar[i] = T(0);
   else a_bar[i] += half_dt * v_bar[i];
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void adj_finish_kernel(long dn, int n, T half_dt, int nfluid,
-                                                            const int* __restrict__ id,
-                                                            const T* __restrict__ vh_bar,
-                                                            T* __restrict__ v_bar,
-                                                            T* __restrict__ a_bar) {
-  const long i = (long)blockIdx.x * kBlock + threadIdx.x;
-  if (i < dn) {
-    const bool wall = id && id[i % n] >= nfluid;
-    const T v = wall ? T(0) : vh_bar[i];
-    v_bar[i] = v;
-    a_bar[i] = half_dt * v;
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void xi_final_kernel(int nrows, const double* __restrict__ partials,
-                                                          double* __restrict__ xi_bar) {
-  __shared__ double red[kBlock / kWave];
-  const double t = block_reduce<double, false>(fold_rows<false>(partials, nrows), red);
-  if (threadIdx.x == 0) xi_bar[0] += t;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -643,33 +634,32 @@ void launch_density_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, cons
 }
 
 template <typename T>
-void launch_tv_ghat(const Launch& l, const Coeffs<T>& k, int n, const T* gsum, const T* beta,
-                    const T* rho, const T* r_bar, T* ghat, double* partials) {
-  if (n == 0) return;
-  // one thread per particle: the partials' first ceil(n / kBlock) * waves-per-block rows
-  const dim3 grid((n + kBlock - 1) / kBlock);
-  if (l.dim == 2)
-    hipLaunchKernelGGL((tv_ghat_kernel<2, T>), grid, dim3(kBlock), 0, l.stream, k, n, gsum, beta,
-                       rho, r_bar, ghat, partials);
-  else
-    hipLaunchKernelGGL((tv_ghat_kernel<3, T>), grid, dim3(kBlock), 0, l.stream, k, n, gsum, beta,
-                       rho, r_bar, ghat, partials);
-}
-
-template <typename T>
 void launch_tv_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                    const int* cs, const T* ghat, const T* gsum, const T* beta, const T* r_in,
-                   T* r_out, T* rho_out) {
+                   T* r_out, T* rho_out, const AdjFinish<T>& fin) {
   if (g.n == 0) return;
-  SPH_SWEEP(tv_vjp_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.rho, p.mass, p.h, ghat, gsum,
-                                    beta, r_in, r_out, rho_out));
+  // with xi_bar, one extra block folds the xi partials
+  Launch lx = l;
+  if (fin.xi_bar) lx.nblk = l.nblk + 1;
+  {
+    const Launch& l = lx;
+    SPH_SWEEP(tv_vjp_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.rho, p.mass, p.h, ghat, gsum,
+                                      beta, r_in, r_out, rho_out, fin));
+  }
 }
 
 template <typename T>
-void launch_unpermute(const Launch& l, int n, const int* perm, const T* src, T* dst, int ncomp) {
+void launch_unpermute_ghat(const Launch& l, const Coeffs<T>& k, int n, const int* perm,
+                           const T* r_bar, const T* v_bar, const T* gsum, const T* beta,
+                           const T* rho, T* r_n, T* vh_n, T* ghat, double* partials) {
   if (n == 0) return;
-  hipLaunchKernelGGL((unpermute_kernel<T>), dim3(blocks_for(n)), dim3(kBlock), 0, l.stream, n,
-                     ncomp, perm, src, dst);
+  const dim3 grid(blocks_for(n));
+  if (l.dim == 2)
+    hipLaunchKernelGGL((unpermute_ghat_kernel<2, T>), grid, dim3(kBlock), 0, l.stream, k, n, perm,
+                       r_bar, v_bar, gsum, beta, rho, r_n, vh_n, ghat, partials);
+  else
+    hipLaunchKernelGGL((unpermute_ghat_kernel<3, T>), grid, dim3(kBlock), 0, l.stream, k, n, perm,
+                       r_bar, v_bar, gsum, beta, rho, r_n, vh_n, ghat, partials);
 }
 
 template <typename T>
@@ -679,15 +669,6 @@ void launch_adj_kick(const Launch& l, const Coeffs<T>& k, int n, const int* id, 
   if (dn == 0) return;
   hipLaunchKernelGGL((adj_kick_kernel<T>), dim3(blocks_for(dn)), dim3(kBlock), 0, l.stream, dn,
                      n, k.half_dt, k.nfluid, id, v_bar, a_bar);
-}
-
-template <typename T>
-void launch_adj_finish(const Launch& l, const Coeffs<T>& k, int n, const int* id,
-                       const T* vhalf_bar, T* v_bar, T* a_bar) {
-  const long dn = (long)l.dim * n;
-  if (dn == 0) return;
-  hipLaunchKernelGGL((adj_finish_kernel<T>), dim3(blocks_for(dn)), dim3(kBlock), 0, l.stream, dn,
-                     n, k.half_dt, k.nfluid, id, vhalf_bar, v_bar, a_bar);
 }
 
 // wall_cells[c] = 1 for the cells holding a wall particle (cells cleared first)
@@ -724,27 +705,20 @@ void launch_zero_walls(const Launch& l, const Coeffs<T>& k, int n, const int* id
                      n, ncomp, id, x, y);
 }
 
-void launch_xi_final(hipStream_t s, int n, const double* partials, double* xi_bar) {
-  const int nrows = (n + kBlock - 1) / kBlock * kWavesPerBlock;
-  hipLaunchKernelGGL(xi_final_kernel, dim3(1), dim3(kBlock), 0, s, nrows, partials, xi_bar);
-}
-
 #define SPH_INST(T)                                                                          \
   template void launch_force_vjp<T>(const Launch&, const Grid&, const Coeffs<T>&,            \
                                     const PArrays<T>&, const int*, const T*, const T*, T*,   \
                                     T*, T*);                                                 \
   template void launch_density_vjp<T>(const Launch&, const Grid&, const Coeffs<T>&,          \
                                       const PArrays<T>&, const int*, const T*, T*, T*, T);   \
-  template void launch_tv_ghat<T>(const Launch&, const Coeffs<T>&, int, const T*, const T*,  \
-                                  const T*, const T*, T*, double*);                          \
   template void launch_tv_vjp<T>(const Launch&, const Grid&, const Coeffs<T>&,               \
                                  const PArrays<T>&, const int*, const T*, const T*,          \
-                                 const T*, const T*, T*, T*);                                \
-  template void launch_unpermute<T>(const Launch&, int, const int*, const T*, T*, int);      \
+                                 const T*, const T*, T*, T*, const AdjFinish<T>&);           \
+  template void launch_unpermute_ghat<T>(const Launch&, const Coeffs<T>&, int, const int*,   \
+                                         const T*, const T*, const T*, const T*, const T*,   \
+                                         T*, T*, T*, double*);                               \
   template void launch_adj_kick<T>(const Launch&, const Coeffs<T>&, int, const int*,          \
                                    const T*, T*);                                            \
-  template void launch_adj_finish<T>(const Launch&, const Coeffs<T>&, int, const int*,        \
-                                     const T*, T*, T*);                                      \
   template void launch_wall_vjp<T>(const Launch&, const Grid&, const Coeffs<T>&,             \
                                    const PArrays<T>&, const int*, const T*, T*, T*, int,     \
                                    bool, int*, T*, T*, T*);                                  \

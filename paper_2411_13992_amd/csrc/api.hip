@@ -151,6 +151,21 @@ WsLayout ws_layout(const Sizes& s) {
   return w;
 }
 
+// A caller's stored-list buffer (sph_list_size bytes): entries, then counts.
+struct ListLayout {
+  size_t entries, counts, total;
+};
+ListLayout list_layout(const Sizes& s) {
+  ListLayout ll{0, 0, 0};
+  if (!lists_usable(s)) return ll;
+  Cursor c;
+  const size_t lanes = (size_t)(s.nblk > 0 ? s.nblk : 1) * kBlock;
+  ll.entries = c.take(sizeof(unsigned) * lanes * list_cap(s.dim, s.G));
+  ll.counts = c.take(sizeof(int) * lanes);
+  ll.total = c.o;
+  return ll;
+}
+
 TapeLayout tape_layout(const Sizes& s) {
   Cursor c;
   TapeLayout tl;
@@ -334,6 +349,9 @@ Launch launch_of(const sph_params* p, bool var, void* stream) {
   return l;
 }
 
+// a tape record that does not fit one copy batch (never with these layouts)
+constexpr int32_t SPH_E_INTERNAL_COPY = SPH_E_HIP;
+
 hipError_t copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
   if (bytes == 0) return hipSuccess;
   return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
@@ -413,33 +431,35 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs_calle
   auto applies = [&](int64_t s) { return p->tv_every > 0 && (s % p->tv_every) == 0; };
   const TapeLayout tl = tape_layout(sz);
   auto tape_of = [&](int64_t s) { return tapes + (size_t)s * tl.total; };
-  // the sorted state (cell, offsets, density, mass, h, cell_start) into a tape
-  auto record_state = [&](char* tp, size_t o_cell, size_t o_off, size_t o_rho, size_t o_mass,
-                          size_t o_h, size_t o_cs, size_t o_id) {
-    hipError_t e = hipSuccess;
-    e = e ? e : copy_d2d(tp + o_cell, a.cell, sizeof(int) * n, stream);
-    if (p->n_wall > 0) e = e ? e : copy_d2d(tp + o_id, a.id, sizeof(int) * n, stream);
-    e = e ? e : copy_d2d(tp + o_off, a.off, t * dn, stream);
-    e = e ? e : copy_d2d(tp + o_rho, a.rho, t * n, stream);
+  // the sorted state (cell, offsets, density, mass, h, cell_start) into a
+  // tape; the copies of one record go out in one launch
+  auto record_state = [&](CopyBatch& b, char* tp, size_t o_cell, size_t o_off, size_t o_rho,
+                          size_t o_mass, size_t o_h, size_t o_cs, size_t o_id) {
+    bool ok = b.add(tp + o_cell, a.cell, sizeof(int) * n);
+    if (p->n_wall > 0) ok = ok && b.add(tp + o_id, a.id, sizeof(int) * n);
+    ok = ok && b.add(tp + o_off, a.off, t * dn);
+    ok = ok && b.add(tp + o_rho, a.rho, t * n);
     if (var) {
-      e = e ? e : copy_d2d(tp + o_mass, a.mass, t * n, stream);
-      e = e ? e : copy_d2d(tp + o_h, a.h, t * n, stream);
+      ok = ok && b.add(tp + o_mass, a.mass, t * n);
+      ok = ok && b.add(tp + o_h, a.h, t * n);
     }
-    e = e ? e : copy_d2d(tp + o_cs, cs, csb, stream);
-    return e;
+    return ok && b.add(tp + o_cs, cs, csb);
   };
-  auto record_pre = [&](char* tp) {
-    return record_state(tp, tl.pre_cell, tl.pre_off, tl.pre_rho, tl.pre_mass, tl.pre_h,
+  auto record_pre = [&](CopyBatch& b, char* tp) {
+    return record_state(b, tp, tl.pre_cell, tl.pre_off, tl.pre_rho, tl.pre_mass, tl.pre_h,
                         tl.pre_cs, tl.pre_id);
   };
-  auto record_post = [&](char* tp) {
-    hipError_t e = record_state(tp, tl.post_cell, tl.post_off, tl.post_rho, tl.post_mass,
-                                tl.post_h, tl.post_cs, tl.post_id);
-    e = e ? e : copy_d2d(tp + tl.perm, perm, sizeof(int) * n, stream);
-    e = e ? e : copy_d2d(tp + tl.post_vhalf, a.vel, t * dn, stream);
-    return e;
+  auto record_post = [&](CopyBatch& b, char* tp) {
+    bool ok = record_state(b, tp, tl.post_cell, tl.post_off, tl.post_rho, tl.post_mass,
+                           tl.post_h, tl.post_cs, tl.post_id);
+    ok = ok && b.add(tp + tl.perm, perm, sizeof(int) * n);
+    return ok && b.add(tp + tl.post_vhalf, a.vel, t * dn);
   };
-  if (tapes && record_pre(tape_of(0)) != hipSuccess) return SPH_E_HIP;
+  if (tapes) {
+    CopyBatch b{};
+    if (!record_pre(b, tape_of(0))) return SPH_E_INTERNAL_COPY;
+    launch_multi_copy(stream, b);
+  }
   launch_fill(stream, cb.counts, cb.fill_ints, 0);
   if (diag) launch_zero_partials(stream, sz.nblk, part[0]);
 
@@ -483,16 +503,17 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs_calle
     cs = csbuf[cur];
     // 4. density summation (Eq. 8), recording the neighbours for the fused
     // force sweep; wall particles from the fluid
-    const StoredList step_sl = s + 1 < nsteps ? sl : StoredList{};
-    launch_density<T>(l, g, k, a, cs, a.rho, cur_part, nullptr, flags, step_sl);
+    launch_density<T>(l, g, k, a, cs, a.rho, cur_part, nullptr, flags, sl);
     launch_wall_state<T>(l, g, k, a, cs, (const T*)parts->wall_vel, (int)p->n_wall,
                          tapes ? (T*)(tape_of(s) + tl.wsum) : nullptr,
                          tapes ? (T*)(tape_of(s) + tl.wavg) : nullptr);
     if (tapes) {
       // the state after this step (half-step velocity, new density, the
       // walls' state) is the state before the next
-      if (record_post(tape_of(s)) != hipSuccess) return SPH_E_HIP;
-      if (s + 1 < nsteps && record_pre(tape_of(s + 1)) != hipSuccess) return SPH_E_HIP;
+      CopyBatch b{};
+      if (!record_post(b, tape_of(s))) return SPH_E_INTERNAL_COPY;
+      if (s + 1 < nsteps && !record_pre(b, tape_of(s + 1))) return SPH_E_INTERNAL_COPY;
+      launch_multi_copy(stream, b);
     }
     if (s + 1 < nsteps) {
       // 5-6. accelerations, 7. kick; the next step's correction and drift
@@ -515,10 +536,10 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs_calle
           launch_zero<T>(stream, (T*)(tn + tl.beta), (long)n);
         }
       }
-      launch_forces_fused<T>(l, g, k, a, cs, fo, flags, step_sl);
+      launch_forces_fused<T>(l, g, k, a, cs, fo, flags, sl);
     } else {
       // 5-6. accelerations at (r^{n+1}, v', rho^{n+1}), 7. second half kick
-      launch_forces<T>(l, g, k, a, cs, a.vel, a.acc, flags);
+      launch_forces<T>(l, g, k, a, cs, a.vel, a.acc, flags, sl);
       launch_kick<T>(l, k, sz.n, a.vel, a.acc, a.mass, a.id, cur_part, true, flags);
       if (diag) launch_diag_fold(stream, DiagFold{cur_part, sz.nblk * kWavesPerBlock, diag + (size_t)SPH_NDIAG * s});
     }
@@ -646,18 +667,16 @@ int32_t adjoint_step_t(const sph_params* p, const char* tape, sph_adjoint* adj, 
                        r_bar, v_bar, rho_bar);
   // 4^T: density, then 2-3^T: r^{n+1} = r^n + dt v' + dr  =>  v'bar += dt rbar
   launch_density_vjp<T>(l, g, k, post, cs_post, rho_bar, r_bar, v_bar, k.dt);
-  // the cell build is a permutation: back to order n
+  // the cell build is a permutation: back to order n, with 1^T's first part
+  // (ghat of the correction dr = T(r^n, rho^n; xi) and the xi partials)
   const int* perm = (const int*)(tape + tl.perm);
-  launch_unpermute<T>(l, sz.n, perm, r_bar, r_n, sz.dim);
-  launch_unpermute<T>(l, sz.n, perm, v_bar, vh_n, sz.dim);
-  // 1^T: the correction dr = T(r^n, rho^n; xi)
-  launch_tv_ghat<T>(l, k, sz.n, (const T*)(tape + tl.g), (const T*)(tape + tl.beta), pre.rho, r_n,
-                    ghat, partials);
-  if (xi_bar) launch_xi_final(stream, sz.n, partials, xi_bar);
+  launch_unpermute_ghat<T>(l, k, sz.n, perm, r_bar, v_bar, (const T*)(tape + tl.g),
+                           (const T*)(tape + tl.beta), pre.rho, r_n, vh_n, ghat, partials);
+  // 1^T's gather, then 2^T: v' = v^n + dt/2 a^n (fluid), and the xi fold
+  AdjFinish<T> fin{pre.id, vh_n, v_bar, a_bar, partials, blocks_for(sz.n) * kWavesPerBlock,
+                   xi_bar};
   launch_tv_vjp<T>(l, g, k, pre, cs_pre, ghat, (const T*)(tape + tl.g),
-                   (const T*)(tape + tl.beta), r_n, r_bar, rho_bar);
-  // 2^T: v' = v^n + dt/2 a^n (fluid)
-  launch_adj_finish<T>(l, k, sz.n, pre.id, vh_n, v_bar, a_bar);
+                   (const T*)(tape + tl.beta), r_n, r_bar, rho_bar, fin);
   return hip_status();
 }
 
@@ -821,6 +840,70 @@ int32_t sph_density(const sph_params* p, const sph_particles* parts, const int32
     using T = decltype(tag);
     launch_density<T>(l, g, coeffs_of<T>(p, g), arrays_of<T>(parts), cell_start, (T*)rho_out,
                       nullptr, nullptr, nullptr);
+    return hip_status();
+  });
+}
+
+int32_t sph_list_size(const sph_params* p, size_t* bytes) {
+  int32_t st = check_params(p);
+  if (st != SPH_OK) return st;
+  if (!bytes) return SPH_E_ARG;
+  *bytes = list_layout(sizes_of(p, is_var(p))).total;
+  return SPH_OK;
+}
+
+static int32_t list_of(const sph_params* p, const void* lists, size_t list_bytes,
+                       StoredList* out) {
+  const Sizes sz = sizes_of(p, is_var(p));
+  const ListLayout ll = list_layout(sz);
+  if (ll.total == 0) return SPH_E_UNSUPPORTED;
+  if (!lists) return SPH_E_ARG;
+  if (list_bytes < ll.total) return SPH_E_WORKSPACE;
+  char* b = (char*)const_cast<void*>(lists);
+  *out = StoredList{(unsigned*)(b + ll.entries), (int*)(b + ll.counts), sz.nblk * kBlock};
+  return SPH_OK;
+}
+
+int32_t sph_density_lists(const sph_params* p, const sph_particles* parts,
+                          const int32_t* cell_start, void* rho_out, void* lists,
+                          size_t list_bytes, void* stream) {
+  int32_t st = check_params(p);
+  if (st != SPH_OK) return st;
+  st = check_particles(p, parts, false);
+  if (st != SPH_OK) return st;
+  StoredList sl{};
+  st = list_of(p, lists, list_bytes, &sl);
+  if (st != SPH_OK) return st;
+  if (p->n == 0) return SPH_OK;
+  if (!cell_start || !rho_out) return SPH_E_ARG;
+  const Grid g = grid_of(p);
+  const Launch l = launch_of(p, is_var(p), stream);
+  return dispatch(p, [&](auto tag) {
+    using T = decltype(tag);
+    launch_density<T>(l, g, coeffs_of<T>(p, g), arrays_of<T>(parts), cell_start, (T*)rho_out,
+                      nullptr, nullptr, nullptr, sl);
+    return hip_status();
+  });
+}
+
+int32_t sph_forces_lists(const sph_params* p, const sph_particles* parts,
+                         const int32_t* cell_start, const void* vel, void* acc_out,
+                         const void* lists, size_t list_bytes, void* stream) {
+  int32_t st = check_params(p);
+  if (st != SPH_OK) return st;
+  st = check_particles(p, parts, false);
+  if (st != SPH_OK) return st;
+  StoredList sl{};
+  st = list_of(p, lists, list_bytes, &sl);
+  if (st != SPH_OK) return st;
+  if (p->n == 0) return SPH_OK;
+  if (!cell_start || !vel || !acc_out || !parts->rho) return SPH_E_ARG;
+  const Grid g = grid_of(p);
+  const Launch l = launch_of(p, is_var(p), stream);
+  return dispatch(p, [&](auto tag) {
+    using T = decltype(tag);
+    launch_forces<T>(l, g, coeffs_of<T>(p, g), arrays_of<T>(parts), cell_start, (const T*)vel,
+                     (T*)acc_out, nullptr, sl);
     return hip_status();
   });
 }

@@ -47,6 +47,38 @@ void launch_stage_copy(const Launch& l, int n, const PArrays<T>& src, const PArr
                        n, src, stg, counts, slot);
 }
 
+// ------------------------------------------------------------------ batched copies
+// Up to kMaxCopies device-to-device copies of whole 4-byte words in one
+// launch (blockIdx.y picks the copy): 16-byte moves where both ends are
+// 16-byte aligned, 4-byte moves for the rest.  Sizes are multiples of 4.
+__global__ __launch_bounds__(kBlock) void multi_copy_kernel(CopyBatch b) {
+  const int c = blockIdx.y;
+  if (c >= b.count) return;
+  const char* __restrict__ src = b.src[c];
+  char* __restrict__ dst = b.dst[c];
+  const long words = b.bytes[c] / 4;
+  const long stride = (long)gridDim.x * kBlock;
+  long head = 0;
+  if ((((unsigned long)src | (unsigned long)dst) & 15ul) == 0) {
+    head = words / 4 * 4;
+    const uint4* __restrict__ s4 = (const uint4*)src;
+    uint4* __restrict__ d4 = (uint4*)dst;
+    for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < head / 4; i += stride) d4[i] = s4[i];
+  }
+  const unsigned* __restrict__ s1 = (const unsigned*)src;
+  unsigned* __restrict__ d1 = (unsigned*)dst;
+  for (long i = head + (long)blockIdx.x * kBlock + threadIdx.x; i < words; i += stride) d1[i] = s1[i];
+}
+
+void launch_multi_copy(hipStream_t s, const CopyBatch& b) {
+  if (b.count <= 0) return;
+  long most = 0;
+  for (int c = 0; c < b.count; ++c) most = b.bytes[c] > most ? b.bytes[c] : most;
+  const long chunks = (most / 16 + kBlock - 1) / kBlock;
+  const int bx = (int)(chunks < 1 ? 1 : (chunks > 1024 ? 1024 : chunks));
+  hipLaunchKernelGGL(multi_copy_kernel, dim3(bx, b.count), dim3(kBlock), 0, s, b);
+}
+
 // ------------------------------------------------------------------ kick + drift + rebin
 // v' = v + dt/2 a; o' = o + dt v' + dr, rebinned (drift_rebin); the moved
 // particle goes to the staging buffers and, with counts given, claims a slot

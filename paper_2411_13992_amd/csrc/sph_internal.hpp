@@ -77,9 +77,11 @@ void launch_density(const Launch& l, const Grid& g, const Coeffs<T>& k, const PA
 template <typename T>
 void launch_tv(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                const int* cs, T* dr, T* beta, double* s_out, T* g_out, double* partials);
+// with sl.entry set, over the stored lists of the density sweep just before
 template <typename T>
 void launch_forces(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
-                   const int* cs, const T* vel, T* acc_out, unsigned* flags);
+                   const int* cs, const T* vel, T* acc_out, unsigned* flags,
+                   const StoredList& sl = StoredList{});
 // with sl.entry set, over the stored lists of the density sweep just before
 template <typename T>
 void launch_forces_fused(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
@@ -191,6 +193,25 @@ void launch_rebuild(const Launch& l, const Grid& g, const RebuildArgs& a, const 
                     const PArrays<T>& dst);
 
 // ---- integration (kdk.hip)
+// Device-to-device copies of 4-byte words, up to kMaxCopies in one launch
+// (tape records).
+constexpr int kMaxCopies = 24;
+struct CopyBatch {
+  int count;
+  const char* src[kMaxCopies];
+  char* dst[kMaxCopies];
+  long bytes[kMaxCopies];
+  bool add(void* d, const void* s, size_t nbytes) {
+    if (nbytes == 0) return true;
+    if (count >= kMaxCopies || (nbytes & 3u)) return false;
+    src[count] = (const char*)s;
+    dst[count] = (char*)d;
+    bytes[count] = (long)nbytes;
+    ++count;
+    return true;
+  }
+};
+void launch_multi_copy(hipStream_t s, const CopyBatch& b);
 template <typename T>
 void launch_stage_copy(const Launch& l, int n, const PArrays<T>& src, const PArrays<T>& stg,
                        int* counts, int* slot);
@@ -214,19 +235,32 @@ void launch_force_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const 
 template <typename T>
 void launch_density_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                         const int* cs, const T* rho_bar, T* r_bar, T* v_bar, T vcoef);
+// What the correction's VJP also does for the reverse step, per particle in
+// order n: the reverse of the first half kick (v_bar = vh_bar, a_bar =
+// dt/2 vh_bar for fluid particles, 0 for walls told by id; skipped when v_bar
+// is null), and, in one extra block, the fold of the xi partials of
+// launch_unpermute_ghat into xi_bar (skipped when xi_bar is null).
 template <typename T>
-void launch_tv_ghat(const Launch& l, const Coeffs<T>& k, int n, const T* gsum, const T* beta,
-                    const T* rho, const T* r_bar, T* ghat, double* partials);
+struct AdjFinish {
+  const int* id;
+  const T* vh_bar;
+  T* v_bar;
+  T* a_bar;
+  const double* xi_partials;
+  int xi_rows;
+  double* xi_bar;
+};
 template <typename T>
 void launch_tv_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                    const int* cs, const T* ghat, const T* gsum, const T* beta, const T* r_in,
-                   T* r_out, T* rho_out);
+                   T* r_out, T* rho_out, const AdjFinish<T>& fin);
+// r_n = r_bar and vh_n = v_bar taken back to order n through perm (new ->
+// previous index), with the correction's ghat and its xi partials (one row
+// per wavefront of a one-thread-per-particle grid)
 template <typename T>
-void launch_unpermute(const Launch& l, int n, const int* perm, const T* src, T* dst, int ncomp);
-// id (optional) tells wall particles, which are neither kicked nor drifted
-template <typename T>
-void launch_adj_finish(const Launch& l, const Coeffs<T>& k, int n, const int* id,
-                       const T* vhalf_bar, T* v_bar, T* a_bar);
+void launch_unpermute_ghat(const Launch& l, const Coeffs<T>& k, int n, const int* perm,
+                           const T* r_bar, const T* v_bar, const T* gsum, const T* beta,
+                           const T* rho, T* r_n, T* vh_n, T* ghat, double* partials);
 template <typename T>
 void launch_adj_kick(const Launch& l, const Coeffs<T>& k, int n, const int* id, const T* v_bar,
                      T* a_bar);
@@ -246,8 +280,6 @@ void launch_wall_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const P
 template <typename T>
 void launch_zero_walls(const Launch& l, const Coeffs<T>& k, int n, const int* id, int ncomp,
                        T* x, T* y);
-// xi_bar += the xi partials tv_ghat wrote for n particles (one block, fixed order)
-void launch_xi_final(hipStream_t s, int n, const double* partials, double* xi_bar);
 
 // Launches a sweep kernel template KERNEL<D, T, VAR, G> on a grid of
 // n * G threads (G lanes per particle), dispatching on dimension, per-particle

@@ -499,6 +499,17 @@ __global__ __launch_bounds__(kBlock) void forces_fused_kernel(
                                          flags, fo, StoredList{});
 }
 
+// the force sweep over the density sweep's stored lists
+template <int D, typename T, bool VAR, int G>
+__global__ __launch_bounds__(kBlock) void forces_list_kernel(
+    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+    const T* __restrict__ off, const T* __restrict__ vel, const T* __restrict__ rho,
+    const T* __restrict__ mass, const T* __restrict__ hh, const int* __restrict__ id,
+    T* __restrict__ acc_out, unsigned* __restrict__ flags, FusedOut<T> fo, StoredList sl) {
+  forces_impl<D, T, VAR, false, G, true>(g, k, cell, cs, off, vel, rho, mass, hh, id, acc_out,
+                                         flags, fo, sl);
+}
+
 // the fused sweep over the density sweep's stored lists
 template <int D, typename T, bool VAR, int G>
 __global__ __launch_bounds__(kBlock) void forces_fused_list_kernel(
@@ -619,11 +630,16 @@ void launch_tv(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays
 
 template <typename T>
 void launch_forces(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
-                   const int* cs, const T* vel, T* acc_out, unsigned* flags) {
+                   const int* cs, const T* vel, T* acc_out, unsigned* flags,
+                   const StoredList& sl) {
   if (g.n == 0) return;
   FusedOut<T> none{};
-  SPH_SWEEP(forces_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, vel, p.rho, p.mass, p.h, p.id,
-                                          acc_out, flags, none));
+  if (sl.entry)
+    SPH_SWEEP(forces_list_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, vel, p.rho, p.mass, p.h,
+                                           p.id, acc_out, flags, none, sl));
+  else
+    SPH_SWEEP(forces_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, vel, p.rho, p.mass, p.h, p.id,
+                                      acc_out, flags, none));
 }
 
 template <typename T>
@@ -656,7 +672,8 @@ void launch_wall_state(const Launch& l, const Grid& g, const Coeffs<T>& k, const
   template void launch_tv<T>(const Launch&, const Grid&, const Coeffs<T>&, const PArrays<T>&,\
                              const int*, T*, T*, double*, T*, double*);                      \
   template void launch_forces<T>(const Launch&, const Grid&, const Coeffs<T>&,               \
-                                 const PArrays<T>&, const int*, const T*, T*, unsigned*);    \
+                                 const PArrays<T>&, const int*, const T*, T*, unsigned*,     \
+                                 const StoredList&);                                         \
   template void launch_forces_fused<T>(const Launch&, const Grid&, const Coeffs<T>&,         \
                                        const PArrays<T>&, const int*, const FusedOut<T>&,    \
                                        unsigned*, const StoredList&);

@@ -189,6 +189,29 @@ class Simulation:
                   _vp(self.cs), _vp(vel), _vp(out), _stream())
         return out
 
+    def neighbor_lists(self) -> torch.Tensor:
+        """A device buffer for the stored neighbour lists (sph_list_size bytes)."""
+        nbytes = _lib.list_size(self.params)
+        if nbytes == 0:
+            raise RuntimeError("stored neighbour lists cannot index this many particles")
+        return torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+
+    def density_lists(self, lists: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """sph_density that also records the neighbour lists into `lists`."""
+        out = self.rho if out is None else out
+        _lib.call("sph_density_lists", ctypes.byref(self.params), ctypes.byref(self.parts()),
+                  _vp(self.cs), _vp(out), _vp(lists), lists.numel(), _stream())
+        return out
+
+    def forces_lists(self, lists: torch.Tensor, vel: torch.Tensor | None = None,
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+        """sph_forces over lists recorded by density_lists at the same state."""
+        vel = self.vel if vel is None else vel
+        out = self.acc if out is None else out
+        _lib.call("sph_forces_lists", ctypes.byref(self.params), ctypes.byref(self.parts()),
+                  _vp(self.cs), _vp(vel), _vp(out), _vp(lists), lists.numel(), _stream())
+        return out
+
     def tv_correction(self):
         """Eq. 14-16 at the current state: dict of dr, beta, s (FP64), g."""
         d, n, dev, T = self.dim, self.n, self.device, self.T

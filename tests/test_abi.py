@@ -180,3 +180,21 @@ def test_static_run_rejects_oversize_before_launch():
                                 None) == -1
     assert L.sph_kdk_run_static(ctypes.byref(small), ctypes.byref(parts), 4096, -1, 3, None,
                                 None, None, None) == -1
+
+
+def test_list_entry_points_check_arguments():
+    """sph_list_size is positive for an ordinary problem; the list sweeps
+    reject a missing or short list buffer before enqueueing anything."""
+    L = _lib.load()
+    p = _params()
+    size = ctypes.c_size_t(0)
+    assert L.sph_list_size(ctypes.byref(p), ctypes.byref(size)) == 0
+    assert size.value > 0
+    parts = _lib.SphParticles()
+    for name in ("cell", "id", "off", "vel", "acc", "rho"):
+        setattr(parts, name, 4096)       # never dereferenced: the checks fail first
+    args = (ctypes.byref(p), ctypes.byref(parts), 4096, 4096)
+    assert L.sph_density_lists(*args, None, size.value, None) == -1
+    assert L.sph_density_lists(*args, 4096, size.value - 1, None) == -3
+    assert L.sph_forces_lists(*args, 4096, None, size.value, None) == -1
+    assert L.sph_forces_lists(*args, 4096, 4096, size.value - 1, None) == -3
