@@ -53,13 +53,15 @@ __device__ __forceinline__ bool pair_kernel(const Coeffs<T>& k, T r2, T hi, T hj
 template <int G>
 struct VjpCap { static constexpr int value = G == 2 ? 24 : (G == 4 ? 16 : 8); };
 
-template <int D, typename T, bool VAR, int G>
-__global__ __launch_bounds__(kBlock) void force_vjp_kernel(
-    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+// LIST: over the stored lists of the same state (no candidate tests)
+template <int D, typename T, bool VAR, int G, bool LIST>
+__device__ __forceinline__ void force_vjp_impl(
+    const Grid& g, const Coeffs<T>& k, const int* __restrict__ cell, const int* __restrict__ cs,
     const T* __restrict__ off, const T* __restrict__ vel, const T* __restrict__ rho,
     const T* __restrict__ mass, const T* __restrict__ hh, const T* __restrict__ a_bar,
-    T* __restrict__ r_bar, T* __restrict__ v_bar, T* __restrict__ rho_bar) {
-  __shared__ NeighbourList<VjpCap<G>::value> nl;
+    T* __restrict__ r_bar, T* __restrict__ v_bar, T* __restrict__ rho_bar,
+    const StoredList& sl) {
+  __shared__ NeighbourList<LIST ? 1 : VjpCap<G>::value> nl;
   const int n = g.n;
   const Cols<T, D> offc(off, n), velc(vel, n), abarc(a_bar, n);
   const Cols<T, 1> rhoc(rho, n), hc(hh, n), mc(mass, n);
@@ -70,7 +72,7 @@ __global__ __launch_bounds__(kBlock) void force_vjp_kernel(
     for (int d = 0; d < D; ++d) v[d] = offc(d, j);
     if constexpr (VAR) v[D] = hc(0, j);
   };
-  __shared__ Stage<D, T, NS, StageCap<D, T>::value> st;
+  __shared__ Stage<D, T, NS, LIST ? 0 : StageCap<D, T>::value> st;
   stage_positions<D, G>(g, cell, cs, st, srct);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
@@ -154,8 +156,10 @@ __global__ __launch_bounds__(kBlock) void force_vjp_kernel(
       }
       pb.add(-Cc * Bw * inv_rhoi - Cc * (T(0.5) * k.c0sq + T(0.25) * br * k.c0 * du) * rw);
     };
-    // the plain candidate walk: batching costs this long body's occupancy
-    for_each_neighbour_listed<D, G, T, NS, 1>(g, k, cell[i], cs, sub, st, nl, srct, test, body);
+    if constexpr (LIST)
+      for_each_stored_entry<D, G, T, NS>(g, k, cell[i], cs, sub, sl, srct, test, body);
+    else   // the plain candidate walk: batching costs this long body's occupancy
+      for_each_neighbour_listed<D, G, T, NS, 1>(g, k, cell[i], cs, sub, st, nl, srct, test, body);
   }
   T rbs[3], vbs[3];
 #pragma unroll
@@ -174,16 +178,36 @@ __global__ __launch_bounds__(kBlock) void force_vjp_kernel(
   }
 }
 
+template <int D, typename T, bool VAR, int G>
+__global__ __launch_bounds__(kBlock) void force_vjp_kernel(
+    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+    const T* __restrict__ off, const T* __restrict__ vel, const T* __restrict__ rho,
+    const T* __restrict__ mass, const T* __restrict__ hh, const T* __restrict__ a_bar,
+    T* __restrict__ r_bar, T* __restrict__ v_bar, T* __restrict__ rho_bar) {
+  force_vjp_impl<D, T, VAR, G, false>(g, k, cell, cs, off, vel, rho, mass, hh, a_bar, r_bar,
+                                      v_bar, rho_bar, StoredList{});
+}
+
+template <int D, typename T, bool VAR, int G>
+__global__ __launch_bounds__(kBlock) void force_vjp_list_kernel(
+    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+    const T* __restrict__ off, const T* __restrict__ vel, const T* __restrict__ rho,
+    const T* __restrict__ mass, const T* __restrict__ hh, const T* __restrict__ a_bar,
+    T* __restrict__ r_bar, T* __restrict__ v_bar, T* __restrict__ rho_bar, StoredList sl) {
+  force_vjp_impl<D, T, VAR, G, true>(g, k, cell, cs, off, vel, rho, mass, hh, a_bar, r_bar,
+                                     v_bar, rho_bar, sl);
+}
+
 // ------------------------------------------------------------------ density^T
 // rbar_i += sum_j (rhobar_i m_j + rhobar_j m_i) F_ij r_ij / kappa, then
 // vbar_i += vcoef * rbar_i (the drift r' = r + dt v' of the same step; wall
 // particles, told by id when id is given, do not drift).
-template <int D, typename T, bool VAR, int G>
-__global__ __launch_bounds__(kBlock) void density_vjp_kernel(
-    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+template <int D, typename T, bool VAR, int G, bool LIST>
+__device__ __forceinline__ void density_vjp_impl(
+    const Grid& g, const Coeffs<T>& k, const int* __restrict__ cell, const int* __restrict__ cs,
     const T* __restrict__ off, const T* __restrict__ mass, const T* __restrict__ hh,
     const int* __restrict__ id, const T* __restrict__ rho_bar, T* __restrict__ r_bar,
-    T* __restrict__ v_bar, T vcoef) {
+    T* __restrict__ v_bar, T vcoef, const StoredList& sl) {
   const int n = g.n;
   const Cols<T, D> offc(off, n);
   const Cols<T, 1> rbarc(rho_bar, n), hc(hh, n), mc(mass, n);
@@ -195,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void density_vjp_kernel(
     for (int d = 0; d < D; ++d) v[d] = offc(d, j);
     if constexpr (VAR) v[D] = hc(0, j);
   };
-  __shared__ Stage<D, T, NS, StageCap<D, T>::value> st;
+  __shared__ Stage<D, T, NS, LIST ? 0 : StageCap<D, T>::value> st;
   stage_positions<D, G>(g, cell, cs, st, srct);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
@@ -210,24 +234,36 @@ __global__ __launch_bounds__(kBlock) void density_vjp_kernel(
     const T hi = VAR ? hh[i] : k.h;
     const T mi = VAR ? mass[i] : k.mass;
     const T pbi = rho_bar[i];
-    for_each_candidate_values<D, G, T, VAR>(
-        g, k, cell[i], cs, sub, st, srct, [&](int j, const T* v, const T* sh, bool live) {
-          T r[3];
-          T r2 = T(0);
+    // one candidate j with test values v (offsets, then h_j)
+    auto pair = [&](int j, const T* v, const T* sh, bool live) {
+      T r[3];
+      T r2 = T(0);
 #pragma unroll
-          for (int d = 0; d < D; ++d) {
-            r[d] = (oi[d] - v[d]) - sh[d];
-            r2 = tfma(r[d], r[d], r2);
-          }
-          if (!live || j == i) return;
-          PairKernel<D, T> pk;
-          T inv_r;
-          if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? v[D] : k.h, pk, inv_r)) return;
-          const T mj = VAR ? mc(0, j) : k.mass;
-          const T c = (pbi * mj + rbarc(0, j) * mi) * pk.F;
+      for (int d = 0; d < D; ++d) {
+        r[d] = (oi[d] - v[d]) - sh[d];
+        r2 = tfma(r[d], r[d], r2);
+      }
+      if (!live || j == i) return;
+      PairKernel<D, T> pk;
+      T inv_r;
+      if (!pair_kernel<D, T, VAR>(k, r2, hi, VAR ? v[D] : k.h, pk, inv_r)) return;
+      const T mj = VAR ? mc(0, j) : k.mass;
+      const T c = (pbi * mj + rbarc(0, j) * mi) * pk.F;
 #pragma unroll
-          for (int d = 0; d < D; ++d) acc[d].add(c * r[d]);
-        });
+      for (int d = 0; d < D; ++d) acc[d].add(c * r[d]);
+    };
+    if constexpr (LIST) {
+      // every stored entry is a neighbour; the pair repeats the (passing) test
+      auto always = [](int, const T*, const T*) { return true; };
+      for_each_stored_entry<D, G, T, NS>(g, k, cell[i], cs, sub, sl, srct, always,
+                                         [&](int j, const T* sh) {
+                                           T v[NS];
+                                           srct(j, v);
+                                           pair(j, v, sh, true);
+                                         });
+    } else {
+      for_each_candidate_values<D, G, T, VAR>(g, k, cell[i], cs, sub, st, srct, pair);
+    }
   }
   T sums[3];
 #pragma unroll
@@ -241,6 +277,26 @@ __global__ __launch_bounds__(kBlock) void density_vjp_kernel(
       if (drifts) v_bar[d * n + i] += vcoef * rb;
     }
   }
+}
+
+template <int D, typename T, bool VAR, int G>
+__global__ __launch_bounds__(kBlock) void density_vjp_kernel(
+    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+    const T* __restrict__ off, const T* __restrict__ mass, const T* __restrict__ hh,
+    const int* __restrict__ id, const T* __restrict__ rho_bar, T* __restrict__ r_bar,
+    T* __restrict__ v_bar, T vcoef) {
+  density_vjp_impl<D, T, VAR, G, false>(g, k, cell, cs, off, mass, hh, id, rho_bar, r_bar, v_bar,
+                                        vcoef, StoredList{});
+}
+
+template <int D, typename T, bool VAR, int G>
+__global__ __launch_bounds__(kBlock) void density_vjp_list_kernel(
+    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+    const T* __restrict__ off, const T* __restrict__ mass, const T* __restrict__ hh,
+    const int* __restrict__ id, const T* __restrict__ rho_bar, T* __restrict__ r_bar,
+    T* __restrict__ v_bar, T vcoef, StoredList sl) {
+  density_vjp_impl<D, T, VAR, G, true>(g, k, cell, cs, off, mass, hh, id, rho_bar, r_bar, v_bar,
+                                       vcoef, sl);
 }
 
 // ------------------------------------------------------------------ wall state^T
@@ -306,13 +362,16 @@ __global__ __launch_bounds__(kBlock) void wall_sums_kernel(
   }
 }
 
-template <int D, typename T, bool VAR, int G>
-__global__ __launch_bounds__(kBlock) void wall_vjp_kernel(
-    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+// LIST: over the stored lists of the same state (entries are the pairs
+// inside the support; the fluid-wall test stays)
+template <int D, typename T, bool VAR, int G, bool LIST>
+__device__ __forceinline__ void wall_vjp_impl(
+    const Grid& g, const Coeffs<T>& k, const int* __restrict__ cell, const int* __restrict__ cs,
     const T* __restrict__ off, const T* __restrict__ hh, const int* __restrict__ id,
     const T* __restrict__ vel, const T* __restrict__ rho, const T* __restrict__ wsum,
     const T* __restrict__ wavg, int n_wall, const int* __restrict__ wall_cells,
-    T* __restrict__ r_bar, T* __restrict__ v_bar, T* __restrict__ rho_bar) {
+    T* __restrict__ r_bar, T* __restrict__ v_bar, T* __restrict__ rho_bar,
+    const StoredList& sl) {
   const int n = g.n;
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
@@ -361,7 +420,7 @@ __global__ __launch_bounds__(kBlock) void wall_vjp_kernel(
     const T pbi = wall_i ? rho_bar[i] : T(0);
     const T si = wall_i ? wsum[iw] : T(0);
     const T hi = VAR ? hh[i] : k.h;
-    for_each_candidate<D, G>(g, k, cell[i], cs, sub, [&](int j, const T* sh) {
+    auto pair = [&](int j, const T* sh) {
       T r[3];
       T r2 = T(0);
 #pragma unroll
@@ -404,7 +463,13 @@ __global__ __launch_bounds__(kBlock) void wall_vjp_kernel(
 #pragma unroll
         for (int d = 0; d < D; ++d) ra[d].add(c * F * r[d]);
       }
-    });
+    };
+    if constexpr (LIST)
+      for_each_stored_entry<D, G, T, 1>(
+          g, k, cell[i], cs, sub, sl, [](int, T*) {},
+          [](int, const T*, const T*) { return true; }, pair);
+    else
+      for_each_candidate<D, G>(g, k, cell[i], cs, sub, pair);
   }
   T rs[3], vs[3];
 #pragma unroll
@@ -422,6 +487,28 @@ __global__ __launch_bounds__(kBlock) void wall_vjp_kernel(
       rho_bar[i] += ps;
     }
   }
+}
+
+template <int D, typename T, bool VAR, int G>
+__global__ __launch_bounds__(kBlock) void wall_vjp_kernel(
+    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+    const T* __restrict__ off, const T* __restrict__ hh, const int* __restrict__ id,
+    const T* __restrict__ vel, const T* __restrict__ rho, const T* __restrict__ wsum,
+    const T* __restrict__ wavg, int n_wall, const int* __restrict__ wall_cells,
+    T* __restrict__ r_bar, T* __restrict__ v_bar, T* __restrict__ rho_bar) {
+  wall_vjp_impl<D, T, VAR, G, false>(g, k, cell, cs, off, hh, id, vel, rho, wsum, wavg, n_wall,
+                                     wall_cells, r_bar, v_bar, rho_bar, StoredList{});
+}
+
+template <int D, typename T, bool VAR, int G>
+__global__ __launch_bounds__(kBlock) void wall_vjp_list_kernel(
+    Grid g, Coeffs<T> k, const int* __restrict__ cell, const int* __restrict__ cs,
+    const T* __restrict__ off, const T* __restrict__ hh, const int* __restrict__ id,
+    const T* __restrict__ vel, const T* __restrict__ rho, const T* __restrict__ wsum,
+    const T* __restrict__ wavg, int n_wall, const int* __restrict__ wall_cells,
+    T* __restrict__ r_bar, T* __restrict__ v_bar, T* __restrict__ rho_bar, StoredList sl) {
+  wall_vjp_impl<D, T, VAR, G, true>(g, k, cell, cs, off, hh, id, vel, rho, wsum, wavg, n_wall,
+                                    wall_cells, r_bar, v_bar, rho_bar, sl);
 }
 
 // x[c][i] = 0 (c < ncomp) and, when given, y[i] = 0 for the wall particles i
@@ -619,18 +706,27 @@ __global__ __launch_bounds__(kBlock) void adj_kick_kernel(long dn, int n, T half
 template <typename T>
 void launch_force_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                       const int* cs, const T* vel, const T* a_bar, T* r_bar, T* v_bar,
-                      T* rho_bar) {
+                      T* rho_bar, const StoredList& sl) {
   if (g.n == 0) return;
-  SPH_SWEEP(force_vjp_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, vel, p.rho, p.mass, p.h, a_bar,
-                                       r_bar, v_bar, rho_bar));
+  if (sl.entry)
+    SPH_SWEEP(force_vjp_list_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, vel, p.rho, p.mass, p.h,
+                                              a_bar, r_bar, v_bar, rho_bar, sl));
+  else
+    SPH_SWEEP(force_vjp_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, vel, p.rho, p.mass, p.h, a_bar,
+                                         r_bar, v_bar, rho_bar));
 }
 
 template <typename T>
 void launch_density_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
-                        const int* cs, const T* rho_bar, T* r_bar, T* v_bar, T vcoef) {
+                        const int* cs, const T* rho_bar, T* r_bar, T* v_bar, T vcoef,
+                        const StoredList& sl) {
   if (g.n == 0) return;
-  SPH_SWEEP(density_vjp_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.mass, p.h, p.id, rho_bar,
-                                         r_bar, v_bar, vcoef));
+  if (sl.entry)
+    SPH_SWEEP(density_vjp_list_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.mass, p.h, p.id,
+                                                rho_bar, r_bar, v_bar, vcoef, sl));
+  else
+    SPH_SWEEP(density_vjp_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.mass, p.h, p.id, rho_bar,
+                                           r_bar, v_bar, vcoef));
 }
 
 template <typename T>
@@ -684,7 +780,7 @@ __global__ __launch_bounds__(kBlock) void mark_wall_cells_kernel(Coeffs<T> k, in
 template <typename T>
 void launch_wall_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                      const int* cs, const T* vel, T* wsum, T* wavg, int n_wall, bool sums_given,
-                     int* wall_cells, T* r_bar, T* v_bar, T* rho_bar) {
+                     int* wall_cells, T* r_bar, T* v_bar, T* rho_bar, const StoredList& sl) {
   if (g.n == 0 || n_wall == 0) return;
   launch_fill(l.stream, wall_cells, g.ncells, 0);
   hipLaunchKernelGGL((mark_wall_cells_kernel<T>), dim3(blocks_for(g.n)), dim3(kBlock), 0,
@@ -692,8 +788,12 @@ void launch_wall_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const P
   if (!sums_given)
     SPH_SWEEP(wall_sums_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.h, p.id, vel, wsum, wavg,
                                          n_wall, wall_cells));
-  SPH_SWEEP(wall_vjp_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.h, p.id, vel, p.rho, wsum, wavg,
-                                      n_wall, wall_cells, r_bar, v_bar, rho_bar));
+  if (sl.entry)
+    SPH_SWEEP(wall_vjp_list_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.h, p.id, vel, p.rho, wsum,
+                                             wavg, n_wall, wall_cells, r_bar, v_bar, rho_bar, sl));
+  else
+    SPH_SWEEP(wall_vjp_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.h, p.id, vel, p.rho, wsum,
+                                        wavg, n_wall, wall_cells, r_bar, v_bar, rho_bar));
   launch_zero_walls<T>(l, k, g.n, p.id, l.dim, v_bar, rho_bar);
 }
 
@@ -708,9 +808,10 @@ void launch_zero_walls(const Launch& l, const Coeffs<T>& k, int n, const int* id
 #define SPH_INST(T)                                                                          \
   template void launch_force_vjp<T>(const Launch&, const Grid&, const Coeffs<T>&,            \
                                     const PArrays<T>&, const int*, const T*, const T*, T*,   \
-                                    T*, T*);                                                 \
+                                    T*, T*, const StoredList&);                              \
   template void launch_density_vjp<T>(const Launch&, const Grid&, const Coeffs<T>&,          \
-                                      const PArrays<T>&, const int*, const T*, T*, T*, T);   \
+                                      const PArrays<T>&, const int*, const T*, T*, T*, T,    \
+                                      const StoredList&);                                    \
   template void launch_tv_vjp<T>(const Launch&, const Grid&, const Coeffs<T>&,               \
                                  const PArrays<T>&, const int*, const T*, const T*,          \
                                  const T*, const T*, T*, T*, const AdjFinish<T>&);           \
@@ -721,7 +822,7 @@ void launch_zero_walls(const Launch& l, const Coeffs<T>& k, int n, const int* id
                                    const T*, T*);                                            \
   template void launch_wall_vjp<T>(const Launch&, const Grid&, const Coeffs<T>&,             \
                                    const PArrays<T>&, const int*, const T*, T*, T*, int,     \
-                                   bool, int*, T*, T*, T*);                                  \
+                                   bool, int*, T*, T*, T*, const StoredList&);               \
   template void launch_zero_walls<T>(const Launch&, const Coeffs<T>&, int, const int*, int,  \
                                      T*, T*);
 SPH_INST(float)

@@ -657,16 +657,27 @@ int32_t adjoint_step_t(const sph_params* p, const char* tape, sph_adjoint* adj, 
   // 7^T: v = v' + dt/2 a  =>  abar += dt/2 vbar, v'bar = vbar (fluid); the
   // walls' acceleration is not an output (always zero): no cotangent
   launch_adj_kick<T>(l, k, sz.n, post.id, v_bar, a_bar);
+  // the neighbour lists of the state after the step, for the force, wall
+  // and density VJPs (a density sweep recording them; its densities, equal
+  // to the tape's, go to scratch).  In 3-D only: there a walk tests about
+  // six candidates per neighbour; the 2-D walks test about three, from
+  // positions staged in LDS, and cost less than the extra sweep.
+  StoredList sl{};
+  if (sz.dim == 3 && lists_usable(sz)) {
+    sl = StoredList{(unsigned*)(ws + w.nlist), (int*)(ws + w.ncount), sz.nblk * kBlock};
+    launch_density<T>(l, g, k, post, cs_post, (T*)(ws + w.stg_rho), nullptr, nullptr, nullptr,
+                      sl);
+  }
   // 6^T, 5^T: accelerations (r^{n+1}, v', rho^{n+1})
-  launch_force_vjp<T>(l, g, k, post, cs_post, post.vel, a_bar, r_bar, v_bar, rho_bar);
+  launch_force_vjp<T>(l, g, k, post, cs_post, post.vel, a_bar, r_bar, v_bar, rho_bar, sl);
   // the walls' state from the fluid (r^{n+1}, rho^{n+1}, v'), reversed: the
   // walls' density and velocity cotangents go to their fluid neighbours
   if (p->n_wall > 0)
     launch_wall_vjp<T>(l, g, k, post, cs_post, post.vel, (T*)(tape + tl.wsum),
                        (T*)(tape + tl.wavg), (int)p->n_wall, true, (int*)(ws + w.wall_cells),
-                       r_bar, v_bar, rho_bar);
+                       r_bar, v_bar, rho_bar, sl);
   // 4^T: density, then 2-3^T: r^{n+1} = r^n + dt v' + dr  =>  v'bar += dt rbar
-  launch_density_vjp<T>(l, g, k, post, cs_post, rho_bar, r_bar, v_bar, k.dt);
+  launch_density_vjp<T>(l, g, k, post, cs_post, rho_bar, r_bar, v_bar, k.dt, sl);
   // the cell build is a permutation: back to order n, with 1^T's first part
   // (ghat of the correction dr = T(r^n, rho^n; xi) and the xi partials)
   const int* perm = (const int*)(tape + tl.perm);

@@ -990,6 +990,43 @@ __device__ __forceinline__ void for_each_neighbour_stored(const Grid& g, const C
   }
 }
 
+// body(j, shift) over lane L's stored list, two entries read at a time (the
+// body reads what it needs of j itself); a lane whose list is incomplete
+// walks its candidates with test(j, v, shift) on the NS values read by
+// src(j, v).  Same order as the walk that wrote the list.
+template <int D, int G, typename T, int NS, typename Src, typename Test, typename Body>
+__device__ __forceinline__ void for_each_stored_entry(const Grid& g, const Coeffs<T>& k,
+                                                      int cell, const int* __restrict__ cs,
+                                                      int sub, const StoredList& sl, Src&& src,
+                                                      Test&& test, Body&& body) {
+  constexpr int CAP = list_cap(D, G);
+  constexpr int JB = list_jbits<D>();
+  constexpr unsigned JMASK = (1u << JB) - 1u;
+  const int L = blockIdx.x * kBlock + threadIdx.x;
+  const int cnt = sl.count[L];
+  if (cnt <= CAP) {
+    for (int q0 = 0; q0 < cnt; q0 += 2) {
+      unsigned e[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) e[u] = (sl.entry + (size_t)min(q0 + u, CAP - 1) * sl.stride)[L];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (q0 + u < cnt) {
+          T shift[3];
+          code_shift<D>(k, e[u] >> JB, shift);
+          body((int)(e[u] & JMASK), shift);
+        }
+      }
+    }
+  } else {
+    for_each_candidate<D, G>(g, k, cell, cs, sub, [&](int j, const T* sh) {
+      T v[NS];
+      src(j, v);
+      if (test(j, v, sh)) body(j, sh);
+    });
+  }
+}
+
 // ---------------------------------------------------------------- reductions
 // Sum or maximum over the 64 lanes of a wavefront, in every lane: DPP moves
 // combine pairs, quads, halves and whole rows of 16, then the four row

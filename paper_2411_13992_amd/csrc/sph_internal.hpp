@@ -229,12 +229,15 @@ template <typename T>
 void launch_zero(hipStream_t s, T* p, long n);
 
 // ---- adjoint (adjoint.hip)
+// with sl.entry set, over stored lists recorded at the same state
 template <typename T>
 void launch_force_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
-                      const int* cs, const T* vel, const T* a_bar, T* r_bar, T* v_bar, T* rho_bar);
+                      const int* cs, const T* vel, const T* a_bar, T* r_bar, T* v_bar, T* rho_bar,
+                      const StoredList& sl = StoredList{});
 template <typename T>
 void launch_density_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
-                        const int* cs, const T* rho_bar, T* r_bar, T* v_bar, T vcoef);
+                        const int* cs, const T* rho_bar, T* r_bar, T* v_bar, T vcoef,
+                        const StoredList& sl = StoredList{});
 // What the correction's VJP also does for the reverse step, per particle in
 // order n: the reverse of the first half kick (v_bar = vh_bar, a_bar =
 // dt/2 vh_bar for fluid particles, 0 for walls told by id; skipped when v_bar
@@ -274,7 +277,8 @@ void launch_adj_kick(const Launch& l, const Coeffs<T>& k, int n, const int* id, 
 template <typename T>
 void launch_wall_vjp(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                      const int* cs, const T* vel, T* wsum, T* wavg, int n_wall, bool sums_given,
-                     int* wall_cells, T* r_bar, T* v_bar, T* rho_bar);
+                     int* wall_cells, T* r_bar, T* v_bar, T* rho_bar,
+                     const StoredList& sl = StoredList{});
 // x[c][i] = 0 (c < ncomp) and, when given, y[i] = 0 for every wall particle i
 // (told by id)
 template <typename T>
