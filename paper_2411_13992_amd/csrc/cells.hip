@@ -439,8 +439,17 @@ __global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildA
   const int total = pst[NP];
   // pass A: the tile's particles among the candidates, U per thread with
   // their loads issued together; the wavefront's members of a batch take
-  // consecutive member slots (one LDS atomic per wavefront and batch)
+  // consecutive member slots (one LDS atomic per wavefront and batch).  When
+  // every candidate fits one batch, each member's values are loaded here
+  // too, into registers, and stored from here once its rank is known: the
+  // loads overlap the count, the look-back and the ranking.  2-D only: the
+  // 3-D stencil's nine rows of candidates seldom fit one batch.
   constexpr int U = 4;
+  const bool early = D == 2 && total <= U * NB;
+  int mslot[U], cq_keep[U], iq_keep[U], qq_keep[U];
+  T mo[U][D], mv[U][D], mms[U], mhs[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) mslot[u] = -1;     // no candidates: no members
   const unsigned long long below = (1ull << lane) - 1ull;
   for (int b0 = 0; b0 < total; b0 += U * NB) {
     int cq[U], iq[U], qq[U];
@@ -472,15 +481,34 @@ __global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildA
     base = __shfl(base, 0, kWave);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+      mslot[u] = -1;
       if ((mm[u] >> lane) & 1ull) {
         const int m = base + __popcll(mm[u] & below);
         if (m < kRebuildCap) {
           s_j[m] = qq[u];
           s_c[m] = cq[u] - tile0;
           s_id[m] = iq[u];
+          mslot[u] = m;
         }
       }
       base += __popcll(mm[u]);
+    }
+    if (early) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        cq_keep[u] = cq[u];
+        iq_keep[u] = iq[u];
+        qq_keep[u] = qq[u];
+        if (mslot[u] < 0) continue;
+        const int j = qq[u];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          mo[u][d] = stg.off[d * n + j];
+          mv[u][d] = dst.vel ? stg.vel[d * n + j] : T(0);
+        }
+        mms[u] = dst.mass ? stg.mass[j] : T(0);
+        mhs[u] = dst.h ? stg.h[j] : T(0);
+      }
     }
   }
   __syncthreads();
@@ -508,34 +536,49 @@ __global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildA
   // before the first tile read as inclusive zeros
   if (tid < kWave) {
     const unsigned ep = a.epoch & 0x3fffffffu;
+    constexpr int NG = 4;           // groups of 64 tile words per round trip
     int prefix = 0;
     int p = tile - 1;
     long spins = 0;
     while (p >= 0) {
-      const int idx = p - lane;
-      const unsigned long long w =
-          idx >= 0 ? __hip_atomic_load(&a.st.tile_state[idx], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT)
-                   : tile_word(kTileInc, a.epoch, 0u);
-      const unsigned long long f = w & kTileFlags;
-      const bool ready = f != 0 && (unsigned)((w >> 32) & 0x3fffffffull) == ep;
-      const unsigned long long incm = __ballot(ready && f == kTileInc);
-      const unsigned long long notr = __ballot(!ready);
-      const int lim = incm ? __ffsll((long long)incm) - 1 : kWave - 1;
-      const unsigned long long need = lim == kWave - 1 ? ~0ull : ((2ull << lim) - 1);
-      if (notr & need) {
+      unsigned long long w[NG];
+#pragma unroll
+      for (int u = 0; u < NG; ++u) {
+        const int idx = p - lane - u * kWave;
+        w[u] = idx >= 0 ? __hip_atomic_load(&a.st.tile_state[idx], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT)
+                        : tile_word(kTileInc, a.epoch, 0u);
+      }
+      // groups nearest first: a complete group adds its totals; one holding
+      // an inclusive prefix ends the look-back; one not ready ends the pass
+      int v = 0, done = 0;
+      bool found = false;
+#pragma unroll
+      for (int u = 0; u < NG; ++u) {
+        if (found || done < u) continue;
+        const unsigned long long f = w[u] & kTileFlags;
+        const bool ready = f != 0 && (unsigned)((w[u] >> 32) & 0x3fffffffull) == ep;
+        const unsigned long long incm = __ballot(ready && f == kTileInc);
+        const unsigned long long notr = __ballot(!ready);
+        const int lim = incm ? __ffsll((long long)incm) - 1 : kWave - 1;
+        const unsigned long long need = lim == kWave - 1 ? ~0ull : ((2ull << lim) - 1);
+        if (notr & need) continue;
+        v += lane <= lim ? (int)(w[u] & 0xffffffffull) : 0;
+        done = u + 1;
+        found = incm != 0;
+      }
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) v += __shfl_xor(v, o, kWave);
+      prefix += v;
+      if (found) break;
+      if (done == 0) {
         if (++spins > kSpinLimit) {
           if (lane == 0) atomicOr(a.flags, kFlagInternal);
           break;
         }
         continue;
       }
-      int v = lane <= lim ? (int)(w & 0xffffffffull) : 0;
-#pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) v += __shfl_xor(v, o, kWave);
-      prefix += v;
-      if (incm) break;
-      p -= kWave;
+      p -= done * kWave;
     }
     if (lane == 0) {
       if (tile > 0)
@@ -592,10 +635,34 @@ __global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildA
           rank += (r < e && (idr[u] < idm || (idr[u] == idm && r < p))) ? 1 : 0;
         }
       }
-      s_order[b + rank] = s_j[m];
-      s_ocell[b + rank] = tile0 + lc;
+      if (early) {
+        s_order[m] = b + rank;          // member -> slot within the tile
+      } else {
+        s_order[b + rank] = s_j[m];
+        s_ocell[b + rank] = tile0 + lc;
+      }
     }
     __syncthreads();
+    if (early) {
+      // each member from the registers that pass A loaded it into
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (mslot[u] < 0) continue;
+        const int to = prefix + s_order[mslot[u]];
+        if (to >= n) continue;
+        dst.cell[to] = cq_keep[u];
+        dst.id[to] = iq_keep[u];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          dst.off[d * n + to] = mo[u][d];
+          if (dst.vel) dst.vel[d * n + to] = mv[u][d];
+        }
+        if (dst.mass) dst.mass[to] = mms[u];
+        if (dst.h) dst.h[to] = mhs[u];
+        if (a.perm) a.perm[to] = qq_keep[u];
+      }
+      return;
+    }
     // two particles per thread at a time, every load issued before the stores
     for (int u0 = tid; u0 < nmem; u0 += 2 * NB) {
       int jj[2], cc[2], ii[2];
