@@ -46,20 +46,30 @@ __device__ __forceinline__ void density_impl(
   };
   __shared__ Stage<D, T, NS, StageCap<D, T>::value> st;
   __shared__ NeighbourList<LIST ? kDensityListCap<D, G> : 1> nl;
-  stage_positions<D, G>(g, cell, cs, st, srct);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   const bool valid = i < n;
+  // the particle's own values, read before the stage so that their round
+  // trip overlaps the stage's
+  T oi[3] = {T(0), T(0), T(0)};
+  T hi = k.h, mi = T(0);
+  int celli = 0;
+  if (valid) {
+    celli = cell[i];
+#pragma unroll
+    for (int d = 0; d < D; ++d) oi[d] = off[d * n + i];
+    if constexpr (VAR) {
+      hi = hh[i];
+      mi = mass[i];
+    }
+  }
+  stage_positions<D, G>(g, cell, cs, st, srct);
   int cnt = 0;
   Acc<T, UseKahan<T>::value> acc;
   acc.init(T(0));
   if (valid) {
-    T oi[3];
-#pragma unroll
-    for (int d = 0; d < D; ++d) oi[d] = off[d * n + i];
-    const T hi = VAR ? hh[i] : k.h;
     if (sub == 0) {
-      if constexpr (VAR) acc.init(mass[i] * wendland_alpha<D>(frcp(hi)));
+      if constexpr (VAR) acc.init(mi * wendland_alpha<D>(frcp(hi)));
       else acc.init(T(1));
     }
     // lane L's neighbours go to the stored list (for the force sweep), first
@@ -91,7 +101,7 @@ __device__ __forceinline__ void density_impl(
         }
       }
     };
-    for_each_candidate_values<D, G, T, VAR>(g, k, cell[i], cs, sub, st, srct, pair);
+    for_each_candidate_values<D, G, T, VAR>(g, k, celli, cs, sub, st, srct, pair);
   }
   if constexpr (LIST) {
     // the LDS list out to the stored list, row by row: a row's stores cover
@@ -103,8 +113,17 @@ __device__ __forceinline__ void density_impl(
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) wave_rows = max(wave_rows, __shfl_xor(wave_rows, o, kWave));
     unsigned* __restrict__ col = sl.entry + L;
-    for (int q = 0; q < wave_rows; ++q)
-      if (q < rows) col[(size_t)q * sl.stride] = nl.slot[q][threadIdx.x];
+    // eight rows at a time: their LDS reads first, then their stores
+    constexpr int CAP = kDensityListCap<D, G>;
+    for (int q0 = 0; q0 < wave_rows; q0 += 8) {
+      unsigned ev[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (q0 + u < CAP) ev[u] = nl.slot[min(q0 + u, CAP - 1)][threadIdx.x];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (q0 + u < rows) col[(size_t)(q0 + u) * sl.stride] = ev[u];
+    }
   }
   const T sum = group_sum<G>(acc);
   cnt = group_sum_int<G>(cnt);
@@ -255,29 +274,16 @@ __device__ __forceinline__ void forces_impl(
     if constexpr (VAR) v[D] = hc(0, j);
   };
   __shared__ Stage<D, T, NS, LIST ? 0 : StageCap<D, T>::value> st;
-  stage_positions<D, G>(g, cell, cs, st, srct);
-  // with stored lists in uniform 2-D FP32, the neighbours' body values in LDS
-  // (in FP64 the twice larger stage costs more occupancy than it saves)
-  constexpr bool BSTAGE = LIST && body_stage_on<D, T, VAR>();
-  constexpr int BCAP = BSTAGE ? 256 : 1;
-  __shared__ BodyStage<T, BCAP> bst;
-  if constexpr (BSTAGE) stage_bodies<G>(g, cell, cs, off, vel, rho, bst);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x % G;
   const bool valid = i < n;
   const bool lead = valid && sub == 0;
-  // wall particles: no acceleration, correction, kick or drift
-  const bool wall = valid && wall_at(k, n, id, i);
+  // the particle's own values, read before the stages so that their round
+  // trip overlaps the stages'
   T oi[3] = {T(0), T(0), T(0)}, vi[3] = {T(0), T(0), T(0)};
   T ai[3] = {T(0), T(0), T(0)}, gi[3] = {T(0), T(0), T(0)};
   int celli = 0;
   T rhoi = T(1);
-  Acc<T, UseKahan<T>::value> acc[3], tv[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    acc[d].init(T(0));
-    tv[d].init(T(0));
-  }
   if (valid) {
     celli = cell[i];
 #pragma unroll
@@ -286,6 +292,23 @@ __device__ __forceinline__ void forces_impl(
       vi[d] = vel[d * n + i];
     }
     rhoi = rho[i];
+  }
+  // wall particles: no acceleration, correction, kick or drift
+  const bool wall = valid && wall_at(k, n, id, i);
+  stage_positions<D, G>(g, cell, cs, st, srct);
+  // with stored lists in uniform 2-D FP32, the neighbours' body values in LDS
+  // (in FP64 the twice larger stage costs more occupancy than it saves)
+  constexpr bool BSTAGE = LIST && body_stage_on<D, T, VAR>();
+  constexpr int BCAP = BSTAGE ? 256 : 1;
+  __shared__ BodyStage<T, BCAP> bst;
+  if constexpr (BSTAGE) stage_bodies<G>(g, cell, cs, off, vel, rho, bst);
+  Acc<T, UseKahan<T>::value> acc[3], tv[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    acc[d].init(T(0));
+    tv[d].init(T(0));
+  }
+  if (valid) {
     const T pi = k.c0sq * (rhoi - k.rho0);
     const T hi = VAR ? hh[i] : k.h;
     // branch-free, so a batch's loads are not moved behind a test
