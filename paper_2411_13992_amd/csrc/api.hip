@@ -31,6 +31,7 @@ struct WsLayout {
   size_t dual_clock;   // two clocks of the dual-criteria steps
   size_t base_total;   // every region above: the least a run can work with
   size_t nlist, ncount;   // stored neighbour lists of a run (0 bytes when not usable)
+  size_t nruns;           // the density sweep's stage runs per block (2-D lists)
   size_t total;
 };
 
@@ -147,23 +148,32 @@ WsLayout ws_layout(const Sizes& s) {
   const bool lists = lists_usable(s);
   w.nlist = c.take(lists ? sizeof(unsigned) * lanes * list_cap(s.dim, s.G) : 0);
   w.ncount = c.take(lists ? sizeof(int) * lanes : 0);
+  w.nruns = c.take(lists && s.dim == 2 ? sizeof(int) * 6 * (size_t)(s.nblk > 0 ? s.nblk : 1) : 0);
   w.total = c.o;
   return w;
 }
 
-// A caller's stored-list buffer (sph_list_size bytes): entries, then counts.
+// A caller's stored-list buffer (sph_list_size bytes): entries, counts, then
+// (2-D) the density sweep's stage runs per block.
 struct ListLayout {
-  size_t entries, counts, total;
+  size_t entries, counts, runs, total;
 };
 ListLayout list_layout(const Sizes& s) {
-  ListLayout ll{0, 0, 0};
+  ListLayout ll{0, 0, 0, 0};
   if (!lists_usable(s)) return ll;
   Cursor c;
   const size_t lanes = (size_t)(s.nblk > 0 ? s.nblk : 1) * kBlock;
   ll.entries = c.take(sizeof(unsigned) * lanes * list_cap(s.dim, s.G));
   ll.counts = c.take(sizeof(int) * lanes);
+  ll.runs = c.take(s.dim == 2 ? sizeof(int) * 6 * (size_t)(s.nblk > 0 ? s.nblk : 1) : 0);
   ll.total = c.o;
   return ll;
+}
+
+// The stored lists in a workspace (lists usable)
+StoredList ws_lists(char* ws, const WsLayout& w, const Sizes& s) {
+  return StoredList{(unsigned*)(ws + w.nlist), (int*)(ws + w.ncount), s.nblk * kBlock,
+                    s.dim == 2 ? (int*)(ws + w.nruns) : nullptr};
 }
 
 TapeLayout tape_layout(const Sizes& s) {
@@ -414,8 +424,7 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs_calle
   const CellBuf cb = cellbuf_of(ws, w.cellbuf, sz.ncells);
   int* perm = (int*)(ws + w.perm);
   StoredList sl{};
-  if (lists && lists_usable(sz))
-    sl = StoredList{(unsigned*)(ws + w.nlist), (int*)(ws + w.ncount), sz.nblk * kBlock};
+  if (lists && lists_usable(sz)) sl = ws_lists(ws, w, sz);
   const size_t n = (size_t)sz.n, dn = (size_t)sz.dim * n, t = sz.tsz;
   const size_t csb = sizeof(int) * ((size_t)sz.ncells + 1);
   // the two cell_start buffers; step s reads csbuf[cur] and writes
@@ -664,7 +673,7 @@ int32_t adjoint_step_t(const sph_params* p, const char* tape, sph_adjoint* adj, 
   // positions staged in LDS, and cost less than the extra sweep.
   StoredList sl{};
   if (sz.dim == 3 && lists_usable(sz)) {
-    sl = StoredList{(unsigned*)(ws + w.nlist), (int*)(ws + w.ncount), sz.nblk * kBlock};
+    sl = ws_lists(ws, w, sz);
     launch_density<T>(l, g, k, post, cs_post, (T*)(ws + w.stg_rho), nullptr, nullptr, nullptr,
                       sl);
   }
@@ -871,7 +880,8 @@ static int32_t list_of(const sph_params* p, const void* lists, size_t list_bytes
   if (!lists) return SPH_E_ARG;
   if (list_bytes < ll.total) return SPH_E_WORKSPACE;
   char* b = (char*)const_cast<void*>(lists);
-  *out = StoredList{(unsigned*)(b + ll.entries), (int*)(b + ll.counts), sz.nblk * kBlock};
+  *out = StoredList{(unsigned*)(b + ll.entries), (int*)(b + ll.counts), sz.nblk * kBlock,
+                    sz.dim == 2 ? (int*)(b + ll.runs) : nullptr};
   return SPH_OK;
 }
 

@@ -702,21 +702,45 @@ struct BodyStage {
   int plen[R];
 };
 
+// With runs (the same block's runs as an earlier sweep over the same state
+// and grid stored them, found with the same cap), the runs are read from there
+// instead of found again: one dependent round trip less.
 template <int G, typename T, int CAP>
 __device__ __forceinline__ void stage_bodies(const Grid& g, const int* __restrict__ cell,
                                              const int* __restrict__ cs,
                                              const T* __restrict__ off, const T* __restrict__ vel,
-                                             const T* __restrict__ rho, BodyStage<T, CAP>& st) {
+                                             const T* __restrict__ rho, BodyStage<T, CAP>& st,
+                                             const int* __restrict__ runs = nullptr) {
   const int n = g.n;
-  if (threadIdx.x < 3) {
-    const StageRun run = stage_run<2, G>(g, cell, cs, threadIdx.x, CAP);
-    st.pstart[threadIdx.x] = run.ps;
-    st.plen[threadIdx.x] = run.len;
+  int rps[3], rlen[3];
+  if (runs) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      // clamped, so runs of another state cost speed, never a wild read (a
+      // slot o holds particle ps + o whatever ps and len are)
+      rps[r] = min(max(runs[blockIdx.x * 6 + r], 0), n - 1);
+      rlen[r] = min(max(runs[blockIdx.x * 6 + 3 + r], 0), min(CAP, n));
+    }
+    if (threadIdx.x < 3) {
+      st.pstart[threadIdx.x] = rps[threadIdx.x];
+      st.plen[threadIdx.x] = rlen[threadIdx.x];
+    }
+  } else {
+    if (threadIdx.x < 3) {
+      const StageRun run = stage_run<2, G>(g, cell, cs, threadIdx.x, CAP);
+      st.pstart[threadIdx.x] = run.ps;
+      st.plen[threadIdx.x] = run.len;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      rps[r] = st.pstart[r];
+      rlen[r] = st.plen[r];
+    }
   }
-  __syncthreads();
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    const int len = st.plen[r], ps = st.pstart[r];
+    const int len = rlen[r], ps = rps[r];
     for (int t = threadIdx.x; t < len; t += kBlock) {
       int j = ps + t;
       j -= (j >= n) ? n : 0;
@@ -934,6 +958,9 @@ struct StoredList {
   unsigned* entry;   // null: no list
   int* count;
   int stride;        // lanes of the sweeps' grid (blocks * kBlock)
+  // per block, the first particle and the length of its three stencil rows'
+  // runs (2-D, as the position stage found them): six ints, or null
+  int* runs = nullptr;
 };
 
 // What a pair body reads of a neighbour: offsets, velocity, density, and

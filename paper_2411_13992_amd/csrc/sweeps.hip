@@ -64,6 +64,13 @@ __device__ __forceinline__ void density_impl(
     }
   }
   stage_positions<D, G>(g, cell, cs, st, srct);
+  if constexpr (LIST && D == 2 && StageCap<D, T>::value > 0) {
+    // the stage's runs, for the force sweep's body stage over the same state
+    if (sl.runs && threadIdx.x < 3) {
+      sl.runs[blockIdx.x * 6 + threadIdx.x] = st.pstart[threadIdx.x];
+      sl.runs[blockIdx.x * 6 + 3 + threadIdx.x] = st.plen[threadIdx.x];
+    }
+  }
   int cnt = 0;
   Acc<T, UseKahan<T>::value> acc;
   acc.init(T(0));
@@ -300,8 +307,9 @@ __device__ __forceinline__ void forces_impl(
   // (in FP64 the twice larger stage costs more occupancy than it saves)
   constexpr bool BSTAGE = LIST && body_stage_on<D, T, VAR>();
   constexpr int BCAP = BSTAGE ? 256 : 1;
+  static_assert(!BSTAGE || BCAP == StageCap<D, T>::value, "runs found with the density's cap");
   __shared__ BodyStage<T, BCAP> bst;
-  if constexpr (BSTAGE) stage_bodies<G>(g, cell, cs, off, vel, rho, bst);
+  if constexpr (BSTAGE) stage_bodies<G>(g, cell, cs, off, vel, rho, bst, sl.runs);
   Acc<T, UseKahan<T>::value> acc[3], tv[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
