@@ -129,7 +129,7 @@ __device__ __forceinline__ void density_impl(
         if (q0 + u < CAP) ev[u] = nl.slot[min(q0 + u, CAP - 1)][threadIdx.x];
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (q0 + u < rows) col[(size_t)(q0 + u) * sl.stride] = ev[u];
+        if (q0 + u < rows) __builtin_nontemporal_store(ev[u], col + (size_t)(q0 + u) * sl.stride);
     }
   }
   const T sum = group_sum<G>(acc);
