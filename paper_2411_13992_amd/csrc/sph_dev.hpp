@@ -90,6 +90,12 @@ __device__ __forceinline__ T wendland_shape(T q) {
   return t2 * t2 * tfma(q, T(2), T(1));
 }
 
+// A store that the next kernel, not this one, reads back: non-temporal, so
+// the bulk outputs of a sweep do not wait in L2 for the end-of-kernel
+// write-back.
+template <typename T>
+__device__ __forceinline__ void st_nt(T* p, T v) { __builtin_nontemporal_store(v, p); }
+
 // ---------------------------------------------------------------- sums
 // Kahan-compensated accumulator (compensation on for FP32 sweeps).
 template <typename T, bool COMP>

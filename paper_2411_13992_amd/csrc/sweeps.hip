@@ -425,7 +425,7 @@ __device__ __forceinline__ void forces_impl(
   }
   if (lead) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) acc_out[d * n + i] = ai[d];
+    for (int d = 0; d < D; ++d) st_nt(acc_out + (d * n + i), ai[d]);
     if (bad) atomicOr(flags, kFlagNonfinite);
   }
   if constexpr (FUSED) {
@@ -439,16 +439,16 @@ __device__ __forceinline__ void forces_impl(
       lin = celli;
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        fo.stg.off[d * n + i] = oi[d];
-        fo.stg.vel[d * n + i] = vi[d];
-        if (fo.g_next) fo.g_next[d * n + i] = T(0);
+        st_nt(fo.stg.off + (d * n + i), oi[d]);
+        st_nt(fo.stg.vel + (d * n + i), vi[d]);
+        if (fo.g_next) st_nt(fo.g_next + (d * n + i), T(0));
       }
-      if (fo.g_next) fo.beta_next[i] = T(0);
-      fo.stg.cell[i] = lin;
-      fo.stg.id[i] = id[i];
+      if (fo.g_next) st_nt(fo.beta_next + i, T(0));
+      st_nt(fo.stg.cell + i, lin);
+      st_nt(fo.stg.id + i, id[i]);
       if constexpr (VAR) {
-        fo.stg.mass[i] = mass[i];
-        fo.stg.h[i] = hh[i];
+        st_nt(fo.stg.mass + i, mass[i]);
+        st_nt(fo.stg.h + i, hh[i]);
       }
     } else if (lead) {
       const double m = VAR ? (double)mass[i] : (double)k.mass;
@@ -467,8 +467,8 @@ __device__ __forceinline__ void forces_impl(
         const Limited lim = limit_correction<D>(k, gi, rhoi, dr);
         if (fo.g_next) {
 #pragma unroll
-          for (int d = 0; d < D; ++d) fo.g_next[d * n + i] = gi[d];
-          fo.beta_next[i] = (T)lim.beta;
+          for (int d = 0; d < D; ++d) st_nt(fo.g_next + (d * n + i), gi[d]);
+          st_nt(fo.beta_next + i, (T)lim.beta);
         }
         double d2 = 0.0;
 #pragma unroll
@@ -482,14 +482,14 @@ __device__ __forceinline__ void forces_impl(
       lin = drift_rebin<D>(g, k, celli, o2, vh, dr, f);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        fo.stg.off[d * n + i] = o2[d];
-        fo.stg.vel[d * n + i] = vh[d];
+        st_nt(fo.stg.off + (d * n + i), o2[d]);
+        st_nt(fo.stg.vel + (d * n + i), vh[d]);
       }
-      fo.stg.cell[i] = lin;
-      fo.stg.id[i] = id[i];
+      st_nt(fo.stg.cell + i, lin);
+      st_nt(fo.stg.id + i, id[i]);
       if constexpr (VAR) {
-        fo.stg.mass[i] = mass[i];
-        fo.stg.h[i] = hh[i];
+        st_nt(fo.stg.mass + i, mass[i]);
+        st_nt(fo.stg.h + i, hh[i]);
       }
       if (f) atomicOr(flags, f);
     }
