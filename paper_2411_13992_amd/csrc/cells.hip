@@ -590,7 +590,7 @@ __global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildA
   }
   __syncthreads();
   const int prefix = s_prefix;
-  for (int c = tid; c < tc; c += NB) a.cs_new[tile0 + c] = prefix + s_off[c];
+  for (int c = tid; c < tc; c += NB) st_nt(a.cs_new + (tile0 + c), prefix + s_off[c]);
   if (tile == a.ntiles - 1 && tid == 0) {
     a.cs_new[a.ncells] = prefix + nmem;
     if (prefix + nmem != n) atomicOr(a.flags, kFlagInternal);   // not a one-cell move
@@ -650,16 +650,16 @@ __global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildA
         if (mslot[u] < 0) continue;
         const int to = prefix + s_order[mslot[u]];
         if (to >= n) continue;
-        dst.cell[to] = cq_keep[u];
-        dst.id[to] = iq_keep[u];
+        st_nt(dst.cell + to, cq_keep[u]);
+        st_nt(dst.id + to, iq_keep[u]);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          dst.off[d * n + to] = mo[u][d];
-          if (dst.vel) dst.vel[d * n + to] = mv[u][d];
+          st_nt(dst.off + (d * n + to), mo[u][d]);
+          if (dst.vel) st_nt(dst.vel + (d * n + to), mv[u][d]);
         }
-        if (dst.mass) dst.mass[to] = mms[u];
-        if (dst.h) dst.h[to] = mhs[u];
-        if (a.perm) a.perm[to] = qq_keep[u];
+        if (dst.mass) st_nt(dst.mass + to, mms[u]);
+        if (dst.h) st_nt(dst.h + to, mhs[u]);
+        if (a.perm) st_nt(a.perm + to, qq_keep[u]);
       }
       return;
     }
@@ -689,16 +689,16 @@ __global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildA
       for (int u = 0; u < 2; ++u) {
         const int to = prefix + u0 + u * NB;
         if (u0 + u * NB >= nmem || to >= n) continue;
-        dst.cell[to] = cc[u];
-        dst.id[to] = ii[u];
+        st_nt(dst.cell + to, cc[u]);
+        st_nt(dst.id + to, ii[u]);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          dst.off[d * n + to] = oo[u][d];
-          if (dst.vel) dst.vel[d * n + to] = vv[u][d];
+          st_nt(dst.off + (d * n + to), oo[u][d]);
+          if (dst.vel) st_nt(dst.vel + (d * n + to), vv[u][d]);
         }
-        if (dst.mass) dst.mass[to] = ms[u];
-        if (dst.h) dst.h[to] = hs[u];
-        if (a.perm) a.perm[to] = jj[u];
+        if (dst.mass) st_nt(dst.mass + to, ms[u]);
+        if (dst.h) st_nt(dst.h + to, hs[u]);
+        if (a.perm) st_nt(a.perm + to, jj[u]);
       }
     }
   } else {

@@ -114,7 +114,7 @@ __device__ __forceinline__ void density_impl(
     // the LDS list out to the stored list, row by row: a row's stores cover
     // consecutive lanes (coalesced); rows past a lane's count are not written
     const int L = blockIdx.x * kBlock + threadIdx.x;
-    sl.count[L] = cnt;
+    st_nt(sl.count + L, cnt);
     const int rows = min(cnt, (int)kDensityListCap<D, G>);
     int wave_rows = rows;
 #pragma unroll
@@ -129,7 +129,7 @@ __device__ __forceinline__ void density_impl(
         if (q0 + u < CAP) ev[u] = nl.slot[min(q0 + u, CAP - 1)][threadIdx.x];
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (q0 + u < rows) __builtin_nontemporal_store(ev[u], col + (size_t)(q0 + u) * sl.stride);
+        if (q0 + u < rows) st_nt(col + (size_t)(q0 + u) * sl.stride, ev[u]);
     }
   }
   const T sum = group_sum<G>(acc);
