@@ -530,11 +530,21 @@ __global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildA
     }
     if (tid == 0) s_off[tc] = tot;
   }
+  __syncthreads();   // the offsets, for the grouping below
   // the particles of all earlier tiles: the first wavefront reads the tile
-  // words of up to 64 earlier tiles at once, nearest first, and adds the
+  // words of up to 256 earlier tiles at once, nearest first, and adds the
   // totals up to the nearest one that carries its inclusive prefix; tiles
-  // before the first tile read as inclusive zeros
-  if (tid < kWave) {
+  // before the first tile read as inclusive zeros.  Meanwhile the other
+  // wavefronts group the members by cell (their ids beside them).
+  if (tid >= kWave) {
+    if (nmem <= kRebuildCap) {
+      for (int m = tid - kWave; m < nmem; m += NB - kWave) {
+        const int pos = atomicAdd(&s_cur[s_c[m]], 1);
+        s_bucket[pos] = m;
+        s_bid[pos] = s_id[m];
+      }
+    }
+  } else {
     const unsigned ep = a.epoch & 0x3fffffffu;
     constexpr int NG = 4;           // groups of 64 tile words per round trip
     int prefix = 0;
@@ -609,15 +619,8 @@ __global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildA
     if (a.perm) a.perm[to] = j;
   };
   if (nmem <= kRebuildCap) {
-    // group the members by cell (their ids beside them), rank each by id
-    // within its cell, then move them in destination order (consecutive
-    // threads, consecutive slots)
-    for (int m = tid; m < nmem; m += NB) {
-      const int pos = atomicAdd(&s_cur[s_c[m]], 1);
-      s_bucket[pos] = m;
-      s_bid[pos] = s_id[m];
-    }
-    __syncthreads();
+    // rank each member by id within its cell (grouped above), then move them
+    // in destination order (consecutive threads, consecutive slots)
     for (int p = tid; p < nmem; p += NB) {
       const int m = s_bucket[p];
       const int lc = s_c[m], idm = s_bid[p];
