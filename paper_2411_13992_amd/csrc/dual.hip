@@ -208,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void dual_prologue_kernel(
   }
   if (partials) {
     const int cols[3] = {6, 7, 8};
-    wave_partials<3>(partials, cols, v, 1u << 2);
+    wave_partials<3>(partials, cols, v, 1u << 2, 3u);
   }
 }
 

@@ -1130,11 +1130,33 @@ __device__ __forceinline__ void block_reduce_multi(double* v, unsigned max_mask,
 // barrier) and its first lane writes the row.
 constexpr int kWavesPerBlock = kBlock / kWave;
 
+// Exact sum of an integer over the wavefront (same lane pattern as wave_reduce)
+__device__ __forceinline__ int wave_sum_int(int v) {
+  v += dpp_move<kDppQuadXor1>(v);
+  v += dpp_move<kDppQuadXor2>(v);
+  v += dpp_move<kDppRowHalfMirror>(v);
+  v += dpp_move<kDppRowMirror>(v);
+  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+         __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
+}
+
+// Bit q of max_mask: value q is reduced by maximum (else sum); of flag_mask:
+// value q is 0 or 1 in every lane and is counted (ballot); of int_mask: value
+// q is a small integer, summed as one.  Counts and integer sums are exact, so
+// they equal the FP64 sums bit for bit.
 template <int NV>
 __device__ __forceinline__ void wave_partials(double* __restrict__ p, const int* cols,
-                                              double* v, unsigned max_mask) {
+                                              double* v, unsigned max_mask,
+                                              unsigned flag_mask = 0u, unsigned int_mask = 0u) {
 #pragma unroll
-  for (int q = 0; q < NV; ++q) v[q] = ((max_mask >> q) & 1u) ? wave_max(v[q]) : wave_sum(v[q]);
+  for (int q = 0; q < NV; ++q) {
+    if ((flag_mask >> q) & 1u)
+      v[q] = (double)__popcll(__ballot(v[q] != 0.0));
+    else if ((int_mask >> q) & 1u)
+      v[q] = (double)wave_sum_int((int)v[q]);
+    else
+      v[q] = ((max_mask >> q) & 1u) ? wave_max(v[q]) : wave_sum(v[q]);
+  }
   if (threadIdx.x % kWave == 0) {
     const size_t nrows = (size_t)gridDim.x * kWavesPerBlock;
     const size_t row = (size_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;

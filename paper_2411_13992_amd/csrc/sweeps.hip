@@ -145,7 +145,7 @@ __device__ __forceinline__ void density_impl(
   if (partials) {
     const int cols[1] = {5};
     double v[1] = {lead ? (double)cnt : 0.0};
-    wave_partials<1>(partials, cols, v, 0u);
+    wave_partials<1>(partials, cols, v, 0u, 0u, 1u);
   }
 }
 
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
   }
   if (partials) {
     const int cols[3] = {6, 7, 8};
-    wave_partials<3>(partials, cols, v, 1u << 2);
+    wave_partials<3>(partials, cols, v, 1u << 2, 3u);
   }
 }
 
@@ -501,7 +501,7 @@ __device__ __forceinline__ void forces_impl(
       const int cur_cols[5] = {0, 1, 2, 3, 4};
       wave_partials<5>(fo.part_cur, cur_cols, v, 1u << 4);
       const int next_cols[3] = {6, 7, 8};
-      wave_partials<3>(fo.part_next, next_cols, v + 5, 1u << 2);
+      wave_partials<3>(fo.part_next, next_cols, v + 5, 1u << 2, 3u);
     }
     if (fo.counts) {
       const int slot = slot_claim_finish(sc);
