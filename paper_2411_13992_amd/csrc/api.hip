@@ -469,21 +469,24 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs_calle
     if (!record_pre(b, tape_of(0))) return SPH_E_INTERNAL_COPY;
     launch_multi_copy(stream, b);
   }
-  launch_fill(stream, cb.counts, cb.fill_ints, 0);
-  if (diag) launch_zero_partials(stream, sz.nblk, part[0]);
-
   // first step: 1. correction at r^n (Eq. 14-16), 2. half kick + drift + rebin
-  T* dr = nullptr;
   if (applies(step0)) {
-    dr = (T*)(ws + w.dr);
-    launch_tv<T>(l, g, k, a, cs, dr, tapes ? (T*)(tapes + tl.beta) : nullptr, nullptr,
-                 tapes ? (T*)(tapes + tl.g) : nullptr, diag ? part[0] : nullptr);
-  } else if (tapes) {
-    // no correction this step: record g = 0, beta = 0 (the reverse then adds nothing)
-    launch_zero<T>(stream, (T*)(tapes + tl.g), (long)dn);
-    launch_zero<T>(stream, (T*)(tapes + tl.beta), (long)n);
+    // one sweep: the correction, then the kick and drift with it, and the
+    // cell build's tile words cleared on the side (every diagnostics partial
+    // of the first step is written by its sweeps: no clearing)
+    const TvDrift<T> td{a, stg, flags, cb.counts, cb.fill_ints};
+    launch_tv<T>(l, g, k, a, cs, (T*)(ws + w.dr), tapes ? (T*)(tapes + tl.beta) : nullptr,
+                 nullptr, tapes ? (T*)(tapes + tl.g) : nullptr, diag ? part[0] : nullptr, td);
+  } else {
+    launch_fill(stream, cb.counts, cb.fill_ints, 0);
+    if (diag) launch_zero_partials(stream, sz.nblk, part[0]);
+    if (tapes) {
+      // no correction this step: record g = 0, beta = 0 (the reverse then adds nothing)
+      launch_zero<T>(stream, (T*)(tapes + tl.g), (long)dn);
+      launch_zero<T>(stream, (T*)(tapes + tl.beta), (long)n);
+    }
+    launch_drift<T>(l, g, k, a, nullptr, stg, nullptr, nullptr, flags);
   }
-  launch_drift<T>(l, g, k, a, dr, stg, nullptr, nullptr, flags);
 
   PArrays<T> dst = a;
   dst.acc = nullptr;
@@ -547,10 +550,18 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs_calle
       }
       launch_forces_fused<T>(l, g, k, a, cs, fo, flags, sl);
     } else {
-      // 5-6. accelerations at (r^{n+1}, v', rho^{n+1}), 7. second half kick
-      launch_forces<T>(l, g, k, a, cs, a.vel, a.acc, flags, sl);
-      launch_kick<T>(l, k, sz.n, a.vel, a.acc, a.mass, a.id, cur_part, true, flags);
-      if (diag) launch_diag_fold(stream, DiagFold{cur_part, sz.nblk * kWavesPerBlock, diag + (size_t)SPH_NDIAG * s});
+      // 5-6. accelerations at (r^{n+1}, v', rho^{n+1}), 7. second half kick in
+      // the same sweep, into the staging velocities (free after this step's
+      // cell build); then the fold and their copy back in one launch
+      FusedOut<T> kick{};
+      kick.kick_vel = stg.vel;
+      kick.part_cur = cur_part;
+      launch_forces<T>(l, g, k, a, cs, a.vel, a.acc, flags, sl, kick);
+      launch_fold_copy(stream,
+                       diag ? DiagFold{cur_part, sz.nblk * kWavesPerBlock,
+                                       diag + (size_t)SPH_NDIAG * s}
+                            : DiagFold{},
+                       stg.vel, a.vel, t * dn);
     }
   }
   return hip_status();

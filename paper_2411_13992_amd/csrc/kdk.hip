@@ -200,6 +200,31 @@ void launch_diag_fold(hipStream_t s, DiagFold fold) {
                      fold.nrows, fold.diag);
 }
 
+// blocks [0, nfold): one diagnostics column each; the others: the copy
+__global__ __launch_bounds__(kBlock) void fold_copy_kernel(const double* __restrict__ partials,
+                                                           int nrows, double* __restrict__ diag,
+                                                           int nfold,
+                                                           const unsigned* __restrict__ src,
+                                                           unsigned* __restrict__ dst, long words) {
+  if ((int)blockIdx.x < nfold) {
+    fold_diag_column(partials, nrows, blockIdx.x, diag);
+    return;
+  }
+  const long nb = (long)gridDim.x - nfold;
+  for (long w = ((long)blockIdx.x - nfold) * kBlock + threadIdx.x; w < words; w += nb * kBlock)
+    dst[w] = src[w];
+}
+
+void launch_fold_copy(hipStream_t s, DiagFold fold, const void* src, void* dst, size_t bytes) {
+  const int nfold = fold.partials ? kNumPartials : 0;
+  const long words = (long)(bytes / 4);
+  const long nb = words > 0 ? blocks_for(words) : 0;
+  const int ncopy = (int)(nb < 1024 ? nb : 1024);
+  if (nfold + ncopy == 0) return;
+  hipLaunchKernelGGL(fold_copy_kernel, dim3(nfold + ncopy), dim3(kBlock), 0, s, fold.partials,
+                     fold.nrows, fold.diag, nfold, (const unsigned*)src, (unsigned*)dst, words);
+}
+
 __global__ __launch_bounds__(kBlock) void zero_double_kernel(double* __restrict__ p, long n) {
   long i = (long)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) p[i] = 0.0;

@@ -66,6 +66,10 @@ struct FusedOut {
   double* part_next;
   T* g_next;           // null: no tape; else the next step's correction sum g [D][N]
   T* beta_next;        // and limiter value [N] (written when apply_next)
+  // unfused sweep only: the second half kick v' + dt/2 a of every fluid
+  // particle into kick_vel [D][N] (not the swept velocities: other blocks
+  // still read those), its diagnostics into part_cur
+  T* kick_vel = nullptr;
 };
 
 // ---- sweeps (sweeps.hip)
@@ -74,14 +78,27 @@ template <typename T>
 void launch_density(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                     const int* cs, T* rho_out, double* partials, int* counts, unsigned* flags,
                     const StoredList& sl = StoredList{});
+// A correction sweep that also does the step's first half kick and drift
+// (the drift sweep's arithmetic, with the correction just computed): every
+// particle of src moved into stg; and clears clear[0, clear_n) on the side.
+template <typename T>
+struct TvDrift {
+  PArrays<T> src;
+  PArrays<T> stg;     // stg.off null: no drift
+  unsigned* flags;
+  int* clear;
+  long clear_n;
+};
 template <typename T>
 void launch_tv(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
-               const int* cs, T* dr, T* beta, double* s_out, T* g_out, double* partials);
+               const int* cs, T* dr, T* beta, double* s_out, T* g_out, double* partials,
+               const TvDrift<T>& td = TvDrift<T>{});
 // with sl.entry set, over the stored lists of the density sweep just before
+// with kick.kick_vel set, the step's second half kick too (see FusedOut)
 template <typename T>
 void launch_forces(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                    const int* cs, const T* vel, T* acc_out, unsigned* flags,
-                   const StoredList& sl = StoredList{});
+                   const StoredList& sl = StoredList{}, const FusedOut<T>& kick = FusedOut<T>{});
 // with sl.entry set, over the stored lists of the density sweep just before
 template <typename T>
 void launch_forces_fused(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
@@ -156,6 +173,9 @@ struct DiagFold {
 void launch_scan(hipStream_t s, int ncells, int* counts, ScanState st, unsigned epoch, int* cs,
                  unsigned* flags, DiagFold fold);
 void launch_diag_fold(hipStream_t s, DiagFold fold);
+// The fold (when fold.partials is set) and a copy of `bytes` (a multiple of
+// 4) from src to dst, in one launch.
+void launch_fold_copy(hipStream_t s, DiagFold fold, const void* src, void* dst, size_t bytes);
 // Sorting scratch: per destination slot, the source index, the particle id
 // and the cell's [start, end).
 struct SortTmp {

@@ -178,8 +178,13 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
     const T* __restrict__ off, const T* __restrict__ rho, const T* __restrict__ mass,
     const T* __restrict__ hh, const int* __restrict__ id, T* __restrict__ dr,
     T* __restrict__ beta_out, double* __restrict__ s_out, T* __restrict__ g_out,
-    double* __restrict__ partials) {
+    double* __restrict__ partials, TvDrift<T> td) {
   const int n = g.n;
+  if (td.clear) {
+    for (long x = (long)blockIdx.x * kBlock + threadIdx.x; x < td.clear_n;
+         x += (long)gridDim.x * kBlock)
+      td.clear[x] = 0;
+  }
   const Cols<T, D> offc(off, n);
   const Cols<T, 1> rhoc(rho, n), hc(hh, n), mc(mass, n);
   const int i = (blockIdx.x * kBlock + threadIdx.x) / G;
@@ -240,6 +245,30 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
     }
     if (beta_out) beta_out[i] = (T)lim.beta;
     if (s_out) s_out[i] = lim.s;
+    if (td.stg.off) {
+      // v' = v + dt/2 a, o' = o + dt v' + dr, rebinned; walls stay in place
+      const PArrays<T>& p = td.src;
+      T o[3], vh[3];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        vh[d] = !fluid ? p.vel[d * n + i] : tfma(k.half_dt, p.acc[d * n + i], p.vel[d * n + i]);
+        o[d] = p.off[d * n + i];
+      }
+      unsigned f = 0;
+      const int lin = !fluid ? p.cell[i] : drift_rebin<D>(g, k, p.cell[i], o, vh, dri, f);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        st_nt(td.stg.off + (d * n + i), o[d]);
+        st_nt(td.stg.vel + (d * n + i), vh[d]);
+      }
+      st_nt(td.stg.cell + i, lin);
+      st_nt(td.stg.id + i, p.id[i]);
+      if constexpr (VAR) {
+        st_nt(td.stg.mass + i, p.mass[i]);
+        st_nt(td.stg.h + i, p.h[i]);
+      }
+      if (f) atomicOr(td.flags, f);
+    }
     v[0] = lim.beta > 0.0 ? 1.0 : 0.0;
     v[1] = fabs(lim.s - k.lim_s0) <= k.band_tol * k.lim_s0 ? 1.0 : 0.0;
     v[2] = sqrt(d2) * k.inv_dt;
@@ -427,6 +456,35 @@ __device__ __forceinline__ void forces_impl(
 #pragma unroll
     for (int d = 0; d < D; ++d) st_nt(acc_out + (d * n + i), ai[d]);
     if (bad) atomicOr(flags, kFlagNonfinite);
+  }
+  if constexpr (!FUSED) {
+    if (fo.kick_vel) {
+      // the step's second half kick (the kick sweep's arithmetic): fluid only
+      double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // ke, mom x3, vmax
+      if (lead && !wall) {
+        const double m = VAR ? (double)mass[i] : (double)k.mass;
+        double v2 = 0.0;
+        bool badv = false;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const T vn = tfma(k.half_dt, ai[d], vi[d]);
+          fo.kick_vel[d * n + i] = vn;
+          badv |= !isfinite(vn);
+          v2 += (double)vn * (double)vn;
+          v[1 + d] = m * (double)vn;
+        }
+        v[0] = 0.5 * m * v2;
+        v[4] = sqrt(v2);
+        if (badv) atomicOr(flags, kFlagNonfinite);
+      } else if (lead) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) fo.kick_vel[d * n + i] = vi[d];
+      }
+      if (fo.part_cur) {
+        const int cols[5] = {0, 1, 2, 3, 4};
+        wave_partials<5>(fo.part_cur, cols, v, 1u << 4);
+      }
+    }
   }
   if constexpr (FUSED) {
     // second half kick of this step, then the next step's half kick, correction
@@ -653,24 +711,24 @@ void launch_density(const Launch& l, const Grid& g, const Coeffs<T>& k, const PA
 
 template <typename T>
 void launch_tv(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
-               const int* cs, T* dr, T* beta, double* s_out, T* g_out, double* partials) {
+               const int* cs, T* dr, T* beta, double* s_out, T* g_out, double* partials,
+               const TvDrift<T>& td) {
   if (g.n == 0) return;
   SPH_SWEEP(tv_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, p.rho, p.mass, p.h, p.id, dr, beta,
-                                s_out, g_out, partials));
+                                s_out, g_out, partials, td));
 }
 
 template <typename T>
 void launch_forces(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                    const int* cs, const T* vel, T* acc_out, unsigned* flags,
-                   const StoredList& sl) {
+                   const StoredList& sl, const FusedOut<T>& kick) {
   if (g.n == 0) return;
-  FusedOut<T> none{};
   if (sl.entry)
     SPH_SWEEP(forces_list_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, vel, p.rho, p.mass, p.h,
-                                           p.id, acc_out, flags, none, sl));
+                                           p.id, acc_out, flags, kick, sl));
   else
     SPH_SWEEP(forces_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, vel, p.rho, p.mass, p.h, p.id,
-                                      acc_out, flags, none));
+                                      acc_out, flags, kick));
 }
 
 template <typename T>
@@ -701,10 +759,10 @@ void launch_wall_state(const Launch& l, const Grid& g, const Coeffs<T>& k, const
                                   const PArrays<T>&, const int*, T*, double*, int*,          \
                                   unsigned*, const StoredList&);                             \
   template void launch_tv<T>(const Launch&, const Grid&, const Coeffs<T>&, const PArrays<T>&,\
-                             const int*, T*, T*, double*, T*, double*);                      \
+                             const int*, T*, T*, double*, T*, double*, const TvDrift<T>&);   \
   template void launch_forces<T>(const Launch&, const Grid&, const Coeffs<T>&,               \
                                  const PArrays<T>&, const int*, const T*, T*, unsigned*,     \
-                                 const StoredList&);                                         \
+                                 const StoredList&, const FusedOut<T>&);                     \
   template void launch_forces_fused<T>(const Launch&, const Grid&, const Coeffs<T>&,         \
                                        const PArrays<T>&, const int*, const FusedOut<T>&,    \
                                        unsigned*, const StoredList&);

@@ -140,7 +140,10 @@ class Simulation:
         ncells = int(np.prod(cfg.cells()[:d]))
         self.ncells = ncells
         self.cs = torch.zeros(ncells + 1, dtype=torch.int32, device=dev)
-        self.diag = torch.zeros(_lib.SPH_NDIAG, dtype=torch.float64, device=dev)
+        # the last step's diagnostics: this buffer after step(), a view of the
+        # last row after run() (no copy launch)
+        self._diag_own = torch.zeros(_lib.SPH_NDIAG, dtype=torch.float64, device=dev)
+        self.diag = self._diag_own
         self.step_index = 0
         pos_dev = torch.as_tensor(pos, device=dev).contiguous()
         s = _stream()
@@ -252,6 +255,7 @@ class Simulation:
             raise ValueError("a tape records exactly one step")
         parts = self.parts()
         s = _stream()
+        self.diag = self._diag_own
         for _ in range(nsteps):
             _lib.call("sph_kdk_step", ctypes.byref(self.params), ctypes.byref(parts),
                       _vp(self.cs), self.step_index, _vp(self.ws), self.ws_bytes, _vp(tape),
@@ -281,7 +285,7 @@ class Simulation:
                   _vp(self.cs), self.step_index, nsteps, _vp(self.ws), self.ws_bytes,
                   _vp(tapes), _vp(d), _stream())
         if d is not None:
-            self.diag.copy_(d[-1])
+            self.diag = d[-1]
         self.step_index += nsteps
         return d
 
@@ -301,7 +305,7 @@ class Simulation:
                   ctypes.byref(self.parts()), _vp(self.cs), nsteps, _vp(self.ws), self.ws_bytes,
                   _vp(d), _vp(rec), _stream())
         if d is not None and nsteps > 0:
-            self.diag.copy_(d[-1])
+            self.diag = d[-1]
         self.step_index += nsteps
         return d, rec
 
@@ -346,6 +350,7 @@ class Simulation:
     def diagnostics(self, fresh: bool = False) -> dict:
         """FP64 diagnostics of the last step (or of the current state alone)."""
         if fresh:
+            self.diag = self._diag_own
             _lib.call("sph_diagnostics", ctypes.byref(self.params), ctypes.byref(self.parts()),
                       _vp(self.cs), _vp(self.ws), self.ws_bytes, _vp(self.diag), _stream())
         vals = self.diag.cpu().numpy()
