@@ -317,6 +317,11 @@ void launch_rank_gather(const Launch& l, int n, SortTmp tmp, const PArrays<T>& s
 constexpr int kRebuildCap = 2048;        // tile particles ranked in LDS
 constexpr int kRebuildMaxCells = 512;    // cells per tile (host: T <= this)
 constexpr int kRebuildBlock = 1024;     // threads per block
+// Up to this many tiles every tile's block runs at once (one per CU) and the
+// launch is one dependent chain: members' values are then loaded early and
+// stored with non-temporal stores.  With more tiles both cost time (measured
+// on a 1M-particle workload) and the plain path runs.
+constexpr int kRebuildLatencyTiles = 256;
 
 int rebuild_tile_cells(int dim, const int nc[3], long n, bool var) {
   const int ncells = nc[0] * nc[1] * (dim == 3 ? nc[2] : 1);
@@ -336,9 +341,14 @@ int rebuild_tiles(int dim, const int nc[3], long n, bool var) {
   return per_row * nc[1] * (dim == 3 ? nc[2] : 1);
 }
 
-template <int D, typename T>
-__global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildArgs a,
-                                                                PArrays<T> stg, PArrays<T> dst) {
+// LAT: the latency regime (see kRebuildLatencyTiles).  The other 2-D
+// instance keeps to 64 VGPRs (eight waves per SIMD), so two of its blocks
+// share a CU (the 3-D one would spill: its nine rows' run bounds live in
+// registers).
+template <int D, typename T, bool LAT>
+__global__ __launch_bounds__(kRebuildBlock, (LAT || D == 3) ? 4 : 8) void rebuild_kernel(Grid g, RebuildArgs a,
+                                                                            PArrays<T> stg,
+                                                                            PArrays<T> dst) {
   constexpr int NB = kRebuildBlock;
   constexpr int NR = D == 3 ? 9 : 3;             // rows of cells around the tile's row
   constexpr int NP = 2 * NR;                     // runs: one or two per row (x seam)
@@ -445,9 +455,10 @@ __global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildA
   // loads overlap the count, the look-back and the ranking.  2-D only: the
   // 3-D stencil's nine rows of candidates seldom fit one batch.
   constexpr int U = 4;
-  const bool early = D == 2 && total <= U * NB;
-  int mslot[U], cq_keep[U], iq_keep[U], qq_keep[U];
-  T mo[U][D], mv[U][D], mms[U], mhs[U];
+  const bool early = D == 2 && LAT && total <= U * NB;
+  constexpr int UE = D == 2 && LAT ? U : 1;      // early-path registers
+  int mslot[U], cq_keep[UE], iq_keep[UE], qq_keep[UE];
+  T mo[UE][D], mv[UE][D], mms[UE], mhs[UE];
 #pragma unroll
   for (int u = 0; u < U; ++u) mslot[u] = -1;     // no candidates: no members
   const unsigned long long below = (1ull << lane) - 1ull;
@@ -493,7 +504,8 @@ __global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildA
       }
       base += __popcll(mm[u]);
     }
-    if (early) {
+    if constexpr (UE == U) {
+      if (early) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         cq_keep[u] = cq[u];
@@ -508,6 +520,7 @@ __global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildA
         }
         mms[u] = dst.mass ? stg.mass[j] : T(0);
         mhs[u] = dst.h ? stg.h[j] : T(0);
+      }
       }
     }
   }
@@ -550,14 +563,16 @@ __global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildA
     int prefix = 0;
     int p = tile - 1;
     long spins = 0;
+    int ng = NG;                    // groups read: one while waiting on the nearest
     while (p >= 0) {
       unsigned long long w[NG];
 #pragma unroll
       for (int u = 0; u < NG; ++u) {
         const int idx = p - lane - u * kWave;
-        w[u] = idx >= 0 ? __hip_atomic_load(&a.st.tile_state[idx], __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT)
-                        : tile_word(kTileInc, a.epoch, 0u);
+        w[u] = u >= ng ? 0ull
+               : idx >= 0 ? __hip_atomic_load(&a.st.tile_state[idx], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT)
+                          : tile_word(kTileInc, a.epoch, 0u);
       }
       // groups nearest first: a complete group adds its totals; one holding
       // an inclusive prefix ends the look-back; one not ready ends the pass
@@ -586,9 +601,11 @@ __global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildA
           if (lane == 0) atomicOr(a.flags, kFlagInternal);
           break;
         }
+        ng = 1;
         continue;
       }
       p -= done * kWave;
+      ng = NG;
     }
     if (lane == 0) {
       if (tile > 0)
@@ -600,7 +617,12 @@ __global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildA
   }
   __syncthreads();
   const int prefix = s_prefix;
-  for (int c = tid; c < tc; c += NB) st_nt(a.cs_new + (tile0 + c), prefix + s_off[c]);
+  // the tile's output: non-temporal stores in the latency regime
+  auto put = [&](auto* ptr, auto v) {
+    if constexpr (LAT) st_nt(ptr, v);
+    else *ptr = v;
+  };
+  for (int c = tid; c < tc; c += NB) put(a.cs_new + (tile0 + c), prefix + s_off[c]);
   if (tile == a.ntiles - 1 && tid == 0) {
     a.cs_new[a.ncells] = prefix + nmem;
     if (prefix + nmem != n) atomicOr(a.flags, kFlagInternal);   // not a one-cell move
@@ -646,25 +668,27 @@ __global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildA
       }
     }
     __syncthreads();
-    if (early) {
+    if constexpr (UE == U) {
+      if (early) {
       // each member from the registers that pass A loaded it into
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (mslot[u] < 0) continue;
         const int to = prefix + s_order[mslot[u]];
         if (to >= n) continue;
-        st_nt(dst.cell + to, cq_keep[u]);
-        st_nt(dst.id + to, iq_keep[u]);
+        put(dst.cell + to, cq_keep[u]);
+        put(dst.id + to, iq_keep[u]);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          st_nt(dst.off + (d * n + to), mo[u][d]);
-          if (dst.vel) st_nt(dst.vel + (d * n + to), mv[u][d]);
+          put(dst.off + (d * n + to), mo[u][d]);
+          if (dst.vel) put(dst.vel + (d * n + to), mv[u][d]);
         }
-        if (dst.mass) st_nt(dst.mass + to, mms[u]);
-        if (dst.h) st_nt(dst.h + to, mhs[u]);
-        if (a.perm) st_nt(a.perm + to, qq_keep[u]);
+        if (dst.mass) put(dst.mass + to, mms[u]);
+        if (dst.h) put(dst.h + to, mhs[u]);
+        if (a.perm) put(a.perm + to, qq_keep[u]);
       }
       return;
+      }
     }
     // two particles per thread at a time, every load issued before the stores
     for (int u0 = tid; u0 < nmem; u0 += 2 * NB) {
@@ -692,16 +716,16 @@ __global__ __launch_bounds__(kRebuildBlock) void rebuild_kernel(Grid g, RebuildA
       for (int u = 0; u < 2; ++u) {
         const int to = prefix + u0 + u * NB;
         if (u0 + u * NB >= nmem || to >= n) continue;
-        st_nt(dst.cell + to, cc[u]);
-        st_nt(dst.id + to, ii[u]);
+        put(dst.cell + to, cc[u]);
+        put(dst.id + to, ii[u]);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          st_nt(dst.off + (d * n + to), oo[u][d]);
-          if (dst.vel) st_nt(dst.vel + (d * n + to), vv[u][d]);
+          put(dst.off + (d * n + to), oo[u][d]);
+          if (dst.vel) put(dst.vel + (d * n + to), vv[u][d]);
         }
-        if (dst.mass) st_nt(dst.mass + to, ms[u]);
-        if (dst.h) st_nt(dst.h + to, hs[u]);
-        if (a.perm) st_nt(a.perm + to, jj[u]);
+        if (dst.mass) put(dst.mass + to, ms[u]);
+        if (dst.h) put(dst.h + to, hs[u]);
+        if (a.perm) put(a.perm + to, jj[u]);
       }
     }
   } else {
@@ -739,13 +763,19 @@ template <typename T>
 void launch_rebuild(const Launch& l, const Grid& g, const RebuildArgs& a, const PArrays<T>& stg,
                     const PArrays<T>& dst) {
   if (g.n == 0) return;
+  const bool lat = a.ntiles <= kRebuildLatencyTiles;
   const int nb = a.ntiles + (a.fold.partials ? kNumPartials : 0);
-  if (l.dim == 2)
-    hipLaunchKernelGGL((rebuild_kernel<2, T>), dim3(nb), dim3(kRebuildBlock), 0, l.stream, g, a,
-                       stg, dst);
-  else
-    hipLaunchKernelGGL((rebuild_kernel<3, T>), dim3(nb), dim3(kRebuildBlock), 0, l.stream, g, a,
-                       stg, dst);
+#define SPH_REBUILD(D, LAT)                                                                   \
+  hipLaunchKernelGGL((rebuild_kernel<D, T, LAT>), dim3(nb), dim3(kRebuildBlock), 0, l.stream, g, \
+                     a, stg, dst)
+  if (l.dim == 2) {
+    if (lat) SPH_REBUILD(2, true);
+    else SPH_REBUILD(2, false);
+  } else {
+    if (lat) SPH_REBUILD(3, true);
+    else SPH_REBUILD(3, false);
+  }
+#undef SPH_REBUILD
 }
 
 #define SPH_INST(T)                                                                          \

@@ -114,7 +114,8 @@ __device__ __forceinline__ void density_impl(
     // the LDS list out to the stored list, row by row: a row's stores cover
     // consecutive lanes (coalesced); rows past a lane's count are not written
     const int L = blockIdx.x * kBlock + threadIdx.x;
-    st_nt(sl.count + L, cnt);
+    if (sl.nt) st_nt(sl.count + L, cnt);
+    else sl.count[L] = cnt;
     const int rows = min(cnt, (int)kDensityListCap<D, G>);
     int wave_rows = rows;
 #pragma unroll
@@ -128,8 +129,12 @@ __device__ __forceinline__ void density_impl(
       for (int u = 0; u < 8; ++u)
         if (q0 + u < CAP) ev[u] = nl.slot[min(q0 + u, CAP - 1)][threadIdx.x];
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (q0 + u < rows) st_nt(col + (size_t)(q0 + u) * sl.stride, ev[u]);
+      for (int u = 0; u < 8; ++u) {
+        if (q0 + u < rows) {
+          if (sl.nt) st_nt(col + (size_t)(q0 + u) * sl.stride, ev[u]);
+          else col[(size_t)(q0 + u) * sl.stride] = ev[u];
+        }
+      }
     }
   }
   const T sum = group_sum<G>(acc);
@@ -258,14 +263,14 @@ __global__ __launch_bounds__(kBlock) void tv_kernel(
       const int lin = !fluid ? p.cell[i] : drift_rebin<D>(g, k, p.cell[i], o, vh, dri, f);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        st_nt(td.stg.off + (d * n + i), o[d]);
-        st_nt(td.stg.vel + (d * n + i), vh[d]);
+        td.stg.off[d * n + i] = o[d];
+        td.stg.vel[d * n + i] = vh[d];
       }
-      st_nt(td.stg.cell + i, lin);
-      st_nt(td.stg.id + i, p.id[i]);
+      td.stg.cell[i] = lin;
+      td.stg.id[i] = p.id[i];
       if constexpr (VAR) {
-        st_nt(td.stg.mass + i, p.mass[i]);
-        st_nt(td.stg.h + i, p.h[i]);
+        td.stg.mass[i] = p.mass[i];
+        td.stg.h[i] = p.h[i];
       }
       if (f) atomicOr(td.flags, f);
     }
@@ -454,7 +459,7 @@ __device__ __forceinline__ void forces_impl(
   }
   if (lead) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) st_nt(acc_out + (d * n + i), ai[d]);
+    for (int d = 0; d < D; ++d) acc_out[d * n + i] = ai[d];
     if (bad) atomicOr(flags, kFlagNonfinite);
   }
   if constexpr (!FUSED) {
@@ -497,16 +502,16 @@ __device__ __forceinline__ void forces_impl(
       lin = celli;
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        st_nt(fo.stg.off + (d * n + i), oi[d]);
-        st_nt(fo.stg.vel + (d * n + i), vi[d]);
-        if (fo.g_next) st_nt(fo.g_next + (d * n + i), T(0));
+        fo.stg.off[d * n + i] = oi[d];
+        fo.stg.vel[d * n + i] = vi[d];
+        if (fo.g_next) fo.g_next[d * n + i] = T(0);
       }
-      if (fo.g_next) st_nt(fo.beta_next + i, T(0));
-      st_nt(fo.stg.cell + i, lin);
-      st_nt(fo.stg.id + i, id[i]);
+      if (fo.g_next) fo.beta_next[i] = T(0);
+      fo.stg.cell[i] = lin;
+      fo.stg.id[i] = id[i];
       if constexpr (VAR) {
-        st_nt(fo.stg.mass + i, mass[i]);
-        st_nt(fo.stg.h + i, hh[i]);
+        fo.stg.mass[i] = mass[i];
+        fo.stg.h[i] = hh[i];
       }
     } else if (lead) {
       const double m = VAR ? (double)mass[i] : (double)k.mass;
@@ -525,8 +530,8 @@ __device__ __forceinline__ void forces_impl(
         const Limited lim = limit_correction<D>(k, gi, rhoi, dr);
         if (fo.g_next) {
 #pragma unroll
-          for (int d = 0; d < D; ++d) st_nt(fo.g_next + (d * n + i), gi[d]);
-          st_nt(fo.beta_next + i, (T)lim.beta);
+          for (int d = 0; d < D; ++d) fo.g_next[d * n + i] = gi[d];
+          fo.beta_next[i] = (T)lim.beta;
         }
         double d2 = 0.0;
 #pragma unroll
@@ -540,14 +545,14 @@ __device__ __forceinline__ void forces_impl(
       lin = drift_rebin<D>(g, k, celli, o2, vh, dr, f);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        st_nt(fo.stg.off + (d * n + i), o2[d]);
-        st_nt(fo.stg.vel + (d * n + i), vh[d]);
+        fo.stg.off[d * n + i] = o2[d];
+        fo.stg.vel[d * n + i] = vh[d];
       }
-      st_nt(fo.stg.cell + i, lin);
-      st_nt(fo.stg.id + i, id[i]);
+      fo.stg.cell[i] = lin;
+      fo.stg.id[i] = id[i];
       if constexpr (VAR) {
-        st_nt(fo.stg.mass + i, mass[i]);
-        st_nt(fo.stg.h + i, hh[i]);
+        fo.stg.mass[i] = mass[i];
+        fo.stg.h[i] = hh[i];
       }
       if (f) atomicOr(flags, f);
     }
