@@ -381,3 +381,30 @@ def test_benchmark_workload_sweeps(dtype):
                           _oracle_nb(st["pos"], h * (1 + 1e-5), case.box))
     assert np.array_equal(counts[~band], np.diff(nb[0])[~band])
     assert sim.flags() == 0
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_rebuild_many_tiles_canonical_order(dtype):
+    """A 700x700 lattice has more cell-build tiles (538) than one block per CU
+    can run at once, so the runs use the cell build's plain instance.  After
+    fused steps the state is in (cell, id) order: the general cell build
+    (slot claims, scan, scatter, in-cell ranking by id) leaves every array
+    unchanged and returns the identity permutation."""
+    import torch
+    case = cases.taylor_green_2d(700, jitter=0.1, seed=21, name="tg2d_700")
+    sim = _sim(case, dtype)
+    nc0, nc1 = int(sim.params.ncell[0]), int(sim.params.ncell[1])
+    occ = sim.n / (nc0 * nc1)
+    t = max(1, min(int(2048 / (1.5 * occ)), 512, nc0))
+    assert -(-nc0 // t) * nc1 > 256
+    sim.run(4)
+    torch.cuda.synchronize()
+    assert sim.flags() == 0
+    keys = ("cell", "id", "off", "vel", "rho", "cs")
+    before = {k: getattr(sim, k).clone() for k in keys}
+    perm = torch.empty(sim.n, dtype=torch.int32, device=sim.device)
+    sim.build_cells(perm)
+    torch.cuda.synchronize()
+    for k in keys:
+        assert torch.equal(before[k], getattr(sim, k)), k
+    assert torch.equal(perm.long(), torch.arange(sim.n, device=sim.device))
