@@ -136,12 +136,17 @@ def _events_time(fn, reps):
 
 def time_steps(sim, steps, warmup):
     """Seconds per step of `steps` consecutive steps (one fused run, every
-    step's diagnostics kept on the device) and the mean ordered pair count."""
+    step's diagnostics kept on the device) and the mean ordered pair count.
+    The timed run continues the warm-up run (sph_kdk_run_resume): its first
+    step's correction sweep was evaluated by the warm-up's last force sweep,
+    and its own last force sweep evaluates the next step's, so the timed
+    region holds exactly `steps` steps of work."""
     import torch
     sim.run(warmup)
     rows = sim.diag_rows(steps)
     torch.cuda.synchronize()
-    t = _events_time(lambda: sim.run(steps, diag=rows), 1) / steps
+    resume = warmup > 0
+    t = _events_time(lambda: sim.run(steps, diag=rows, resume=resume), 1) / steps
     pairs = float(rows[:, 5].mean().item())
     return t, pairs
 

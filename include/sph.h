@@ -284,6 +284,21 @@ int32_t sph_kdk_run(const sph_params *p, sph_particles *parts, int32_t *cell_sta
                     int64_t step_index, int64_t nsteps, void *ws, size_t ws_bytes,
                     void *tapes, double *diag, void *stream);
 
+/* sph_kdk_run continuing a run: every sph_kdk_run or sph_kdk_step ends with
+ * the force sweep that (as inside a run) also evaluates the next step's
+ * correction and applies its first half kick and drift, into the workspace;
+ * this call starts from there instead of evaluating the correction sweep of
+ * its first step again.  Results are bit-identical to an uninterrupted run of
+ * the same steps.  The caller guarantees that nothing has changed the
+ * particle arrays, cell_start, the params or the workspace since the
+ * previous sph_kdk_run / sph_kdk_step / sph_kdk_run_resume on this workspace
+ * (that call ended at step step_index); this is not checked, and anything
+ * else gives wrong results.  No tapes (use sph_kdk_run to record).  Same
+ * arguments and errors as sph_kdk_run otherwise. */
+int32_t sph_kdk_run_resume(const sph_params *p, sph_particles *parts, int32_t *cell_start,
+                           int64_t step_index, int64_t nsteps, void *ws, size_t ws_bytes,
+                           double *diag, void *stream);
+
 /* sph_kdk_run without a workspace argument, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid allocation): the same kernels and arithmetic

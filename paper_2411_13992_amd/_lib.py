@@ -38,7 +38,7 @@ EXPORTS = (
     "sph_build_cells", "sph_density", "sph_forces", "sph_list_size", "sph_density_lists",
     "sph_forces_lists", "sph_wall_state", "sph_tv_correction",
     "sph_kdk_step",
-    "sph_kdk_run", "sph_kdk_run_static", "sph_dual_run", "sph_diagnostics", "sph_adjoint_step", "sph_adjoint_init", "sph_neighbor_counts",
+    "sph_kdk_run", "sph_kdk_run_resume", "sph_kdk_run_static", "sph_dual_run", "sph_diagnostics", "sph_adjoint_step", "sph_adjoint_init", "sph_neighbor_counts",
     "sph_get_flags", "sph_clear_flags", "sph_status_string",
 )
 
@@ -113,6 +113,8 @@ def load():
                          vp],
         "sph_kdk_run": [pp, P(SphParticles), vp, ctypes.c_int64, ctypes.c_int64, vp,
                         ctypes.c_size_t, vp, vp, vp],
+        "sph_kdk_run_resume": [pp, P(SphParticles), vp, ctypes.c_int64, ctypes.c_int64, vp,
+                               ctypes.c_size_t, vp, vp],
         "sph_kdk_run_static": [pp, P(SphParticles), vp, ctypes.c_int64, ctypes.c_int64, vp, vp,
                                vp, vp],
         "sph_dual_run": [pp, P(SphDualParams), P(SphParticles), vp, ctypes.c_int64, vp,

@@ -412,10 +412,16 @@ int32_t build_cells_t(const sph_params* p, sph_particles* parts, int32_t* cs, in
 // the density sweep; the state after step s is the state before step s + 1.
 // With `lists`, each step's density sweep records the neighbour lists its
 // force sweep then reads (the workspace holds the list regions).
+// With `resume`, the call continues a run: the workspace's staging already
+// holds the first step's corrected, kicked and drifted state (every run's
+// last force sweep leaves it there, with the next step's correction
+// diagnostics and cleared tile words), so the first step starts with the
+// cell build.  Partial rows alternate with the parity of the global step
+// index, so those diagnostics are where the continuing call looks for them.
 template <typename T>
 int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs_caller, int64_t step0,
                     int64_t nsteps, char* ws, char* tapes, double* diag, hipStream_t stream,
-                    bool lists, unsigned* flag_word = nullptr) {
+                    bool lists, unsigned* flag_word = nullptr, bool resume = false) {
   const bool var = is_var(p);
   const Sizes sz = sizes_of(p, var);
   const WsLayout w = ws_layout(sz);
@@ -424,6 +430,7 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs_calle
   const Launch l = launch_of(p, var, stream);
   unsigned* flags = flag_word ? flag_word : (unsigned*)(ws + w.flags);
   double* part[2] = {(double*)(ws + w.partials), (double*)(ws + w.partials2)};
+  auto part_of = [&](int64_t s) { return part[(step0 + s) & 1]; };   // step s of this call
   PArrays<T> a = arrays_of<T>(parts);
   PArrays<T> stg = staging_of<T>(ws, w, var);
   const CellBuf cb = cellbuf_of(ws, w.cellbuf, sz.ncells);
@@ -475,16 +482,18 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs_calle
     launch_multi_copy(stream, b);
   }
   // first step: 1. correction at r^n (Eq. 14-16), 2. half kick + drift + rebin
-  if (applies(step0)) {
+  if (resume) {
+    // done by the previous call's last force sweep
+  } else if (applies(step0)) {
     // one sweep: the correction, then the kick and drift with it, and the
     // cell build's tile words cleared on the side (every diagnostics partial
     // of the first step is written by its sweeps: no clearing)
     const TvDrift<T> td{a, stg, flags, cb.counts, cb.fill_ints};
     launch_tv<T>(l, g, k, a, cs, (T*)(ws + w.dr), tapes ? (T*)(tapes + tl.beta) : nullptr,
-                 nullptr, tapes ? (T*)(tapes + tl.g) : nullptr, diag ? part[0] : nullptr, td);
+                 nullptr, tapes ? (T*)(tapes + tl.g) : nullptr, diag ? part_of(0) : nullptr, td);
   } else {
     launch_fill(stream, cb.counts, cb.fill_ints, 0);
-    if (diag) launch_zero_partials(stream, sz.nblk, part[0]);
+    if (diag) launch_zero_partials(stream, sz.nblk, part_of(0));
     if (tapes) {
       // no correction this step: record g = 0, beta = 0 (the reverse then adds nothing)
       launch_zero<T>(stream, (T*)(tapes + tl.g), (long)dn);
@@ -505,12 +514,12 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs_calle
   rb.perm = tapes ? perm : nullptr;
   rb.flags = flags;
   for (int64_t s = 0; s < nsteps; ++s) {
-    double* cur_part = diag ? part[s & 1] : nullptr;
-    double* nxt = diag ? part[(s + 1) & 1] : nullptr;
+    double* cur_part = diag ? part_of(s) : nullptr;
+    double* nxt = diag ? part_of(s + 1) : nullptr;
     // 3. cell build, folding the previous step's diagnostics in its extra blocks
     rb.fold = DiagFold{};
     if (diag && s > 0)
-      rb.fold = DiagFold{part[(s - 1) & 1], sz.nblk * kWavesPerBlock,
+      rb.fold = DiagFold{part_of(s - 1), sz.nblk * kWavesPerBlock,
                          diag + (size_t)SPH_NDIAG * (s - 1)};
     rb.cs_old = csbuf[cur];
     rb.cs_new = csbuf[cur ^ 1];
@@ -532,42 +541,43 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs_calle
       if (s + 1 < nsteps && !record_pre(b, tape_of(s + 1))) return SPH_E_INTERNAL_COPY;
       launch_multi_copy(stream, b);
     }
-    if (s + 1 < nsteps) {
-      // 5-6. accelerations, 7. kick; the next step's correction and drift
-      FusedOut<T> fo;
-      fo.apply_next = applies(step0 + s + 1) ? 1 : 0;
-      fo.stg = stg;
-      fo.counts = nullptr;
-      fo.slot = nullptr;
-      fo.part_cur = cur_part;
-      fo.part_next = nxt;
-      fo.g_next = nullptr;
-      fo.beta_next = nullptr;
-      if (tapes) {
-        char* tn = tape_of(s + 1);
-        if (fo.apply_next) {
-          fo.g_next = (T*)(tn + tl.g);
-          fo.beta_next = (T*)(tn + tl.beta);
-        } else {
-          launch_zero<T>(stream, (T*)(tn + tl.g), (long)dn);
-          launch_zero<T>(stream, (T*)(tn + tl.beta), (long)n);
-        }
+    // 5-6. accelerations, 7. kick; the next step's correction and drift (the
+    // last step's too: a later call may resume from them)
+    const bool last = s + 1 == nsteps;
+    FusedOut<T> fo{};
+    fo.apply_next = applies(step0 + s + 1) ? 1 : 0;
+    fo.stg = stg;
+    fo.counts = nullptr;
+    fo.slot = nullptr;
+    fo.part_cur = cur_part;
+    fo.part_next = last ? part_of(s + 1) : nxt;
+    fo.g_next = nullptr;
+    fo.beta_next = nullptr;
+    if (tapes && !last) {
+      char* tn = tape_of(s + 1);
+      if (fo.apply_next) {
+        fo.g_next = (T*)(tn + tl.g);
+        fo.beta_next = (T*)(tn + tl.beta);
+      } else {
+        launch_zero<T>(stream, (T*)(tn + tl.g), (long)dn);
+        launch_zero<T>(stream, (T*)(tn + tl.beta), (long)n);
       }
-      launch_forces_fused<T>(l, g, k, a, cs, fo, flags, sl);
-    } else {
-      // 5-6. accelerations at (r^{n+1}, v', rho^{n+1}), 7. second half kick in
-      // the same sweep, into the staging velocities (free after this step's
-      // cell build); then the fold and their copy back in one launch
-      FusedOut<T> kick{};
-      kick.kick_vel = stg.vel;
-      kick.part_cur = cur_part;
-      launch_forces<T>(l, g, k, a, cs, a.vel, a.acc, flags, sl, kick);
+    }
+    if (last) {
+      // the state after the run: its velocity into scratch (the sweep still
+      // reads the current one), copied back with the diagnostics fold; the
+      // tile words cleared for a resuming call's first cell build
+      fo.kick_vel = (T*)(ws + w.dr);
+      fo.clear = cb.counts;
+      fo.clear_n = cb.fill_ints;
+    }
+    launch_forces_fused<T>(l, g, k, a, cs, fo, flags, sl);
+    if (last)
       launch_fold_copy(stream,
                        diag ? DiagFold{cur_part, sz.nblk * kWavesPerBlock,
                                        diag + (size_t)SPH_NDIAG * s}
                             : DiagFold{},
-                       stg.vel, a.vel, t * dn);
-    }
+                       fo.kick_vel, a.vel, t * dn);
   }
   return hip_status();
 }
@@ -1022,7 +1032,7 @@ int32_t sph_tv_correction(const sph_params* p, const sph_particles* parts,
 
 static int32_t kdk_common(const sph_params* p, sph_particles* parts, int32_t* cell_start,
                           int64_t step_index, int64_t nsteps, void* ws, size_t ws_bytes,
-                          void* tape, double* diag, void* stream) {
+                          void* tape, double* diag, void* stream, bool resume = false) {
   int32_t st = check_params(p);
   if (st != SPH_OK) return st;
   st = check_particles(p, parts, true);
@@ -1039,7 +1049,7 @@ static int32_t kdk_common(const sph_params* p, sph_particles* parts, int32_t* ce
   return dispatch(p, [&](auto tag) {
     using T = decltype(tag);
     return run_steps_t<T>(p, parts, cell_start, step_index, nsteps, (char*)ws, (char*)tape, diag,
-                          (hipStream_t)stream, true);
+                          (hipStream_t)stream, true, nullptr, resume);
   });
 }
 
@@ -1053,6 +1063,13 @@ int32_t sph_kdk_run(const sph_params* p, sph_particles* parts, int32_t* cell_sta
                     int64_t step_index, int64_t nsteps, void* ws, size_t ws_bytes, void* tapes,
                     double* diag, void* stream) {
   return kdk_common(p, parts, cell_start, step_index, nsteps, ws, ws_bytes, tapes, diag, stream);
+}
+
+int32_t sph_kdk_run_resume(const sph_params* p, sph_particles* parts, int32_t* cell_start,
+                           int64_t step_index, int64_t nsteps, void* ws, size_t ws_bytes,
+                           double* diag, void* stream) {
+  return kdk_common(p, parts, cell_start, step_index, nsteps, ws, ws_bytes, nullptr, diag, stream,
+                    true);
 }
 
 int32_t sph_kdk_run_static(const sph_params* p, sph_particles* parts, int32_t* cell_start,

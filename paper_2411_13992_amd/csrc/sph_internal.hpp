@@ -62,14 +62,16 @@ struct FusedOut {
   PArrays<T> stg;
   int* counts;         // zeroed histogram for the next cell build (null: no slot claims)
   int* slot;
-  double* part_cur;    // null: no diagnostics
-  double* part_next;
+  double* part_cur;    // null: no diagnostics of this step
+  double* part_next;   // null: none of the next step's correction
   T* g_next;           // null: no tape; else the next step's correction sum g [D][N]
   T* beta_next;        // and limiter value [N] (written when apply_next)
-  // unfused sweep only: the second half kick v' + dt/2 a of every fluid
-  // particle into kick_vel [D][N] (not the swept velocities: other blocks
-  // still read those), its diagnostics into part_cur
+  // when set: the velocity after this step's second half kick into
+  // kick_vel [D][N] (not the swept velocities: other blocks still read them)
   T* kick_vel = nullptr;
+  // when set: clear[0, clear_n) zeroed on the side (the cell build's tile words)
+  int* clear = nullptr;
+  long clear_n = 0;
 };
 
 // ---- sweeps (sweeps.hip)
@@ -94,11 +96,10 @@ void launch_tv(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays
                const int* cs, T* dr, T* beta, double* s_out, T* g_out, double* partials,
                const TvDrift<T>& td = TvDrift<T>{});
 // with sl.entry set, over the stored lists of the density sweep just before
-// with kick.kick_vel set, the step's second half kick too (see FusedOut)
 template <typename T>
 void launch_forces(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                    const int* cs, const T* vel, T* acc_out, unsigned* flags,
-                   const StoredList& sl = StoredList{}, const FusedOut<T>& kick = FusedOut<T>{});
+                   const StoredList& sl = StoredList{});
 // with sl.entry set, over the stored lists of the density sweep just before
 template <typename T>
 void launch_forces_fused(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,

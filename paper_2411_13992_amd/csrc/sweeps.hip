@@ -305,6 +305,13 @@ __device__ __forceinline__ void forces_impl(
     const StoredList& sl) {
   __shared__ NeighbourList<LIST ? 1 : ForceCap<G>::value> nl;
   const int n = g.n;
+  if constexpr (FUSED) {
+    if (fo.clear) {
+      for (long x = (long)blockIdx.x * kBlock + threadIdx.x; x < fo.clear_n;
+           x += (long)gridDim.x * kBlock)
+        fo.clear[x] = 0;
+    }
+  }
   const Cols<T, D> offc(off, n), velc(vel, n);
   const Cols<T, 1> rhoc(rho, n), hc(hh, n), mc(mass, n);
   // candidate-test values: offsets, then h (variable resolution)
@@ -462,35 +469,6 @@ __device__ __forceinline__ void forces_impl(
     for (int d = 0; d < D; ++d) acc_out[d * n + i] = ai[d];
     if (bad) atomicOr(flags, kFlagNonfinite);
   }
-  if constexpr (!FUSED) {
-    if (fo.kick_vel) {
-      // the step's second half kick (the kick sweep's arithmetic): fluid only
-      double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // ke, mom x3, vmax
-      if (lead && !wall) {
-        const double m = VAR ? (double)mass[i] : (double)k.mass;
-        double v2 = 0.0;
-        bool badv = false;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          const T vn = tfma(k.half_dt, ai[d], vi[d]);
-          fo.kick_vel[d * n + i] = vn;
-          badv |= !isfinite(vn);
-          v2 += (double)vn * (double)vn;
-          v[1 + d] = m * (double)vn;
-        }
-        v[0] = 0.5 * m * v2;
-        v[4] = sqrt(v2);
-        if (badv) atomicOr(flags, kFlagNonfinite);
-      } else if (lead) {
-#pragma unroll
-        for (int d = 0; d < D; ++d) fo.kick_vel[d * n + i] = vi[d];
-      }
-      if (fo.part_cur) {
-        const int cols[5] = {0, 1, 2, 3, 4};
-        wave_partials<5>(fo.part_cur, cols, v, 1u << 4);
-      }
-    }
-  }
   if constexpr (FUSED) {
     // second half kick of this step, then the next step's half kick, correction
     // and drift; the moved particle goes to the staging buffers
@@ -504,6 +482,7 @@ __device__ __forceinline__ void forces_impl(
       for (int d = 0; d < D; ++d) {
         fo.stg.off[d * n + i] = oi[d];
         fo.stg.vel[d * n + i] = vi[d];
+        if (fo.kick_vel) fo.kick_vel[d * n + i] = vi[d];
         if (fo.g_next) fo.g_next[d * n + i] = T(0);
       }
       if (fo.g_next) fo.beta_next[i] = T(0);
@@ -517,13 +496,17 @@ __device__ __forceinline__ void forces_impl(
       const double m = VAR ? (double)mass[i] : (double)k.mass;
       T vh[3], dr[3] = {T(0), T(0), T(0)};
       double v2 = 0.0;
+      bool badv = false;
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         const T vn = tfma(k.half_dt, ai[d], vi[d]);
+        if (fo.kick_vel) fo.kick_vel[d * n + i] = vn;
+        badv |= !isfinite(vn);
         v2 += (double)vn * (double)vn;
         v[1 + d] = m * (double)vn;
         vh[d] = tfma(k.half_dt, ai[d], vn);
       }
+      if (badv) atomicOr(flags, kFlagNonfinite);
       v[0] = 0.5 * m * v2;
       v[4] = sqrt(v2);
       if (fo.apply_next) {
@@ -563,6 +546,8 @@ __device__ __forceinline__ void forces_impl(
     if (fo.part_cur) {
       const int cur_cols[5] = {0, 1, 2, 3, 4};
       wave_partials<5>(fo.part_cur, cur_cols, v, 1u << 4);
+    }
+    if (fo.part_next) {
       const int next_cols[3] = {6, 7, 8};
       wave_partials<3>(fo.part_next, next_cols, v + 5, 1u << 2, 3u);
     }
@@ -726,14 +711,15 @@ void launch_tv(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays
 template <typename T>
 void launch_forces(const Launch& l, const Grid& g, const Coeffs<T>& k, const PArrays<T>& p,
                    const int* cs, const T* vel, T* acc_out, unsigned* flags,
-                   const StoredList& sl, const FusedOut<T>& kick) {
+                   const StoredList& sl) {
   if (g.n == 0) return;
+  FusedOut<T> none{};
   if (sl.entry)
     SPH_SWEEP(forces_list_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, vel, p.rho, p.mass, p.h,
-                                           p.id, acc_out, flags, kick, sl));
+                                           p.id, acc_out, flags, none, sl));
   else
     SPH_SWEEP(forces_kernel, SPH_ARGS(g, k, p.cell, cs, p.off, vel, p.rho, p.mass, p.h, p.id,
-                                      acc_out, flags, kick));
+                                      acc_out, flags, none));
 }
 
 template <typename T>
@@ -767,7 +753,7 @@ void launch_wall_state(const Launch& l, const Grid& g, const Coeffs<T>& k, const
                              const int*, T*, T*, double*, T*, double*, const TvDrift<T>&);   \
   template void launch_forces<T>(const Launch&, const Grid&, const Coeffs<T>&,               \
                                  const PArrays<T>&, const int*, const T*, T*, unsigned*,     \
-                                 const StoredList&, const FusedOut<T>&);                     \
+                                 const StoredList&);                                         \
   template void launch_forces_fused<T>(const Launch&, const Grid&, const Coeffs<T>&,         \
                                        const PArrays<T>&, const int*, const FusedOut<T>&,    \
                                        unsigned*, const StoredList&);

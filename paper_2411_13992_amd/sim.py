@@ -145,6 +145,10 @@ class Simulation:
         self._diag_own = torch.zeros(_lib.SPH_NDIAG, dtype=torch.float64, device=dev)
         self.diag = self._diag_own
         self.step_index = 0
+        # step index at which the last run() or step() left the state (None once
+        # anything else touched the state, params or workspace): run(resume=True)
+        # continues only from there
+        self._resume_at = None
         pos_dev = torch.as_tensor(pos, device=dev).contiguous()
         s = _stream()
         _lib.call("sph_bin_positions", ctypes.byref(self.params), _vp(pos_dev),
@@ -176,16 +180,19 @@ class Simulation:
 
     # ------------------------------------------------------------ hot path
     def build_cells(self, perm: torch.Tensor | None = None) -> None:
+        self._resume_at = None
         _lib.call("sph_build_cells", ctypes.byref(self.params), ctypes.byref(self.parts()),
                   _vp(self.cs), _vp(perm), _vp(self.ws), self.ws_bytes, _stream())
 
     def density(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        self._resume_at = None
         out = self.rho if out is None else out
         _lib.call("sph_density", ctypes.byref(self.params), ctypes.byref(self.parts()),
                   _vp(self.cs), _vp(out), _stream())
         return out
 
     def forces(self, vel: torch.Tensor | None = None, out: torch.Tensor | None = None):
+        self._resume_at = None
         vel = self.vel if vel is None else vel
         out = self.acc if out is None else out
         _lib.call("sph_forces", ctypes.byref(self.params), ctypes.byref(self.parts()),
@@ -194,6 +201,7 @@ class Simulation:
 
     def neighbor_lists(self) -> torch.Tensor:
         """A device buffer for the stored neighbour lists (sph_list_size bytes)."""
+        self._resume_at = None
         nbytes = _lib.list_size(self.params)
         if nbytes == 0:
             raise RuntimeError("stored neighbour lists cannot index this many particles")
@@ -201,6 +209,7 @@ class Simulation:
 
     def density_lists(self, lists: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """sph_density that also records the neighbour lists into `lists`."""
+        self._resume_at = None
         out = self.rho if out is None else out
         _lib.call("sph_density_lists", ctypes.byref(self.params), ctypes.byref(self.parts()),
                   _vp(self.cs), _vp(out), _vp(lists), lists.numel(), _stream())
@@ -209,6 +218,7 @@ class Simulation:
     def forces_lists(self, lists: torch.Tensor, vel: torch.Tensor | None = None,
                      out: torch.Tensor | None = None) -> torch.Tensor:
         """sph_forces over lists recorded by density_lists at the same state."""
+        self._resume_at = None
         vel = self.vel if vel is None else vel
         out = self.acc if out is None else out
         _lib.call("sph_forces_lists", ctypes.byref(self.params), ctypes.byref(self.parts()),
@@ -217,6 +227,7 @@ class Simulation:
 
     def tv_correction(self):
         """Eq. 14-16 at the current state: dict of dr, beta, s (FP64), g."""
+        self._resume_at = None
         d, n, dev, T = self.dim, self.n, self.device, self.T
         out = {"dr": torch.zeros((d, n), dtype=T, device=dev),
                "beta": torch.zeros(n, dtype=T, device=dev),
@@ -228,6 +239,7 @@ class Simulation:
         return out
 
     def neighbor_counts(self) -> torch.Tensor:
+        self._resume_at = None
         out = torch.zeros(self.n, dtype=torch.int32, device=self.device)
         _lib.call("sph_neighbor_counts", ctypes.byref(self.params), ctypes.byref(self.parts()),
                   _vp(self.cs), _vp(out), _stream())
@@ -236,6 +248,7 @@ class Simulation:
     def wall_state(self) -> None:
         """Wall particles' density and no-slip mirror velocity from the fluid
         (sph_wall_state); nothing without walls."""
+        self._resume_at = None
         if self.n_wall:
             _lib.call("sph_wall_state", ctypes.byref(self.params), ctypes.byref(self.parts()),
                       _vp(self.cs), _stream())
@@ -243,6 +256,7 @@ class Simulation:
     def init_fields(self) -> None:
         """rho^0 by summation (Eq. 8), the walls' state, and a^0 from the
         initial velocity."""
+        self._resume_at = None
         self.density()
         self.wall_state()
         self.forces()
@@ -261,14 +275,21 @@ class Simulation:
                       _vp(self.cs), self.step_index, _vp(self.ws), self.ws_bytes, _vp(tape),
                       _vp(self.diag) if diag else None, s)
             self.step_index += 1
+            self._resume_at = self.step_index
 
-    def run(self, nsteps: int, diag=True, tapes: torch.Tensor | None = None) -> torch.Tensor | None:
+    def run(self, nsteps: int, diag=True, tapes: torch.Tensor | None = None,
+            resume: bool = False) -> torch.Tensor | None:
         """nsteps steps in one fused call (sph_kdk_run).  diag: True keeps every
-        step's diagnostics (returned as an (nsteps, 9) FP64 device tensor, the
-        last row also in self.diag), False skips them, or a preallocated
+        step's diagnostics (returned as an (nsteps, 9) FP64 device tensor;
+        self.diag then views its last row), False skips them, or a preallocated
         (nsteps, 9) FP64 device tensor to fill.  tapes: optional uint8 device
         tensor of at least nsteps x tape_bytes() bytes (one tape per step,
-        contiguous)."""
+        contiguous).  resume: continue the previous run() or step()
+        (sph_kdk_run_resume: its first step's correction was evaluated by that
+        call's last force sweep; bit-identical results); only valid when
+        nothing has changed the particle tensors since then (refused when a
+        method of this class did; writes into the tensors themselves are not
+        seen), without tapes."""
         if nsteps <= 0:
             return None
         if diag is True:
@@ -281,12 +302,22 @@ class Simulation:
             if (tapes.dtype != torch.uint8 or not tapes.is_contiguous()
                     or tapes.numel() < nsteps * self.tape_bytes()):
                 raise ValueError("tapes must be a contiguous uint8 tensor of nsteps x tape_bytes()")
-        _lib.call("sph_kdk_run", ctypes.byref(self.params), ctypes.byref(self.parts()),
-                  _vp(self.cs), self.step_index, nsteps, _vp(self.ws), self.ws_bytes,
-                  _vp(tapes), _vp(d), _stream())
+        if resume:
+            if tapes is not None:
+                raise ValueError("a resumed run records no tapes")
+            if self._resume_at != self.step_index:
+                raise ValueError("resume needs the state a run() or step() left, untouched")
+            _lib.call("sph_kdk_run_resume", ctypes.byref(self.params), ctypes.byref(self.parts()),
+                      _vp(self.cs), self.step_index, nsteps, _vp(self.ws), self.ws_bytes,
+                      _vp(d), _stream())
+        else:
+            _lib.call("sph_kdk_run", ctypes.byref(self.params), ctypes.byref(self.parts()),
+                      _vp(self.cs), self.step_index, nsteps, _vp(self.ws), self.ws_bytes,
+                      _vp(tapes), _vp(d), _stream())
         if d is not None:
             self.diag = d[-1]
         self.step_index += nsteps
+        self._resume_at = self.step_index
         return d
 
     def dual_run(self, nsteps: int, cfl_ad: float = 0.25, cfl_ac: float = 0.6,
@@ -296,6 +327,7 @@ class Simulation:
         continuity equation, step sizes of Eq. 9-11 chosen on the device.
         Returns (diagnostics rows (nsteps, 9), step records (nsteps, 3):
         dt_ad, substeps, time covered), FP64 device tensors."""
+        self._resume_at = None
         q = _lib.SphDualParams(cfl_ad=cfl_ad, cfl_ac=cfl_ac, u_ref=self.cfg.u_ref,
                                nu=self.cfg.eta / self.cfg.rho0, max_substeps=max_substeps)
         d = (torch.empty((nsteps, _lib.SPH_NDIAG), dtype=torch.float64, device=self.device)
@@ -317,6 +349,7 @@ class Simulation:
         return _lib.tape_size(self.params)
 
     def set_xi(self, xi: float) -> None:
+        self._resume_at = None
         self.params.xi = float(xi)
 
     # ------------------------------------------------------------ checkpoints
@@ -331,6 +364,7 @@ class Simulation:
         return snap
 
     def restore(self, snap: dict) -> None:
+        self._resume_at = None
         for k in self._STATE:
             getattr(self, k).copy_(snap[k])
         if self.var:
@@ -340,6 +374,7 @@ class Simulation:
 
     def set_velocity(self, vel_by_id: torch.Tensor) -> None:
         """Replace velocities from an id-ordered (D, N) tensor."""
+        self._resume_at = None
         self.vel.copy_(vel_by_id.to(self.device, self.T)[:, self.id.long()])
 
     def velocity_by_id(self) -> torch.Tensor:
@@ -350,6 +385,7 @@ class Simulation:
     def diagnostics(self, fresh: bool = False) -> dict:
         """FP64 diagnostics of the last step (or of the current state alone)."""
         if fresh:
+            self._resume_at = None
             self.diag = self._diag_own
             _lib.call("sph_diagnostics", ctypes.byref(self.params), ctypes.byref(self.parts()),
                       _vp(self.cs), _vp(self.ws), self.ws_bytes, _vp(self.diag), _stream())
@@ -375,6 +411,7 @@ class Simulation:
     def load_checkpoint(self, path: str) -> None:
         """Restore a state written by save_checkpoint for the same run
         parameters (checked byte for byte, xi aside)."""
+        self._resume_at = None
         with np.load(path) as z:
             mine = bytearray(bytes(self.params))
             theirs = bytearray(z["params"].tobytes())

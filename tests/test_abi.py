@@ -198,3 +198,21 @@ def test_list_entry_points_check_arguments():
     assert L.sph_density_lists(*args, 4096, size.value - 1, None) == -3
     assert L.sph_forces_lists(*args, 4096, None, size.value, None) == -1
     assert L.sph_forces_lists(*args, 4096, 4096, size.value - 1, None) == -3
+
+
+def test_resume_checks_arguments():
+    """sph_kdk_run_resume validates its arguments like sph_kdk_run, before
+    enqueueing anything."""
+    L = _lib.load()
+    p = _params()
+    parts = _lib.SphParticles()
+    for name in ("cell", "id", "off", "vel", "acc", "rho"):
+        setattr(parts, name, 4096)       # never dereferenced: the checks fail first
+    assert L.sph_kdk_run_resume(ctypes.byref(p), ctypes.byref(parts), None, 0, 3, 4096, 1 << 40,
+                                None, None) == -1
+    assert L.sph_kdk_run_resume(ctypes.byref(p), ctypes.byref(parts), 4096, 0, 3, None, 1 << 40,
+                                None, None) == -1
+    assert L.sph_kdk_run_resume(ctypes.byref(p), ctypes.byref(parts), 4096, 0, 3, 4096, 16,
+                                None, None) == -3
+    assert L.sph_kdk_run_resume(ctypes.byref(p), ctypes.byref(parts), 4096, -1, 3, 4096, 1 << 40,
+                                None, None) == -1

@@ -408,3 +408,62 @@ def test_rebuild_many_tiles_canonical_order(dtype):
     for k in keys:
         assert torch.equal(before[k], getattr(sim, k)), k
     assert torch.equal(perm.long(), torch.arange(sim.n, device=sim.device))
+
+
+def _cavity_small():
+    return cases.lid_driven_cavity(12, jitter=0.1, seed=31)
+
+
+@pytest.mark.parametrize("name,dtype,tv_every", [("jitter64", "f32", 1), ("jitter64", "f64", 1),
+                                                 ("jitter64", "f32", 3), ("tg3d_12", "f32", 1),
+                                                 ("varres_small", "f32", 1), ("cavity", "f32", 1)])
+def test_resumed_run_equals_one_run(name, dtype, tv_every):
+    """sph_kdk_run_resume continues where the previous run or step left off
+    (its first correction and drift come from that call's last force sweep):
+    3 + 4 resumed steps, and 2 single steps + 5 resumed, equal one run of 7
+    bit for bit, states and every diagnostics row, also when the earlier call
+    kept no diagnostics."""
+    import torch
+    case = _cavity_small() if name == "cavity" else SMALL[name]
+    ref = _sim(case, dtype, tv_every=tv_every)
+    d_ref = ref.run(7)
+    a = _sim(case, dtype, tv_every=tv_every)
+    d1 = a.run(3)
+    d2 = a.run(4, resume=True)
+    b = _sim(case, dtype, tv_every=tv_every)
+    b.step(2)
+    d3 = b.run(5, resume=True)
+    c = _sim(case, dtype, tv_every=tv_every)
+    c.run(4, diag=False)
+    d4 = c.run(3, resume=True)
+    torch.cuda.synchronize()
+    for sim in (a, b, c):
+        for key in ("cell", "id", "off", "vel", "acc", "rho", "cs"):
+            assert torch.equal(getattr(ref, key), getattr(sim, key)), key
+        assert sim.flags() == 0
+    assert torch.equal(torch.cat([d1, d2]), d_ref)
+    assert torch.equal(d3, d_ref[2:])
+    assert torch.equal(d4, d_ref[4:])
+
+
+def test_resume_refused_after_state_changes():
+    """The Python layer refuses to resume once anything but a run or step
+    touched the simulation, and a resumed run records no tapes."""
+    case = SMALL["jitter64"]
+    sim = _sim(case, "f32")
+    with pytest.raises(ValueError):
+        sim.run(2, resume=True)          # nothing to resume from yet
+    sim.run(2)
+    sim.set_xi(sim.params.xi)
+    with pytest.raises(ValueError):
+        sim.run(2, resume=True)
+    sim.run(2)
+    sim.density()
+    with pytest.raises(ValueError):
+        sim.run(2, resume=True)
+    sim.step(1)
+    sim.run(2, resume=True)
+    import torch
+    tapes = torch.zeros((2, sim.tape_bytes()), dtype=torch.uint8, device=sim.device)
+    with pytest.raises(ValueError):
+        sim.run(2, resume=True, tapes=tapes)
