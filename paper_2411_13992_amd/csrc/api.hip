@@ -170,15 +170,10 @@ ListLayout list_layout(const Sizes& s) {
   return ll;
 }
 
-// Stored lists up to this size are written with non-temporal stores (the
-// eight XCDs' L2s hold 32 MiB together)
-constexpr size_t kListNtBytes = 24u << 20;
-
 // The stored lists in a workspace (lists usable)
 StoredList ws_lists(char* ws, const WsLayout& w, const Sizes& s) {
   return StoredList{(unsigned*)(ws + w.nlist), (int*)(ws + w.ncount), s.nblk * kBlock,
-                    s.dim == 2 ? (int*)(ws + w.nruns) : nullptr,
-                    w.ncount - w.nlist <= kListNtBytes ? 1 : 0};
+                    s.dim == 2 ? (int*)(ws + w.nruns) : nullptr};
 }
 
 TapeLayout tape_layout(const Sizes& s) {
@@ -907,8 +902,7 @@ static int32_t list_of(const sph_params* p, const void* lists, size_t list_bytes
   if (list_bytes < ll.total) return SPH_E_WORKSPACE;
   char* b = (char*)const_cast<void*>(lists);
   *out = StoredList{(unsigned*)(b + ll.entries), (int*)(b + ll.counts), sz.nblk * kBlock,
-                    sz.dim == 2 ? (int*)(b + ll.runs) : nullptr,
-                    ll.counts - ll.entries <= kListNtBytes ? 1 : 0};
+                    sz.dim == 2 ? (int*)(b + ll.runs) : nullptr};
   return SPH_OK;
 }
 

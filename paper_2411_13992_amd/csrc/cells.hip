@@ -318,9 +318,9 @@ constexpr int kRebuildCap = 2048;        // tile particles ranked in LDS
 constexpr int kRebuildMaxCells = 512;    // cells per tile (host: T <= this)
 constexpr int kRebuildBlock = 1024;     // threads per block
 // Up to this many tiles every tile's block runs at once (one per CU) and the
-// launch is one dependent chain: members' values are then loaded early and
-// stored with non-temporal stores.  With more tiles both cost time (measured
-// on a 1M-particle workload) and the plain path runs.
+// launch is one dependent chain: members' values are then loaded early.  With
+// more tiles the registers that takes cost a block per CU (measured on a
+// 1M-particle workload) and the plain path runs.
 constexpr int kRebuildLatencyTiles = 256;
 
 int rebuild_tile_cells(int dim, const int nc[3], long n, bool var) {
@@ -617,11 +617,7 @@ __global__ __launch_bounds__(kRebuildBlock, (LAT || D == 3) ? 4 : 8) void rebuil
   }
   __syncthreads();
   const int prefix = s_prefix;
-  // the tile's output: non-temporal stores in the latency regime
-  auto put = [&](auto* ptr, auto v) {
-    if constexpr (LAT) st_nt(ptr, v);
-    else *ptr = v;
-  };
+  auto put = [&](auto* ptr, auto v) { *ptr = v; };
   for (int c = tid; c < tc; c += NB) put(a.cs_new + (tile0 + c), prefix + s_off[c]);
   if (tile == a.ntiles - 1 && tid == 0) {
     a.cs_new[a.ncells] = prefix + nmem;

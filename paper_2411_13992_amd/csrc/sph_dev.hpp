@@ -90,13 +90,6 @@ __device__ __forceinline__ T wendland_shape(T q) {
   return t2 * t2 * tfma(q, T(2), T(1));
 }
 
-// A store that the next kernel, not this one, reads back: non-temporal, so
-// the output does not wait in L2 for the end-of-kernel write-back.  Used for
-// the cell build's output and stored lists that fit in the L2s (measured
-// faster); the force sweep's outputs stay ordinary stores.
-template <typename T>
-__device__ __forceinline__ void st_nt(T* p, T v) { __builtin_nontemporal_store(v, p); }
-
 // ---------------------------------------------------------------- sums
 // Kahan-compensated accumulator (compensation on for FP32 sweeps).
 template <typename T, bool COMP>
@@ -968,10 +961,6 @@ struct StoredList {
   // per block, the first particle and the length of its three stencil rows'
   // runs (2-D, as the position stage found them): six ints, or null
   int* runs = nullptr;
-  // lists written with non-temporal stores: set when they fit in the L2s
-  // (then the end-of-launch write-back is what those stores avoid; larger
-  // lists are read back faster after ordinary stores)
-  int nt = 0;
 };
 
 // What a pair body reads of a neighbour: offsets, velocity, density, and

@@ -114,8 +114,7 @@ __device__ __forceinline__ void density_impl(
     // the LDS list out to the stored list, row by row: a row's stores cover
     // consecutive lanes (coalesced); rows past a lane's count are not written
     const int L = blockIdx.x * kBlock + threadIdx.x;
-    if (sl.nt) st_nt(sl.count + L, cnt);
-    else sl.count[L] = cnt;
+    sl.count[L] = cnt;
     const int rows = min(cnt, (int)kDensityListCap<D, G>);
     int wave_rows = rows;
 #pragma unroll
@@ -129,12 +128,8 @@ __device__ __forceinline__ void density_impl(
       for (int u = 0; u < 8; ++u)
         if (q0 + u < CAP) ev[u] = nl.slot[min(q0 + u, CAP - 1)][threadIdx.x];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (q0 + u < rows) {
-          if (sl.nt) st_nt(col + (size_t)(q0 + u) * sl.stride, ev[u]);
-          else col[(size_t)(q0 + u) * sl.stride] = ev[u];
-        }
-      }
+      for (int u = 0; u < 8; ++u)
+        if (q0 + u < rows) col[(size_t)(q0 + u) * sl.stride] = ev[u];
     }
   }
   const T sum = group_sum<G>(acc);
