@@ -51,11 +51,18 @@ __device__ __forceinline__ double substep_dt(const DualCoeffs& q, const DualSlot
   return fmin(q.cfl_ac * q.h_min / (vk + q.c0), dt_ad - t);
 }
 
-// Largest |v| of the wavefront's valid lanes into slot->vmax_bits.
+// Largest |v| of the wavefront's valid lanes into slot->vmax_bits.  The
+// slot only grows, so a wavefront whose maximum is not above what the slot
+// already holds skips its atomic: one address takes a handful of atomics per
+// launch instead of one per wavefront (they serialise there).  A stale read
+// only costs an unneeded atomic; the result is the same maximum.
 __device__ __forceinline__ void wave_vmax(double speed, DualSlot* slot) {
   const double m = wave_max(speed);
-  if (threadIdx.x % kWave == 0 && m > 0.0)
-    atomicMax(&slot->vmax_bits, double_to_bits(m));
+  if (threadIdx.x % kWave == 0 && m > 0.0) {
+    const unsigned long long b = double_to_bits(m);
+    if (__hip_atomic_load(&slot->vmax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b)
+      atomicMax(&slot->vmax_bits, b);
+  }
 }
 
 // The listed neighbour walk of particle i on the step's topology: body(j,
@@ -460,8 +467,7 @@ __global__ __launch_bounds__(kBlock) void dual_start_kernel(int n, int dim, cons
   double v2 = 0.0;
   if (i < n)
     for (int d = 0; d < dim; ++d) v2 += (double)vel[(size_t)d * n + i] * (double)vel[(size_t)d * n + i];
-  const double m = wave_max(sqrt(v2));
-  if (threadIdx.x % kWave == 0 && m > 0.0) atomicMax(&clk[0].vmax_bits, double_to_bits(m));
+  wave_vmax(sqrt(v2), &clk[0]);
 }
 
 // ------------------------------------------------------------------ launchers
