@@ -51,17 +51,26 @@ __device__ __forceinline__ double substep_dt(const DualCoeffs& q, const DualSlot
   return fmin(q.cfl_ac * q.h_min / (vk + q.c0), dt_ad - t);
 }
 
-// Largest |v| of the wavefront's valid lanes into slot->vmax_bits.  The
-// slot only grows, so a wavefront whose maximum is not above what the slot
-// already holds skips its atomic: one address takes a handful of atomics per
-// launch instead of one per wavefront (they serialise there).  A stale read
-// only costs an unneeded atomic; the result is the same maximum.
-__device__ __forceinline__ void wave_vmax(double speed, DualSlot* slot) {
-  const double m = wave_max(speed);
-  if (threadIdx.x % kWave == 0 && m > 0.0) {
-    const unsigned long long b = double_to_bits(m);
-    if (__hip_atomic_load(&slot->vmax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b)
-      atomicMax(&slot->vmax_bits, b);
+// Largest |v| of the block's valid lanes into slot->vmax_bits; every thread
+// of the block calls it (it synchronises the block).  Requests to one address
+// serialise where device-scope atomics are served, so the block reduces first
+// (one request per block, not per wavefront), and as the slot only grows a
+// block whose maximum is not above what the slot already holds skips its
+// atomic.  A stale read only costs an unneeded atomic; the result is the same
+// maximum.
+__device__ __forceinline__ void block_vmax(double speed, DualSlot* slot) {
+  __shared__ double red[kBlock / kWave];
+  const double w = wave_max(speed);
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int q = 1; q < kBlock / kWave; ++q) m = fmax(m, red[q]);
+    if (m > 0.0) {
+      const unsigned long long b = double_to_bits(m);
+      if (__hip_atomic_load(&slot->vmax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b)
+        atomicMax(&slot->vmax_bits, b);
+    }
   }
 }
 
@@ -310,7 +319,7 @@ __global__ __launch_bounds__(kBlock) void dual_pressure_kernel(
     speed = sqrt(v2);
     if (bad) atomicOr(flags, kFlagNonfinite);
   }
-  wave_vmax(speed, &clk[sk + 1]);
+  block_vmax(speed, &clk[sk + 1]);
 }
 
 // ------------------------------------------------------------------ continuity substep
@@ -449,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void dual_move_kernel(
     }
     if (f) atomicOr(flags, f);
   }
-  wave_vmax(v[4], &clk_next[0]);
+  block_vmax(v[4], &clk_next[0]);
   const int slot = wave_claim_slot(lead, lin, counts);
   if (lead) slot_out[i] = slot;
   if (partials) {
@@ -467,7 +476,7 @@ __global__ __launch_bounds__(kBlock) void dual_start_kernel(int n, int dim, cons
   double v2 = 0.0;
   if (i < n)
     for (int d = 0; d < dim; ++d) v2 += (double)vel[(size_t)d * n + i] * (double)vel[(size_t)d * n + i];
-  wave_vmax(sqrt(v2), &clk[0]);
+  block_vmax(sqrt(v2), &clk[0]);
 }
 
 // ------------------------------------------------------------------ launchers
