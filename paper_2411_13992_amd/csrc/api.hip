@@ -580,16 +580,16 @@ int32_t run_steps_t(const sph_params* p, sph_particles* parts, int32_t* cs_calle
 // ---------------------------------------------------------------- dual-criteria steps
 // nsteps advection steps of the dual-criteria scheme (dual.hip).  Per step:
 // density summation, prologue sweep, K pressure + continuity substep
-// sweeps, move, and the cell build (scan, scatter, rank + gather).  The
+// sweeps, move, and the one-launch cell build (densities moved too).  The
 // substeps reuse workspace regions the kick-drift-kick run and the adjoint
 // use for other things: the correction buffer holds the displacement
 // accumulator, the adjoint buffers the viscous acceleration, the second
 // velocity and density buffers and both density-rate buffers.  Diagnostics
 // partials alternate between the two partials buffers and are folded by the
-// next step's scan (the last step's by an extra fold).
+// step's own cell build.
 template <typename T>
-int32_t dual_steps_t(const sph_params* p, const DualCoeffs& q, sph_particles* parts, int32_t* cs,
-                     int64_t nsteps, char* ws, double* diag, double* record,
+int32_t dual_steps_t(const sph_params* p, const DualCoeffs& q, sph_particles* parts,
+                     int32_t* cs_caller, int64_t nsteps, char* ws, double* diag, double* record,
                      hipStream_t stream) {
   const bool var = is_var(p);
   const Sizes sz = sizes_of(p, var);
@@ -603,10 +603,17 @@ int32_t dual_steps_t(const sph_params* p, const DualCoeffs& q, sph_particles* pa
   PArrays<T> stg = staging_of<T>(ws, w, var);
   const CellBuf cb = cellbuf_of(ws, w.cellbuf, sz.ncells);
   int* counts = cb.counts;
-  int* slot = (int*)(ws + w.slot);
-  const SortTmp st{(int*)(ws + w.tmp), (int*)(ws + w.tmp_id), (int2*)(ws + w.tmp_range)};
-  int* perm = (int*)(ws + w.perm);
   const size_t n = (size_t)sz.n;
+  // the two cell_start buffers, as in run_steps_t: step s reads csbuf[cur]
+  // and its cell build writes csbuf[cur ^ 1]; an odd number of steps starts
+  // from the workspace copy, so the last step writes the caller's buffer
+  const size_t csb = sizeof(int) * ((size_t)sz.ncells + 1);
+  int* csbuf[2] = {cs_caller, (int*)(ws + w.cs2)};
+  int cur_cs = 0;
+  if (nsteps & 1) {
+    if (copy_d2d(csbuf[1], cs_caller, csb, stream) != hipSuccess) return SPH_E_HIP;
+    cur_cs = 1;
+  }
   T* delta = (T*)(ws + w.dr);
   T* visc = (T*)(ws + w.adj_r);
   T* vel_buf[2] = {a.vel, (T*)(ws + w.adj_v)};
@@ -618,11 +625,20 @@ int32_t dual_steps_t(const sph_params* p, const DualCoeffs& q, sph_particles* pa
               (long)(2 * sizeof(DualSlot) * (kMaxDualSubsteps + 1) / sizeof(int)), 0);
   launch_fill(stream, counts, cb.fill_ints, 0);
   launch_dual_start<T>(stream, sz.n, sz.dim, a.vel, clock[0]);
-  PArrays<T> src = stg;
-  src.acc = nullptr;
+  // the cell build moves the densities too (the run's result carries the
+  // continuity equation's); the one-launch rebuild of the kick-drift-kick runs
   PArrays<T> dst = a;
   dst.acc = nullptr;
+  RebuildArgs rb{};
+  rb.ncells = sz.ncells;
+  rb.tile_cells = rebuild_tile_cells(sz.dim, p->ncell, (long)n, var);
+  rb.tiles_per_row = (p->ncell[0] + rb.tile_cells - 1) / rb.tile_cells;
+  rb.ntiles = rebuild_tiles(sz.dim, p->ncell, (long)n, var);
+  rb.st = cb.scan;
+  rb.perm = nullptr;
+  rb.flags = flags;
   for (int64_t s = 0; s < nsteps; ++s) {
+    int* cs = csbuf[cur_cs];
     double* cur = diag ? part[s & 1] : nullptr;
     DualSlot* clk = clock[s & 1];
     DualSlot* nxt = clock[(s + 1) & 1];
@@ -635,13 +651,15 @@ int32_t dual_steps_t(const sph_params* p, const DualCoeffs& q, sph_particles* pa
       launch_dual_continuity<T>(l, g, k, q, sk, a, cs, vel_buf[b ^ 1], rho_buf[b], drho_buf[b],
                                 rho_buf[b ^ 1], drho_buf[b ^ 1], clk, flags);
     }
-    launch_dual_move<T>(l, g, k, q, a, delta, stg, counts, slot, clk, nxt, cur,
+    launch_dual_move<T>(l, g, k, q, a, delta, stg, nullptr, nullptr, clk, nxt, cur,
                         record ? record + 3 * s : nullptr, flags);
-    DiagFold fold{};
-    if (diag) fold = DiagFold{cur, sz.nblk * kWavesPerBlock, diag + (size_t)SPH_NDIAG * s};
-    launch_scan(stream, sz.ncells, counts, cb.scan, (unsigned)s, cs, flags, fold);
-    launch_scatter(stream, sz.n, stg.cell, stg.id, slot, cs, st);
-    launch_rank_gather<T>(l, sz.n, st, src, dst, perm);
+    rb.fold = diag ? DiagFold{cur, sz.nblk * kWavesPerBlock, diag + (size_t)SPH_NDIAG * s}
+                   : DiagFold{};
+    rb.cs_old = csbuf[cur_cs];
+    rb.cs_new = csbuf[cur_cs ^ 1];
+    rb.epoch = (unsigned)s;
+    launch_rebuild<T>(l, g, rb, stg, dst);
+    cur_cs ^= 1;
   }
   return hip_status();
 }

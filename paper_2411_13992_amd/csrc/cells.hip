@@ -309,8 +309,8 @@ void launch_rank_gather(const Launch& l, int n, SortTmp tmp, const PArrays<T>& s
 // new cells, counts the tile's particles per cell in LDS, gets the number of
 // particles in all earlier tiles by a decoupled look-back over the tiles'
 // totals (the same scheme as scan_lookback_kernel), ranks each particle by id
-// among its cell's particles and writes them, its cells' starts and the
-// permutation.  The order is a function of (cell, id) only.  A tile with more
+// among its cell's particles and writes them (their densities too when dst.rho
+// is given), its cells' starts and the permutation.  The order is a function of (cell, id) only.  A tile with more
 // than kRebuildCap particles ranks them from global memory instead (slow,
 // exact).  Extra blocks past the tiles fold diagnostics partials, as the
 // scan's do.
@@ -458,7 +458,7 @@ __global__ __launch_bounds__(kRebuildBlock, (LAT || D == 3) ? 4 : 8) void rebuil
   const bool early = D == 2 && LAT && total <= U * NB;
   constexpr int UE = D == 2 && LAT ? U : 1;      // early-path registers
   int mslot[U], cq_keep[UE], iq_keep[UE], qq_keep[UE];
-  T mo[UE][D], mv[UE][D], mms[UE], mhs[UE];
+  T mo[UE][D], mv[UE][D], mms[UE], mhs[UE], mrs[UE];
 #pragma unroll
   for (int u = 0; u < U; ++u) mslot[u] = -1;     // no candidates: no members
   const unsigned long long below = (1ull << lane) - 1ull;
@@ -520,6 +520,7 @@ __global__ __launch_bounds__(kRebuildBlock, (LAT || D == 3) ? 4 : 8) void rebuil
         }
         mms[u] = dst.mass ? stg.mass[j] : T(0);
         mhs[u] = dst.h ? stg.h[j] : T(0);
+        mrs[u] = dst.rho ? stg.rho[j] : T(0);
       }
       }
     }
@@ -634,6 +635,7 @@ __global__ __launch_bounds__(kRebuildBlock, (LAT || D == 3) ? 4 : 8) void rebuil
     }
     if (dst.mass) dst.mass[to] = stg.mass[j];
     if (dst.h) dst.h[to] = stg.h[j];
+    if (dst.rho) dst.rho[to] = stg.rho[j];
     if (a.perm) a.perm[to] = j;
   };
   if (nmem <= kRebuildCap) {
@@ -681,6 +683,7 @@ __global__ __launch_bounds__(kRebuildBlock, (LAT || D == 3) ? 4 : 8) void rebuil
         }
         if (dst.mass) put(dst.mass + to, mms[u]);
         if (dst.h) put(dst.h + to, mhs[u]);
+        if (dst.rho) put(dst.rho + to, mrs[u]);
         if (a.perm) put(a.perm + to, qq_keep[u]);
       }
       return;
@@ -689,7 +692,7 @@ __global__ __launch_bounds__(kRebuildBlock, (LAT || D == 3) ? 4 : 8) void rebuil
     // two particles per thread at a time, every load issued before the stores
     for (int u0 = tid; u0 < nmem; u0 += 2 * NB) {
       int jj[2], cc[2], ii[2];
-      T oo[2][D], vv[2][D], ms[2], hs[2];
+      T oo[2][D], vv[2][D], ms[2], hs[2], rs[2];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int uu = min(u0 + u * NB, nmem - 1);
@@ -707,6 +710,7 @@ __global__ __launch_bounds__(kRebuildBlock, (LAT || D == 3) ? 4 : 8) void rebuil
         }
         ms[u] = dst.mass ? stg.mass[j] : T(0);
         hs[u] = dst.h ? stg.h[j] : T(0);
+        rs[u] = dst.rho ? stg.rho[j] : T(0);
       }
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
@@ -721,6 +725,7 @@ __global__ __launch_bounds__(kRebuildBlock, (LAT || D == 3) ? 4 : 8) void rebuil
         }
         if (dst.mass) put(dst.mass + to, ms[u]);
         if (dst.h) put(dst.h + to, hs[u]);
+        if (dst.rho) put(dst.rho + to, rs[u]);
         if (a.perm) put(a.perm + to, jj[u]);
       }
     }

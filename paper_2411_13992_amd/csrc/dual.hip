@@ -459,8 +459,10 @@ __global__ __launch_bounds__(kBlock) void dual_move_kernel(
     if (f) atomicOr(flags, f);
   }
   block_vmax(v[4], &clk_next[0]);
-  const int slot = wave_claim_slot(lead, lin, counts);
-  if (lead) slot_out[i] = slot;
+  if (counts) {
+    const int slot = wave_claim_slot(lead, lin, counts);
+    if (lead) slot_out[i] = slot;
+  }
   if (partials) {
     const int cols[5] = {0, 1, 2, 3, 4};
     wave_partials<5>(partials, cols, v, 1u << 4);
